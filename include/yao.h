@@ -1,0 +1,184 @@
+/*
+ * yao.h -- C ABI of the MI355X (gfx950) state-vector library.
+ *
+ * The operations follow the problem statement of Yao (arXiv:1912.10877):
+ *   - registers and batched registers: Sec. "Quantum Registers", "Batched Quantum Registers";
+ *   - gate instructions instruct!(reg, G, locs, ctrl_locs, ctrl_configs[, theta]):
+ *     Sec. "Instructions on Quantum Registers";
+ *   - circuits as chains of put/control blocks applied in order: Sec. "Representing
+ *     Quantum Circuits";
+ *   - expect(H, reg) of a sum of Pauli strings: Sec. "Matrix Representation" (Listing
+ *     "Heisenberg Hamiltonian") and Sec. "Forward Mode";
+ *   - expect'(H, reg => circuit): reverse mode with uncomputation, eqs. apply-back and
+ *     outer-product of Sec. "Reverse Mode".
+ *
+ * Conventions shared by every call:
+ *   - Qubits are 0-based; qubit q is bit q of the amplitude index (the paper's
+ *     little-endian readout, 1-based qubits).
+ *   - A state of n qubits and batch B is 2^n * B complex numbers, element (i, b) at
+ *     offset i*B + b (batch innermost), re/im interleaved: complex64 = 2 x float,
+ *     complex128 = 2 x double.
+ *   - A k-qubit matrix on locs l_0..l_{k-1} is 2^k x 2^k complex128, row-major,
+ *     re/im interleaved (2 * 4^k doubles); locs[j] is bit j of its row/column index.
+ *   - A control (c, v) passes when bit c of the amplitude index equals v (v = 0 is
+ *     the paper's "inverse control"). ctrl_vals == NULL means all ones.
+ *   - Every call returns 0 on success or a negative yao_status. Validation happens on the
+ *     host before any launch; a call that fails validation leaves every state unchanged.
+ *     yao_last_error() returns the message of the last failure in this thread.
+ *   - Device work goes to the stream set with yao_set_stream (default: the null stream)
+ *     and is asynchronous, except for calls that return host values (yao_expect,
+ *     yao_backward, yao_batch_run, yao_state_download), which synchronise that stream.
+ *   - Host arrays passed in are copied during the call; the caller keeps ownership.
+ *     Output arrays are caller-allocated host memory.
+ *   - The library targets gfx950 only. Calls on a machine without such a device fail
+ *     with YAO_ENODEV.
+ */
+#ifndef YAO_C_ABI_H_
+#define YAO_C_ABI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct yao_state yao_state;
+typedef struct yao_circuit yao_circuit;
+typedef struct yao_pauli_sum yao_pauli_sum;
+
+enum yao_status {
+    YAO_OK = 0,
+    YAO_EINVAL = -1,   /* invalid argument (message says which) */
+    YAO_ENOMEM = -2,   /* device allocation failed */
+    YAO_EHIP = -3,     /* HIP runtime error */
+    YAO_EDRIFT = -4,   /* reversible uncompute drifted past the bound with fallback disabled */
+    YAO_ENODEV = -5    /* no gfx950 device */
+};
+
+enum yao_dtype { YAO_C64 = 0, YAO_C128 = 1 };
+
+/* Gate kinds (App. "Builtin blocks"). Rotations are R_G(theta) = exp(-i theta G / 2) with G
+ * Hermitian and reflexive (Sec. "Forward Mode"); YAO_ROT takes G as a dense 2^k x 2^k
+ * matrix. YAO_SHIFT is diag(1, e^{i theta}) (Listing "inspecting gates"). YAO_DENSE is an
+ * arbitrary unitary (matblock). */
+enum yao_gate {
+    YAO_X = 0, YAO_Y = 1, YAO_Z = 2, YAO_H = 3, YAO_S = 4, YAO_SDAG = 5, YAO_T = 6, YAO_TDAG = 7,
+    YAO_RX = 8, YAO_RY = 9, YAO_RZ = 10, YAO_SHIFT = 11, YAO_ROT = 12, YAO_DENSE = 13
+};
+
+/* Backward strategies. REVERSIBLE uncomputes the state with inverse gates (constant memory
+ * in depth, Sec. "Reverse Mode"). CHECKPOINT keeps forward states and restarts each
+ * backward step from them (memory grows with depth). AUTO uncomputes and falls back to the
+ * stored checkpoint wherever the uncomputed state drifts past the bound. */
+enum yao_grad_mode { YAO_GRAD_REVERSIBLE = 0, YAO_GRAD_CHECKPOINT = 1, YAO_GRAD_AUTO = 2 };
+
+/* Execution options (process-wide; set before the calls they should affect).
+ *   plain            1: one kernel launch per gate (the per-gate form); 0: fused tile passes.
+ *   tile_qubits      qubits per fused tile (0 = chosen by the library or the autotuner).
+ *   fuse_width       widest host-fused dense block, 1..5 (1 = no dense fusion).
+ *   checkpoint_every passes between stored states in CHECKPOINT / AUTO mode (0 = sqrt rule).
+ *   drift_tol        max |psi_uncomputed - psi_stored| accepted before falling back
+ *                    (0 = 1e-5 for complex64 states, 1e-10 for complex128).
+ *   mfma             1: dense blocks of 4 or 5 qubits on complex64 states run on FP32
+ *                    matrix cores; 0: on the vector units. */
+typedef struct {
+    int plain;
+    int tile_qubits;
+    int fuse_width;
+    int checkpoint_every;
+    double drift_tol;
+    int mfma;
+} yao_options;
+
+/* Library ------------------------------------------------------------------------------ */
+
+/* Select the current HIP device, check that it is gfx950, reset options to defaults. */
+int yao_init(void);
+const char* yao_last_error(void);
+/* Bind the stream (a hipStream_t, or NULL for the null stream) that later calls use. */
+int yao_set_stream(void* hip_stream);
+int yao_synchronize(void);
+int yao_set_options(const yao_options* opt);
+int yao_get_options(yao_options* opt);
+
+/* States (a1) --------------------------------------------------------------------------- */
+
+/* Allocate a state of n qubits (1 <= n <= 34) and batch >= 1, set to |0...0> in every slot
+ * (the paper's zero_state(n; nbatch)). The library owns the memory. */
+int yao_state_create(int n, int batch, enum yao_dtype dt, yao_state** out);
+/* Wrap caller-owned device memory of 2^n * batch elements (e.g. a torch tensor); the
+ * library never frees it. The pointer must stay valid while the state is used. */
+int yao_state_wrap(void* dev_ptr, int n, int batch, enum yao_dtype dt, yao_state** out);
+int yao_state_destroy(yao_state* s);
+/* |0...0> in every batch slot. */
+int yao_state_reset(yao_state* s);
+/* Copy a host state in the layout above; bytes must equal the state's size. */
+int yao_state_upload(yao_state* s, const void* host, size_t bytes);
+int yao_state_download(const yao_state* s, void* host, size_t bytes);
+/* Device pointer, qubit count, batch and dtype of a state. */
+int yao_state_info(const yao_state* s, void** dev_ptr, int* n, int* batch, int* dtype);
+
+/* Gate instructions (a2, a3, a4) --------------------------------------------------------- */
+
+/* Apply a k-qubit matrix U (1 <= k <= 5) on locs, with nctrl controls (instruct! with a
+ * general matrix). Errors: YAO_EINVAL for a loc or control out of range, repeated qubits,
+ * a control on a target, k out of range. U is rounded once to the state's precision. */
+int yao_apply(yao_state* s, const double* U, int k, const int* locs, int nctrl, const int* ctrls,
+              const int* ctrl_vals);
+/* Apply a named gate; theta is used by the parametric kinds, G by YAO_ROT (generator) and
+ * YAO_DENSE (matrix), k is the number of locs (1 for every kind but YAO_ROT/YAO_DENSE). */
+int yao_apply_gate(yao_state* s, enum yao_gate g, double theta, const double* G, const int* locs, int k,
+                   int nctrl, const int* ctrls, const int* ctrl_vals);
+
+/* Observables (a5, a6) --------------------------------------------------------------- */
+
+/* H = sum_t coef[t] P_t on n qubits; P_t has X on the bits set only in xmask[t], Z on the
+ * bits set only in zmask[t], Y on the bits set in both. */
+int yao_pauli_sum_create(int n, int nterms, const double* coef, const uint64_t* xmask, const uint64_t* zmask,
+                         yao_pauli_sum** out);
+int yao_pauli_sum_destroy(yao_pauli_sum* h);
+/* energy[b] = Re <psi_b|H|psi_b> for every batch slot, accumulated in FP64. Synchronises. */
+int yao_expect(const yao_state* s, const yao_pauli_sum* h, double* energy);
+/* out = H psi (the adjoint seed of the reverse mode) and, if energy != NULL,
+ * energy[b] = Re <psi_b|H psi_b> from the same pass. out must match s in n, batch, dtype. */
+int yao_hpsi(const yao_state* s, const yao_pauli_sum* h, yao_state* out, double* energy);
+
+/* Circuits ---------------------------------------------------------------------------- */
+
+int yao_circuit_create(int n, yao_circuit** out);
+int yao_circuit_destroy(yao_circuit* c);
+/* Append a gate. param_index >= 0 takes the angle from params[param_index] at run time
+ * (several gates may share one); -1 uses theta_fixed. G as for yao_apply_gate. */
+int yao_circuit_push(yao_circuit* c, enum yao_gate g, int param_index, double theta_fixed, const double* G,
+                     const int* locs, int k, int nctrl, const int* ctrls, const int* ctrl_vals);
+/* 1 + the largest param_index pushed. */
+int yao_circuit_nparams(const yao_circuit* c, int* out);
+
+/* Forward and backward (a7, a8) ------------------------------------------------------- */
+
+/* psi <- circuit(params) psi (apply!(reg, circuit)). */
+int yao_forward(yao_state* s, const yao_circuit* c, const double* params);
+/* expect'(H, reg => circuit): runs the circuit on s (which holds the input and ends
+ * holding the output state), energy[b] = <psi_b|H|psi_b> and the gradient of every
+ * parameter: grad[b * nparams + p] if reduce_batch == 0, else grad[p] summed over the
+ * batch (the paper's batched gradient). If drift != NULL it receives
+ * max |psi_0 uncomputed - psi_0| (0 in CHECKPOINT mode). Synchronises. */
+int yao_backward(yao_state* s, const yao_circuit* c, const double* params, const yao_pauli_sum* h,
+                 enum yao_grad_mode mode, int reduce_batch, double* energy, double* grad, double* drift);
+
+/* Batches of independent circuits (a9) --------------------------------------------------- */
+
+/* Energy and gradient of ncirc independent circuits, each on its own single-slot state
+ * (n may differ between circuits) starting from |0...0>; energy[c] and grad[c] (length
+ * nparams of circuit c) are host arrays. All circuits run in one persistent launch
+ * replayed from a HIP graph; states[c] ends holding circuit c's output. Synchronises. */
+int yao_batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* circs,
+                  const double* const* params, const yao_pauli_sum* const* h, double* energy,
+                  double* const* grad);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* YAO_C_ABI_H_ */

@@ -1,0 +1,27 @@
+// Drivers behind the C ABI: per-gate and fused execution of circuits, the reverse sweep and
+// batches of circuits. Arguments are validated by the caller.
+#pragma once
+
+#include "runtime.h"
+
+namespace yao {
+
+int apply_one(yao_state* s, const GateRec& g, double theta);
+int forward(yao_state* s, const yao_circuit* c, const double* params);
+int backward(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h, int mode, bool reduce_batch,
+             double* energy, double* grad, double* drift);
+int batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* circs, const double* const* params,
+              yao_pauli_sum* const* h, double* energy, double* const* grad);
+void drop_plans(const yao_circuit* c);
+
+// Per-gate form.
+int forward_plain(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params);
+int backward_plain(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h, bool reduce_batch,
+                   double* energy, double* grad, double* drift);
+
+inline double gate_theta(const GateRec& g, const double* params)
+{
+    return g.param >= 0 ? params[g.param] : g.theta;
+}
+
+}  // namespace yao

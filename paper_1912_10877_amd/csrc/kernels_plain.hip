@@ -1,0 +1,672 @@
+// Per-gate ("plain form") kernels of the gfx950 state-vector library, the Pauli-sum
+// expectation and H psi kernels, and small utilities.
+//
+// Every kernel walks the state with the batch innermost, so consecutive lanes touch
+// consecutive addresses: for a single state (B = 1) the lanes run along the low bits of the
+// pair index, for a batch they run along the batch slots of one amplitude row.
+#include <cstdarg>
+#include <cstdio>
+
+#include "runtime.h"
+
+namespace yao {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename R> __device__ __forceinline__ vec2_t<R> mk(R a, R b)
+{
+    vec2_t<R> v;
+    v.x = a;
+    v.y = b;
+    return v;
+}
+
+// -------------------------------------------------------------------------------- state init
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_fill_basis(vec2_t<R>* __restrict__ psi, uint64_t elems, int B)
+{
+    uint64_t e = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= elems) return;
+    psi[e] = mk<R>(e < (uint64_t)B ? R(1) : R(0), R(0));
+}
+
+// -------------------------------------------------------------------------------- 1-qubit gate
+// Work item w = j * 2^logBp + b: pair row j (2^(n-1) of them) and batch slot b (padded to a
+// power of two, slots >= B idle). The pair is (i0, i0 + 2^q) with bit q of i0 clear.
+template <typename R, int CLS>
+__global__ __launch_bounds__(kThreads) void k_gate1(vec2_t<R>* __restrict__ psi, uint64_t nwork, int q, int logBp,
+                                                    int B, uint64_t cmask, uint64_t cval, M2<R> m)
+{
+    using V = vec2_t<R>;
+    uint64_t w = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (w >= nwork) return;
+    int b = (int)(w & ((uint64_t(1) << logBp) - 1));
+    if (b >= B) return;
+    uint64_t j = w >> logBp;
+    uint64_t i0 = insert_zero(j, q);
+    if ((i0 & cmask) != cval) return;
+    uint64_t o0 = i0 * (uint64_t)B + b;
+    uint64_t o1 = o0 + ((uint64_t)B << q);
+    if (CLS == MC_DIAG1) {
+        V c = psi[o1];
+        psi[o1] = mk<R>(m.re[3] * c.x - m.im[3] * c.y, m.re[3] * c.y + m.im[3] * c.x);
+        return;
+    }
+    V a = psi[o0], c = psi[o1];
+    V r0, r1;
+    if (CLS == MC_DIAG) {
+        r0 = mk<R>(m.re[0] * a.x - m.im[0] * a.y, m.re[0] * a.y + m.im[0] * a.x);
+        r1 = mk<R>(m.re[3] * c.x - m.im[3] * c.y, m.re[3] * c.y + m.im[3] * c.x);
+    } else if (CLS == MC_ANTI) {
+        r0 = mk<R>(m.re[1] * c.x - m.im[1] * c.y, m.re[1] * c.y + m.im[1] * c.x);
+        r1 = mk<R>(m.re[2] * a.x - m.im[2] * a.y, m.re[2] * a.y + m.im[2] * a.x);
+    } else {
+        R x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+        cmul_acc(x0, y0, m.re[0], m.im[0], a);
+        cmul_acc(x0, y0, m.re[1], m.im[1], c);
+        cmul_acc(x1, y1, m.re[2], m.im[2], a);
+        cmul_acc(x1, y1, m.re[3], m.im[3], c);
+        r0 = mk<R>(x0, y0);
+        r1 = mk<R>(x1, y1);
+    }
+    psi[o0] = r0;
+    psi[o1] = r1;
+}
+
+// -------------------------------------------------------------------------------- k-qubit gate
+// Offsets of the 2^K members of a group relative to its base index, and the target bit
+// positions in ascending order (for inserting the zero bits).
+template <int K> struct GroupGeom {
+    uint64_t off[1 << K];
+    int sorted[K];
+};
+
+template <int K> __device__ __forceinline__ uint64_t group_base(uint64_t j, const GroupGeom<K>& g)
+{
+#pragma unroll
+    for (int t = 0; t < K; ++t) j = insert_zero(j, g.sorted[t]);
+    return j;
+}
+
+template <typename R, int K>
+__global__ __launch_bounds__(kThreads) void k_gatek(vec2_t<R>* __restrict__ psi, uint64_t nwork, int logBp, int B,
+                                                    GroupGeom<K> gg, uint64_t cmask, uint64_t cval,
+                                                    const R* __restrict__ Ure, const R* __restrict__ Uim)
+{
+    using V = vec2_t<R>;
+    constexpr int D = 1 << K;
+    uint64_t w = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (w >= nwork) return;
+    int b = (int)(w & ((uint64_t(1) << logBp) - 1));
+    if (b >= B) return;
+    uint64_t base = group_base<K>(w >> logBp, gg);
+    if ((base & cmask) != cval) return;
+    V a[D];
+#pragma unroll
+    for (int s = 0; s < D; ++s) a[s] = psi[(base + gg.off[s]) * (uint64_t)B + b];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        R x = 0, y = 0;
+#pragma unroll
+        for (int s = 0; s < D; ++s) cmul_acc(x, y, Ure[r * D + s], Uim[r * D + s], a[s]);
+        psi[(base + gg.off[r]) * (uint64_t)B + b] = mk<R>(x, y);
+    }
+}
+
+// -------------------------------------------------------------------------------- reductions
+// Block reduction of one double per thread, grouped by batch slot (tid & (Bc-1)).
+__device__ __forceinline__ double block_sum_by_slot(double v, int logBc, double* red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kThreads / 2; s >= (1 << logBc); s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    return red[threadIdx.x];
+}
+
+struct PGroup {
+    uint64_t x;
+    int t0, t1;
+};
+struct PTerm {
+    double c;
+    uint64_t z;
+    int ny;
+    int pad;
+};
+
+// Value of Re(i^ny * w) for w = wr + i wi.
+__device__ __forceinline__ double re_iny(int ny, double wr, double wi)
+{
+    switch (ny & 3) {
+    case 0: return wr;
+    case 1: return -wi;
+    case 2: return -wr;
+    default: return wi;
+    }
+}
+
+// E_b = sum_i sum_t c_t Re( conj(psi_{i ^ x_t}) i^{ny_t} (-1)^{|i & z_t|} psi_i ), using
+// P|i> = i^{ny} (-1)^{|i & z|} |i ^ x> with ny = |x & z|. Rows are amplitude indices.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_expect(const vec2_t<R>* __restrict__ psi, uint64_t rows, int B,
+                                                     int logBc, const PGroup* __restrict__ groups, int ngroups,
+                                                     const PTerm* __restrict__ terms, double* __restrict__ partial)
+{
+    __shared__ double red[kThreads];
+    const int bb = threadIdx.x & ((1 << logBc) - 1);
+    const int b = blockIdx.y * (1 << logBc) + bb;
+    const int rpb = kThreads >> logBc;
+    double acc = 0;
+    if (b < B) {
+        for (uint64_t i = (uint64_t)blockIdx.x * rpb + (threadIdx.x >> logBc); i < rows; i += (uint64_t)gridDim.x * rpb) {
+            vec2_t<R> a = psi[i * B + b];
+            for (int g = 0; g < ngroups; ++g) {
+                uint64_t x = groups[g].x;
+                vec2_t<R> p = x ? psi[(i ^ x) * B + b] : a;
+                double wr = (double)p.x * a.x + (double)p.y * a.y;
+                double wi = (double)p.x * a.y - (double)p.y * a.x;
+                for (int t = groups[g].t0; t < groups[g].t1; ++t) {
+                    double v = re_iny(terms[t].ny, wr, wi);
+                    acc += (__popcll(i & terms[t].z) & 1) ? -terms[t].c * v : terms[t].c * v;
+                }
+            }
+        }
+    }
+    double s = block_sum_by_slot(acc, logBc, red);
+    if ((int)threadIdx.x < (1 << logBc) && b < B) partial[(uint64_t)b * gridDim.x + blockIdx.x] = s;
+}
+
+// out_j = sum_t c_t i^{ny_t} (-1)^{|(j ^ x_t) & z_t|} psi_{j ^ x_t}, plus E from the same pass.
+template <typename R, typename RO>
+__global__ __launch_bounds__(kThreads) void k_hpsi(const vec2_t<R>* __restrict__ psi, vec2_t<RO>* __restrict__ out,
+                                                   uint64_t rows, int B, int logBc, const PGroup* __restrict__ groups,
+                                                   int ngroups, const PTerm* __restrict__ terms,
+                                                   double* __restrict__ partial)
+{
+    __shared__ double red[kThreads];
+    const int bb = threadIdx.x & ((1 << logBc) - 1);
+    const int b = blockIdx.y * (1 << logBc) + bb;
+    const int rpb = kThreads >> logBc;
+    double acc = 0;
+    if (b < B) {
+        for (uint64_t j = (uint64_t)blockIdx.x * rpb + (threadIdx.x >> logBc); j < rows; j += (uint64_t)gridDim.x * rpb) {
+            double orr = 0, oi = 0;
+            for (int g = 0; g < ngroups; ++g) {
+                uint64_t x = groups[g].x;
+                uint64_t src = j ^ x;
+                vec2_t<R> p = psi[src * B + b];
+                double cr = 0, ci = 0;  // sum of c_t i^{ny} (-1)^{|src & z|}
+                for (int t = groups[g].t0; t < groups[g].t1; ++t) {
+                    double c = (__popcll(src & terms[t].z) & 1) ? -terms[t].c : terms[t].c;
+                    switch (terms[t].ny & 3) {
+                    case 0: cr += c; break;
+                    case 1: ci += c; break;
+                    case 2: cr -= c; break;
+                    default: ci -= c; break;
+                    }
+                }
+                orr += cr * p.x - ci * p.y;
+                oi += cr * p.y + ci * p.x;
+            }
+            vec2_t<R> a = psi[j * B + b];
+            acc += (double)a.x * orr + (double)a.y * oi;
+            vec2_t<RO> o;
+            o.x = (RO)orr;
+            o.y = (RO)oi;
+            out[j * B + b] = o;
+        }
+    }
+    double s = block_sum_by_slot(acc, logBc, red);
+    if ((int)threadIdx.x < (1 << logBc) && b < B) partial[(uint64_t)b * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void k_row_sums(const double* __restrict__ partial, int rows, int nblk, double* __restrict__ sums)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    double s = 0;
+    for (int j = 0; j < nblk; ++j) s += partial[(uint64_t)r * nblk + j];
+    sums[r] = s;
+}
+
+template <typename RA, typename RB>
+__global__ __launch_bounds__(kThreads) void k_convert(const vec2_t<RA>* __restrict__ a, vec2_t<RB>* __restrict__ b,
+                                                      uint64_t elems)
+{
+    for (uint64_t e = (uint64_t)blockIdx.x * kThreads + threadIdx.x; e < elems; e += (uint64_t)gridDim.x * kThreads) {
+        vec2_t<RA> v = a[e];
+        vec2_t<RB> o;
+        o.x = (RB)v.x;
+        o.y = (RB)v.y;
+        b[e] = o;
+    }
+}
+
+template <typename RA, typename RB>
+__global__ __launch_bounds__(kThreads) void k_maxdiff(const vec2_t<RA>* __restrict__ a, const vec2_t<RB>* __restrict__ b,
+                                                      uint64_t elems, double* __restrict__ partial)
+{
+    __shared__ double red[kThreads];
+    double m = 0;
+    for (uint64_t e = (uint64_t)blockIdx.x * kThreads + threadIdx.x; e < elems; e += (uint64_t)gridDim.x * kThreads) {
+        vec2_t<RA> u = a[e];
+        vec2_t<RB> v = b[e];
+        double dr = (double)u.x - (double)v.x, di = (double)u.y - (double)v.y;
+        m = fmax(m, sqrt(dr * dr + di * di));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// -------------------------------------------------------------------------------- adjoint step
+// One gate of the reverse sweep (eq. apply-back): gradient partial 2 Re <lam|M|psi> over the
+// controlled subspace, then psi <- Ud psi (FP64) and lam <- Ud lam. Rows are pair rows.
+struct AdjMats1 {
+    double udr[4], udi[4], mr[4], mi[4];
+};
+
+template <typename RL, int K, bool GRAD>
+__global__ __launch_bounds__(kThreads) void k_adjoint(double2* __restrict__ psi, vec2_t<RL>* __restrict__ lam,
+                                                      uint64_t rows, int B, int logBc, GroupGeom<K> gg,
+                                                      uint64_t cmask, uint64_t cval, AdjMats1 m1,
+                                                      const double* __restrict__ mats, double* __restrict__ partial)
+{
+    constexpr int D = 1 << K;
+    constexpr int DD = D * D;
+    // K == 1: matrices by value; otherwise mats holds Ud re, Ud im, M re, M im (DD doubles each).
+    const double* Udr = K == 1 ? m1.udr : mats;
+    const double* Udi = K == 1 ? m1.udi : mats + DD;
+    const double* Mr = K == 1 ? m1.mr : mats + 2 * DD;
+    const double* Mi = K == 1 ? m1.mi : mats + 3 * DD;
+    __shared__ double red[kThreads];
+    const int bb = threadIdx.x & ((1 << logBc) - 1);
+    const int b = blockIdx.y * (1 << logBc) + bb;
+    const int rpb = kThreads >> logBc;
+    double acc = 0;
+    if (b < B) {
+        for (uint64_t j = (uint64_t)blockIdx.x * rpb + (threadIdx.x >> logBc); j < rows; j += (uint64_t)gridDim.x * rpb) {
+            uint64_t base = group_base<K>(j, gg);
+            if ((base & cmask) != cval) continue;
+            double2 p[D];
+            vec2_t<RL> l[D];
+#pragma unroll
+            for (int s = 0; s < D; ++s) {
+                uint64_t o = (base + gg.off[s]) * (uint64_t)B + b;
+                p[s] = psi[o];
+                l[s] = lam[o];
+            }
+            if (GRAD) {
+#pragma unroll
+                for (int r = 0; r < D; ++r) {
+                    double x = 0, y = 0;
+#pragma unroll
+                    for (int s = 0; s < D; ++s) cmul_acc(x, y, Mr[r * D + s], Mi[r * D + s], p[s]);
+                    acc += 2.0 * ((double)l[r].x * x + (double)l[r].y * y);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                double x = 0, y = 0, u = 0, v = 0;
+#pragma unroll
+                for (int s = 0; s < D; ++s) {
+                    cmul_acc(x, y, Udr[r * D + s], Udi[r * D + s], p[s]);
+                    cmul_acc(u, v, Udr[r * D + s], Udi[r * D + s], l[s]);
+                }
+                uint64_t o = (base + gg.off[r]) * (uint64_t)B + b;
+                psi[o] = make_double2(x, y);
+                vec2_t<RL> lo;
+                lo.x = (RL)u;
+                lo.y = (RL)v;
+                lam[o] = lo;
+            }
+        }
+    }
+    if (GRAD) {
+        double s = block_sum_by_slot(acc, logBc, red);
+        if ((int)threadIdx.x < (1 << logBc) && b < B) partial[(uint64_t)b * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+template <int K> GroupGeom<K> make_group_geom(const int* locs)
+{
+    GroupGeom<K> g;
+    for (int s = 0; s < (1 << K); ++s) {
+        uint64_t o = 0;
+        for (int j = 0; j < K; ++j)
+            if ((s >> j) & 1) o |= uint64_t(1) << locs[j];
+        g.off[s] = o;
+    }
+    int tmp[K];
+    for (int j = 0; j < K; ++j) tmp[j] = locs[j];
+    for (int a = 0; a < K; ++a)
+        for (int c = a + 1; c < K; ++c)
+            if (tmp[c] < tmp[a]) {
+                int t = tmp[a];
+                tmp[a] = tmp[c];
+                tmp[c] = t;
+            }
+    for (int j = 0; j < K; ++j) g.sorted[j] = tmp[j];
+    return g;
+}
+
+unsigned grid1(uint64_t work)
+{
+    return (unsigned)((work + kThreads - 1) / kThreads);
+}
+
+template <typename R>
+int gate_typed(void* data, int n, int B, const HostMat& U, const int* locs, CtrlSpec c, const void* dev_mat)
+{
+    using V = vec2_t<R>;
+    V* psi = (V*)data;
+    const int k = U.k;
+    const int logBp = ilog2_ceil((uint64_t)B);
+    const uint64_t nwork = (uint64_t(1) << (n - k)) << logBp;
+    hipStream_t st = stream();
+    if (k == 1) {
+        M2<R> m;
+        for (int t = 0; t < 4; ++t) {
+            m.re[t] = (R)U.re[t];
+            m.im[t] = (R)U.im[t];
+        }
+        switch (classify(U)) {
+        case MC_DIAG1: k_gate1<R, MC_DIAG1><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, locs[0], logBp, B, c.mask, c.val, m); break;
+        case MC_DIAG: k_gate1<R, MC_DIAG><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, locs[0], logBp, B, c.mask, c.val, m); break;
+        case MC_ANTI: k_gate1<R, MC_ANTI><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, locs[0], logBp, B, c.mask, c.val, m); break;
+        default: k_gate1<R, MC_DENSE><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, locs[0], logBp, B, c.mask, c.val, m); break;
+        }
+        YAO_HIP(hipGetLastError());
+        return 0;
+    }
+    // k >= 2: the matrix, rounded once to R (re block then im block), lives in device memory.
+    const size_t dd = size_t(1) << (2 * k);
+    const R* dm = (const R*)dev_mat;
+    if (!dm) {
+        std::vector<R> h(2 * dd);
+        for (size_t t = 0; t < dd; ++t) {
+            h[t] = (R)U.re[t];
+            h[dd + t] = (R)U.im[t];
+        }
+        dm = (const R*)ring_upload(h.data(), h.size() * sizeof(R));
+        if (!dm) return YAO_ENOMEM;
+    }
+    switch (k) {
+    case 2: k_gatek<R, 2><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, logBp, B, make_group_geom<2>(locs), c.mask, c.val, dm, dm + dd); break;
+    case 3: k_gatek<R, 3><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, logBp, B, make_group_geom<3>(locs), c.mask, c.val, dm, dm + dd); break;
+    case 4: k_gatek<R, 4><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, logBp, B, make_group_geom<4>(locs), c.mask, c.val, dm, dm + dd); break;
+    case 5: k_gatek<R, 5><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, logBp, B, make_group_geom<5>(locs), c.mask, c.val, dm, dm + dd); break;
+    default: return set_error(YAO_EINVAL, "k = %d not supported", k);
+    }
+    YAO_HIP(hipGetLastError());
+    return 0;
+}
+
+int reduce_grid_x(uint64_t rows, int logBc)
+{
+    uint64_t rpb = kThreads >> logBc;
+    uint64_t nb = (rows + rpb - 1) / rpb;
+    return (int)(nb < 1024 ? nb : 1024);
+}
+
+}  // namespace
+
+// =========================================================================================
+// Launchers
+// =========================================================================================
+
+int launch_fill_basis(void* data, int dtype, int n, int B)
+{
+    uint64_t elems = (uint64_t(1) << n) * (uint64_t)B;
+    if (dtype == YAO_C64)
+        k_fill_basis<float><<<grid1(elems), kThreads, 0, stream()>>>((float2*)data, elems, B);
+    else
+        k_fill_basis<double><<<grid1(elems), kThreads, 0, stream()>>>((double2*)data, elems, B);
+    YAO_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_reset(yao_state* s)
+{
+    return launch_fill_basis(s->data, s->dtype, s->n, s->batch);
+}
+
+int launch_gate(void* data, int dtype, int n, int B, const HostMat& U, const int* locs, CtrlSpec c, const void* dev_mat)
+{
+    return dtype == YAO_C64 ? gate_typed<float>(data, n, B, U, locs, c, dev_mat)
+                            : gate_typed<double>(data, n, B, U, locs, c, dev_mat);
+}
+
+int launch_row_sums(const double* partial, int rows, int nblk, double* sums)
+{
+    k_row_sums<<<(rows + 255) / 256, 256, 0, stream()>>>(partial, rows, nblk, sums);
+    YAO_HIP(hipGetLastError());
+    return 0;
+}
+
+int pauli_upload(yao_pauli_sum* h)
+{
+    if (h->d_groups) return 0;
+    std::vector<PGroup> groups;
+    std::vector<PTerm> terms;
+    std::vector<uint64_t> xs;
+    // Group the terms by X mask, keeping first-appearance order.
+    for (size_t t = 0; t < h->coef.size(); ++t) {
+        bool seen = false;
+        for (uint64_t x : xs) seen |= (x == h->x[t]);
+        if (!seen) xs.push_back(h->x[t]);
+    }
+    for (uint64_t x : xs) {
+        PGroup g;
+        g.x = x;
+        g.t0 = (int)terms.size();
+        for (size_t t = 0; t < h->coef.size(); ++t) {
+            if (h->x[t] != x) continue;
+            PTerm pt;
+            pt.c = h->coef[t];
+            pt.z = h->z[t];
+            pt.ny = __builtin_popcountll(h->x[t] & h->z[t]);
+            pt.pad = 0;
+            terms.push_back(pt);
+        }
+        g.t1 = (int)terms.size();
+        groups.push_back(g);
+    }
+    void *dg = nullptr, *dt = nullptr;
+    if (hipMalloc(&dg, sizeof(PGroup) * (groups.size() + 1)) != hipSuccess) return set_error(YAO_ENOMEM, "pauli tables");
+    if (hipMalloc(&dt, sizeof(PTerm) * (terms.size() + 1)) != hipSuccess) {
+        (void)hipFree(dg);
+        return set_error(YAO_ENOMEM, "pauli tables");
+    }
+    YAO_HIP(hipMemcpy(dg, groups.data(), sizeof(PGroup) * groups.size(), hipMemcpyHostToDevice));
+    YAO_HIP(hipMemcpy(dt, terms.data(), sizeof(PTerm) * terms.size(), hipMemcpyHostToDevice));
+    h->d_groups = dg;
+    h->d_terms = dt;
+    h->ngroups = (int)groups.size();
+    h->nterms_dev = (int)terms.size();
+    return 0;
+}
+
+static int finish_slot_sums(double* partial, int B, int nblk, double* energy_host)
+{
+    double* sums = (double*)workspace(WS_PARTIAL2, sizeof(double) * B);
+    if (!sums) return YAO_ENOMEM;
+    YAO_TRY(launch_row_sums(partial, B, nblk, sums));
+    double* hs = (double*)host_staging(sizeof(double) * B);
+    if (!hs) return YAO_ENOMEM;
+    YAO_HIP(hipMemcpyAsync(hs, sums, sizeof(double) * B, hipMemcpyDeviceToHost, stream()));
+    YAO_HIP(hipStreamSynchronize(stream()));
+    memcpy(energy_host, hs, sizeof(double) * B);
+    return 0;
+}
+
+int launch_expect(const void* data, int dtype, int n, int B, yao_pauli_sum* h, double* energy_host)
+{
+    YAO_TRY(pauli_upload(h));
+    BatchGeom bg = make_batch_geom(B);
+    uint64_t rows = uint64_t(1) << n;
+    int nbx = reduce_grid_x(rows, bg.logBc);
+    double* partial = (double*)workspace(WS_PARTIAL, sizeof(double) * (size_t)B * nbx);
+    if (!partial) return YAO_ENOMEM;
+    dim3 grid(nbx, bg.nchunks);
+    if (dtype == YAO_C64)
+        k_expect<float><<<grid, kThreads, 0, stream()>>>((const float2*)data, rows, B, bg.logBc, (const PGroup*)h->d_groups,
+                                                         h->ngroups, (const PTerm*)h->d_terms, partial);
+    else
+        k_expect<double><<<grid, kThreads, 0, stream()>>>((const double2*)data, rows, B, bg.logBc, (const PGroup*)h->d_groups,
+                                                          h->ngroups, (const PTerm*)h->d_terms, partial);
+    YAO_HIP(hipGetLastError());
+    return finish_slot_sums(partial, B, nbx, energy_host);
+}
+
+int launch_hpsi(const void* data, int dtype, void* out, int out_dtype, int n, int B, yao_pauli_sum* h,
+                double* energy_host)
+{
+    YAO_TRY(pauli_upload(h));
+    BatchGeom bg = make_batch_geom(B);
+    uint64_t rows = uint64_t(1) << n;
+    int nbx = reduce_grid_x(rows, bg.logBc);
+    double* partial = (double*)workspace(WS_PARTIAL, sizeof(double) * (size_t)B * nbx);
+    if (!partial) return YAO_ENOMEM;
+    dim3 grid(nbx, bg.nchunks);
+    const PGroup* G = (const PGroup*)h->d_groups;
+    const PTerm* T = (const PTerm*)h->d_terms;
+    hipStream_t st = stream();
+    if (dtype == YAO_C64 && out_dtype == YAO_C64)
+        k_hpsi<float, float><<<grid, kThreads, 0, st>>>((const float2*)data, (float2*)out, rows, B, bg.logBc, G, h->ngroups, T, partial);
+    else if (dtype == YAO_C64)
+        k_hpsi<float, double><<<grid, kThreads, 0, st>>>((const float2*)data, (double2*)out, rows, B, bg.logBc, G, h->ngroups, T, partial);
+    else if (out_dtype == YAO_C64)
+        k_hpsi<double, float><<<grid, kThreads, 0, st>>>((const double2*)data, (float2*)out, rows, B, bg.logBc, G, h->ngroups, T, partial);
+    else
+        k_hpsi<double, double><<<grid, kThreads, 0, st>>>((const double2*)data, (double2*)out, rows, B, bg.logBc, G, h->ngroups, T, partial);
+    YAO_HIP(hipGetLastError());
+    if (!energy_host) return 0;
+    return finish_slot_sums(partial, B, nbx, energy_host);
+}
+
+int launch_convert(const void* src, int src_dtype, void* dst, int dst_dtype, size_t elems)
+{
+    unsigned nb = (unsigned)std::min<uint64_t>((elems + kThreads - 1) / kThreads, 65536);
+    hipStream_t st = stream();
+    if (src_dtype == YAO_C64 && dst_dtype == YAO_C64)
+        k_convert<float, float><<<nb, kThreads, 0, st>>>((const float2*)src, (float2*)dst, elems);
+    else if (src_dtype == YAO_C64)
+        k_convert<float, double><<<nb, kThreads, 0, st>>>((const float2*)src, (double2*)dst, elems);
+    else if (dst_dtype == YAO_C64)
+        k_convert<double, float><<<nb, kThreads, 0, st>>>((const double2*)src, (float2*)dst, elems);
+    else
+        k_convert<double, double><<<nb, kThreads, 0, st>>>((const double2*)src, (double2*)dst, elems);
+    YAO_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_maxdiff(const void* a, int a_dtype, const void* b, int b_dtype, size_t elems, double* out)
+{
+    const unsigned nb = 512;
+    double* partial = (double*)workspace(WS_PARTIAL2, sizeof(double) * nb);
+    if (!partial) return YAO_ENOMEM;
+    hipStream_t st = stream();
+    if (a_dtype == YAO_C128 && b_dtype == YAO_C64)
+        k_maxdiff<double, float><<<nb, kThreads, 0, st>>>((const double2*)a, (const float2*)b, elems, partial);
+    else if (a_dtype == YAO_C128 && b_dtype == YAO_C128)
+        k_maxdiff<double, double><<<nb, kThreads, 0, st>>>((const double2*)a, (const double2*)b, elems, partial);
+    else if (a_dtype == YAO_C64 && b_dtype == YAO_C64)
+        k_maxdiff<float, float><<<nb, kThreads, 0, st>>>((const float2*)a, (const float2*)b, elems, partial);
+    else
+        k_maxdiff<float, double><<<nb, kThreads, 0, st>>>((const float2*)a, (const double2*)b, elems, partial);
+    YAO_HIP(hipGetLastError());
+    double* hs = (double*)host_staging(sizeof(double) * nb);
+    if (!hs) return YAO_ENOMEM;
+    YAO_HIP(hipMemcpyAsync(hs, partial, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    YAO_HIP(hipStreamSynchronize(st));
+    double m = 0;
+    for (unsigned t = 0; t < nb; ++t) m = hs[t] > m ? hs[t] : m;
+    *out = m;
+    return 0;
+}
+
+int adjoint_nblk(int n, int k, int B)
+{
+    BatchGeom bg = make_batch_geom(B);
+    return reduce_grid_x(uint64_t(1) << (n - k), bg.logBc);
+}
+
+template <typename RL, int K>
+static int adjoint_k(double* psi, void* lam, int n, int B, const int* locs, CtrlSpec c, const AdjMats1& m1,
+                     const double* dm, bool grad, double* partial)
+{
+    BatchGeom bg = make_batch_geom(B);
+    uint64_t rows = uint64_t(1) << (n - K);
+    int nbx = reduce_grid_x(rows, bg.logBc);
+    dim3 grid(nbx, bg.nchunks);
+    GroupGeom<K> gg = make_group_geom<K>(locs);
+    if (grad)
+        k_adjoint<RL, K, true><<<grid, kThreads, 0, stream()>>>((double2*)psi, (vec2_t<RL>*)lam, rows, B, bg.logBc, gg,
+                                                                 c.mask, c.val, m1, dm, partial);
+    else
+        k_adjoint<RL, K, false><<<grid, kThreads, 0, stream()>>>((double2*)psi, (vec2_t<RL>*)lam, rows, B, bg.logBc, gg,
+                                                                  c.mask, c.val, m1, dm, partial);
+    YAO_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_adjoint_step(double* psi, void* lam, int lam_dtype, int n, int B, const HostMat& Ud, const HostMat* M,
+                        const int* locs, CtrlSpec c, const double* dev_mats, double* partial, int* nblk)
+{
+    const int k = Ud.k;
+    AdjMats1 m1;
+    memset(&m1, 0, sizeof(m1));
+    if (k == 1) {
+        for (int t = 0; t < 4; ++t) {
+            m1.udr[t] = Ud.re[t];
+            m1.udi[t] = Ud.im[t];
+            if (M) {
+                m1.mr[t] = M->re[t];
+                m1.mi[t] = M->im[t];
+            }
+        }
+    } else if (!dev_mats) {
+        const size_t dd = size_t(1) << (2 * k);
+        std::vector<double> h(4 * dd, 0.0);
+        for (size_t t = 0; t < dd; ++t) {
+            h[t] = Ud.re[t];
+            h[dd + t] = Ud.im[t];
+            if (M) {
+                h[2 * dd + t] = M->re[t];
+                h[3 * dd + t] = M->im[t];
+            }
+        }
+        dev_mats = (const double*)ring_upload(h.data(), h.size() * sizeof(double));
+        if (!dev_mats) return YAO_ENOMEM;
+    }
+    *nblk = adjoint_nblk(n, k, B);
+    const bool g = M != nullptr;
+    const double* dm = dev_mats;
+#define YAO_ADJ_CASES(RL)                                                                  \
+    switch (k) {                                                                           \
+    case 1: return adjoint_k<RL, 1>(psi, lam, n, B, locs, c, m1, dm, g, partial);          \
+    case 2: return adjoint_k<RL, 2>(psi, lam, n, B, locs, c, m1, dm, g, partial);          \
+    case 3: return adjoint_k<RL, 3>(psi, lam, n, B, locs, c, m1, dm, g, partial);          \
+    case 4: return adjoint_k<RL, 4>(psi, lam, n, B, locs, c, m1, dm, g, partial);          \
+    case 5: return adjoint_k<RL, 5>(psi, lam, n, B, locs, c, m1, dm, g, partial);          \
+    default: return set_error(YAO_EINVAL, "k = %d not supported", k);                      \
+    }
+    if (lam_dtype == YAO_C64) {
+        YAO_ADJ_CASES(float)
+    } else {
+        YAO_ADJ_CASES(double)
+    }
+#undef YAO_ADJ_CASES
+}
+
+}  // namespace yao

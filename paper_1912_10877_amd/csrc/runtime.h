@@ -1,0 +1,114 @@
+// Host runtime of the gfx950 state-vector library: errors, stream, workspace, gate matrices
+// and the launchers of every kernel family.
+#pragma once
+
+#include "common.h"
+
+namespace yao {
+
+// ---------------------------------------------------------------------------- errors
+int set_error(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+#define YAO_HIP(call)                                   \
+    do {                                                \
+        hipError_t _e = (call);                         \
+        if (_e != hipSuccess) return hip_fail(_e, #call); \
+    } while (0)
+#define YAO_TRY(call)          \
+    do {                       \
+        int _r = (call);       \
+        if (_r != 0) return _r; \
+    } while (0)
+
+hipStream_t stream();
+const yao_options& options();
+int ensure_device();
+
+// ---------------------------------------------------------------------------- workspace
+// Named device scratch slots that grow on demand and live until the library unloads.
+enum WsSlot {
+    WS_PSI0 = 0,    // copy of the input state (drift check)
+    WS_PSI64,       // complex128 state of the backward sweep
+    WS_LAM,         // adjoint state
+    WS_PARTIAL,     // per-block partial sums
+    WS_PARTIAL2,    // second-level sums
+    WS_MAT,         // gate matrices and pass programs
+    WS_CKPT,        // checkpoints
+    WS_SEG,         // segment states of the checkpointed backward
+    WS_MISC,
+    WS_COUNT
+};
+void* workspace(int slot, size_t bytes);
+// Pinned host staging buffer for results (grows on demand).
+void* host_staging(size_t bytes);
+// Copy a small host block (<= 64 KiB) into the next slot of a device ring and return the slot.
+// The copy is queued on the current stream, so kernels queued after it see the data; slots
+// are reused round-robin after 256 uploads.
+void* ring_upload(const void* host, size_t bytes);
+// Copy a host block into workspace slot `slot` (grown as needed), ordered on the stream.
+void* upload_to(int slot, const void* host, size_t bytes);
+
+// ---------------------------------------------------------------------------- matrices
+// A dense 2^k x 2^k complex matrix in FP64, row-major; row/col bit j <-> locs[j].
+struct HostMat {
+    int k = 0;
+    std::vector<double> re, im;
+    int dim() const { return 1 << k; }
+    void resize(int kk)
+    {
+        k = kk;
+        re.assign(size_t(1) << (2 * k), 0.0);
+        im.assign(size_t(1) << (2 * k), 0.0);
+    }
+};
+bool is_param_kind(int kind);
+// U(theta) of a gate; returns false on an unknown kind.
+bool gate_matrix(const GateRec& g, double theta, HostMat& U);
+// (dU/dtheta) U^dagger, so that dE/dtheta = 2 Re <lambda_{k+1}| M |psi_{k+1}> on the gate's
+// controlled subspace.
+bool gate_grad_matrix(const GateRec& g, double theta, HostMat& M);
+HostMat dagger(const HostMat& U);
+HostMat matmul(const HostMat& A, const HostMat& B);
+
+// Matrix classes that pick a kernel specialisation (App. "sparse matrices": diagonal,
+// permutation-with-phases, dense).
+enum MatClass { MC_DENSE = 0, MC_DIAG = 1, MC_DIAG1 = 2, MC_ANTI = 3 };
+int classify(const HostMat& U);
+
+// ---------------------------------------------------------------------------- launchers
+struct CtrlSpec {
+    uint64_t mask = 0, val = 0;
+};
+CtrlSpec make_ctrl(int nctrl, const int* ctrls, const int* cvals);
+
+int launch_reset(yao_state* s);
+int launch_fill_basis(void* data, int dtype, int n, int B);
+// One gate on a state of either precision (per-gate form).
+// k >= 2 matrices come from dev_mat (re block then im block, rounded to the state's real
+// type) or, when dev_mat is null, from a ring upload.
+int launch_gate(void* data, int dtype, int n, int B, const HostMat& U, const int* locs, CtrlSpec c,
+                const void* dev_mat = nullptr);
+// energy[b] (host) = Re <psi|H|psi>.
+int launch_expect(const void* data, int dtype, int n, int B, yao_pauli_sum* h, double* energy_host);
+// out = H psi; energy[b] (host, may be null) from the same pass. out_dtype may differ.
+int launch_hpsi(const void* data, int dtype, void* out, int out_dtype, int n, int B, yao_pauli_sum* h,
+                double* energy_host);
+// Precision conversion / copies between states of equal shape.
+int launch_convert(const void* src, int src_dtype, void* dst, int dst_dtype, size_t elems);
+// max |a - b| over the elements (host result).
+int launch_maxdiff(const void* a, int a_dtype, const void* b, int b_dtype, size_t elems, double* out);
+
+// One reverse step of the per-gate backward: grad partials of gate g (if M != null) with
+// psi_{k+1}, lambda_{k+1}, then psi <- Ud psi, lambda <- Ud lambda. psi is complex128,
+// lambda is lam_dtype. partial receives [B][nblk] doubles; nblk is returned via *nblk.
+// k >= 2 matrices come from dev_mats (Ud re, Ud im, M re, M im; 4^k doubles each) or a ring upload.
+int launch_adjoint_step(double* psi, void* lam, int lam_dtype, int n, int B, const HostMat& Ud, const HostMat* M,
+                        const int* locs, CtrlSpec c, const double* dev_mats, double* partial, int* nblk);
+int adjoint_nblk(int n, int k, int B);
+// sums[r] = sum_j partial[r * nblk + j] for r < rows (device), sequential per row.
+int launch_row_sums(const double* partial, int rows, int nblk, double* sums);
+
+// Pauli tables
+int pauli_upload(yao_pauli_sum* h);
+
+}  // namespace yao
