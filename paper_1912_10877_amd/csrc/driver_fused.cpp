@@ -1,0 +1,303 @@
+// Fused execution of circuits: plans are cached per circuit and geometry; each call lowers
+// the current parameters to one device program (ops, groups, FP64 matrices) and launches one
+// kernel per pass.
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "driver.h"
+#include "fused.h"
+
+namespace yao {
+
+int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, const POp* ops, const PGroupDesc* groups,
+                const double* mats, double* gpartial, int pstride, int n, int B, int c, int t, int group0,
+                int ngroups, const std::vector<int>& tile_qubits);
+int launch_fill(double* p, size_t count, double v);
+int launch_adjoint_step_strided(double* psi, void* lam, int lam_dtype, int n, int B, const HostMat& Ud,
+                                const HostMat* M, const int* locs, CtrlSpec c, double* partial, int pstride);
+
+namespace {
+
+using PlanKey = std::tuple<const yao_circuit*, uint64_t, int, int, int, int, bool>;
+std::map<PlanKey, Plan> g_plans;
+std::mutex g_plan_mu;
+
+const Plan& get_plan(const yao_circuit* c, int B, int t, int cb, int L, bool reverse)
+{
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    PlanKey key{c, c->version, B, t, cb, L, reverse};
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) return it->second;
+    return g_plans.emplace(key, make_plan(c, B, t, cb, L, reverse)).first->second;
+}
+
+int op_type_of(const HostMat& U)
+{
+    if (U.k != 1) return OT_LDSK;
+    const auto& r = U.re;
+    const auto& i = U.im;
+    if (r[0] == 0 && i[0] == 0 && r[3] == 0 && i[3] == 0) {
+        if (r[1] == 1 && i[1] == 0 && r[2] == 1 && i[2] == 0) return OT_SWAP;
+        return OT_ANTI;
+    }
+    if (r[1] == 0 && i[1] == 0 && r[2] == 0 && i[2] == 0) return (r[0] == 1 && i[0] == 0) ? OT_DIAG1 : OT_DIAG;
+    if (i[0] == 0 && i[1] == 0 && i[2] == 0 && i[3] == 0) return OT_REAL;
+    if (i[0] == 0 && i[3] == 0 && r[1] == 0 && r[2] == 0 && r[0] == r[3] && i[1] == i[2]) return OT_RX;
+    return OT_DENSE;
+}
+
+int gen_type_of(const GateRec& g)
+{
+    if (g.k != 1) return GEN_DENSE;
+    switch (g.kind) {
+    case YAO_RX: return GEN_X;
+    case YAO_RY: return GEN_Y;
+    case YAO_RZ: return GEN_Z;
+    case YAO_SHIFT: return GEN_P1;
+    default: return GEN_DENSE;
+    }
+}
+
+// Device program of one plan for the given parameters.
+struct Program {
+    std::vector<POp> ops;
+    std::vector<PGroupDesc> groups;
+    std::vector<double> mats;
+    std::vector<int> pass_group0;   // per pass
+    std::vector<int> slot_of_gate;  // gradient slot per gate (-1)
+    int nslots = 0;
+};
+
+void append(std::vector<double>& v, const std::vector<double>& a)
+{
+    v.insert(v.end(), a.begin(), a.end());
+}
+
+int build_program(const Plan& P, const yao_circuit* c, const double* params, bool bwd, Program& prog)
+{
+    const int G = (int)c->gates.size();
+    prog.slot_of_gate.assign(G, -1);
+    if (bwd) {
+        for (int g = 0; g < G; ++g)
+            if (is_param_kind(c->gates[g].kind) && c->gates[g].param >= 0) prog.slot_of_gate[g] = prog.nslots++;
+    }
+    for (const HostPass& pass : P.passes) {
+        prog.pass_group0.push_back((int)prog.groups.size());
+        if (pass.standalone >= 0) continue;
+        uint64_t T = 0;
+        for (int q : pass.tile_qubits) T |= uint64_t(1) << q;
+        auto tile_bit = [&](int q) {
+            int r = 0;
+            for (int j = 0; j < q; ++j) r += (T >> j) & 1;
+            return P.c + r;
+        };
+        for (const HostGroup& hg : pass.groups) {
+            PGroupDesc gd;
+            memset(&gd, 0, sizeof(gd));
+            int nr = 0;
+            for (int b = 0; b < P.t; ++b)
+                if ((hg.rbits >> b) & 1) {
+                    if (nr < kRegBits) gd.rpos[nr] = b;
+                    ++nr;
+                }
+            gd.lds = hg.lds ? 1 : 0;
+            gd.op0 = (int)prog.ops.size();
+            gd.nops = (int)hg.ops.size();
+            gd.nslot = 0;
+            for (int oi : hg.ops) {
+                const HostOp& hop = P.ops[oi];
+                const GateRec& g = c->gates[hop.gate];
+                const double th = gate_theta(g, params);
+                HostMat U;
+                if (!gate_matrix(g, th, U)) return set_error(YAO_EINVAL, "bad gate %d", hop.gate);
+                POp op;
+                memset(&op, 0, sizeof(op));
+                op.k = g.k;
+                op.slot = bwd ? prog.slot_of_gate[hop.gate] : -1;
+                op.mat = (int)prog.mats.size();
+                if (!bwd) {
+                    op.type = op_type_of(U);
+                    op.gen = GEN_NONE;
+                    append(prog.mats, U.re);
+                    append(prog.mats, U.im);
+                } else {
+                    HostMat Ud = dagger(U);
+                    op.type = op_type_of(Ud);
+                    append(prog.mats, Ud.re);
+                    append(prog.mats, Ud.im);
+                    HostMat M;
+                    if (op.slot >= 0) {
+                        gate_grad_matrix(g, th, M);
+                        op.gen = gen_type_of(g);
+                        gd.nslot++;
+                    } else {
+                        M.resize(g.k);
+                        op.gen = GEN_NONE;
+                    }
+                    append(prog.mats, M.re);
+                    append(prog.mats, M.im);
+                }
+                if (g.k > 1) op.type = OT_LDSK;
+                for (int j = 0; j < g.k; ++j) op.tpos[j] = tile_bit(g.locs[j]);
+                op.rpos = 0;
+                if (!hg.lds) {
+                    for (int j = 0; j < kRegBits; ++j)
+                        if (gd.rpos[j] == op.tpos[0]) op.rpos = j;
+                }
+                for (int m = 0; m < g.nctrl; ++m) {
+                    const int q = g.ctrls[m];
+                    if ((T >> q) & 1) {
+                        op.cmask |= 1u << tile_bit(q);
+                        if (g.cvals[m]) op.cval |= 1u << tile_bit(q);
+                    } else {
+                        op.omask |= uint64_t(1) << q;
+                        if (g.cvals[m]) op.oval |= uint64_t(1) << q;
+                    }
+                }
+                prog.ops.push_back(op);
+            }
+            prog.groups.push_back(gd);
+        }
+    }
+    return 0;
+}
+
+struct DevProgram {
+    POp* ops;
+    PGroupDesc* groups;
+    double* mats;
+};
+
+int upload_program(const Program& prog, DevProgram& d)
+{
+    const size_t so = prog.ops.size() * sizeof(POp);
+    const size_t sg = prog.groups.size() * sizeof(PGroupDesc);
+    const size_t sm = prog.mats.size() * sizeof(double);
+    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    std::vector<char> blob(al(so) + al(sg) + al(sm) + 256, 0);
+    if (so) memcpy(blob.data(), prog.ops.data(), so);
+    if (sg) memcpy(blob.data() + al(so), prog.groups.data(), sg);
+    if (sm) memcpy(blob.data() + al(so) + al(sg), prog.mats.data(), sm);
+    char* dev = (char*)upload_to(WS_MAT, blob.data(), blob.size());
+    if (!dev) return YAO_ENOMEM;
+    d.ops = (POp*)dev;
+    d.groups = (PGroupDesc*)(dev + al(so));
+    d.mats = (double*)(dev + al(so) + al(sg));
+    return 0;
+}
+
+}  // namespace
+
+int forward_fused(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params)
+{
+    if (c->gates.empty()) return 0;
+    int t, cb, L;
+    tile_geometry(n, B, dtype, false, &t, &cb, &L);
+    const Plan& P = get_plan(c, B, t, cb, L, false);
+    Program prog;
+    YAO_TRY(build_program(P, c, params, false, prog));
+    DevProgram d;
+    YAO_TRY(upload_program(prog, d));
+    for (size_t p = 0; p < P.passes.size(); ++p) {
+        const HostPass& pass = P.passes[p];
+        if (pass.standalone >= 0) {
+            const GateRec& g = c->gates[P.ops[pass.standalone].gate];
+            HostMat U;
+            gate_matrix(g, gate_theta(g, params), U);
+            YAO_TRY(launch_gate(data, dtype, n, B, U, g.locs, make_ctrl(g.nctrl, g.ctrls, g.cvals)));
+            continue;
+        }
+        YAO_TRY(launch_pass(false, dtype, dtype, data, nullptr, d.ops, d.groups, d.mats, nullptr, 0, n, B, cb, t,
+                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits));
+    }
+    return 0;
+}
+
+int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h, int mode,
+                   bool reduce_batch, double* energy, double* grad, double* drift)
+{
+    (void)mode;
+    const int n = s->n, B = s->batch;
+    const size_t elems = s->elems();
+    hipStream_t st = stream();
+    void* psi0 = workspace(WS_PSI0, s->bytes());
+    if (!psi0) return YAO_ENOMEM;
+    YAO_HIP(hipMemcpyAsync(psi0, s->data, s->bytes(), hipMemcpyDeviceToDevice, st));
+    YAO_TRY(forward_fused(s->data, s->dtype, n, B, c, params));
+    double* psi = (double*)workspace(WS_PSI64, elems * 16);
+    void* lam = workspace(WS_LAM, s->bytes());
+    if (!psi || !lam) return YAO_ENOMEM;
+    YAO_TRY(launch_convert(s->data, s->dtype, psi, YAO_C128, elems));
+    YAO_TRY(launch_hpsi(s->data, s->dtype, lam, s->dtype, n, B, h, energy));
+
+    int t, cb, L;
+    tile_geometry(n, B, s->dtype, true, &t, &cb, &L);
+    const Plan& P = get_plan(c, B, t, cb, L, true);
+    Program prog;
+    YAO_TRY(build_program(P, c, params, true, prog));
+    DevProgram d;
+    YAO_TRY(upload_program(prog, d));
+    const int ntiles = 1 << (n - (t - cb));
+    const int W = std::max(ntiles, adjoint_nblk(n, 1, B));
+    const int nslots = prog.nslots;
+    double* gpartial = (double*)workspace(WS_PARTIAL, sizeof(double) * (size_t)std::max(1, nslots) * B * W);
+    if (!gpartial) return YAO_ENOMEM;
+    if (nslots) YAO_TRY(launch_fill(gpartial, (size_t)nslots * B * W, 0.0));
+    for (size_t p = 0; p < P.passes.size(); ++p) {
+        const HostPass& pass = P.passes[p];
+        if (pass.standalone >= 0) {
+            const int gi = P.ops[pass.standalone].gate;
+            const GateRec& g = c->gates[gi];
+            const double th = gate_theta(g, params);
+            HostMat U, M;
+            gate_matrix(g, th, U);
+            HostMat Ud = dagger(U);
+            const int slot = prog.slot_of_gate[gi];
+            if (slot >= 0) gate_grad_matrix(g, th, M);
+            YAO_TRY(launch_adjoint_step_strided(psi, lam, s->dtype, n, B, Ud, slot >= 0 ? &M : nullptr, g.locs,
+                                                make_ctrl(g.nctrl, g.ctrls, g.cvals),
+                                                slot >= 0 ? gpartial + (size_t)slot * B * W : nullptr, W));
+            continue;
+        }
+        YAO_TRY(launch_pass(true, YAO_C128, s->dtype, psi, lam, d.ops, d.groups, d.mats, gpartial, W, n, B, cb, t,
+                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits));
+    }
+    const int P_ = c->nparams;
+    const size_t glen = reduce_batch ? (size_t)P_ : (size_t)P_ * B;
+    for (size_t e = 0; e < glen; ++e) grad[e] = 0.0;
+    if (nslots > 0) {
+        double* sums = (double*)workspace(WS_PARTIAL2, sizeof(double) * (size_t)nslots * B);
+        if (!sums) return YAO_ENOMEM;
+        YAO_TRY(launch_row_sums(gpartial, nslots * B, W, sums));
+        double* hs = (double*)host_staging(sizeof(double) * (size_t)nslots * B);
+        if (!hs) return YAO_ENOMEM;
+        YAO_HIP(hipMemcpyAsync(hs, sums, sizeof(double) * (size_t)nslots * B, hipMemcpyDeviceToHost, st));
+        YAO_HIP(hipStreamSynchronize(st));
+        for (int gi = (int)c->gates.size() - 1; gi >= 0; --gi) {
+            const int slot = prog.slot_of_gate[gi];
+            if (slot < 0) continue;
+            const int p = c->gates[gi].param;
+            for (int b = 0; b < B; ++b) {
+                const double v = hs[(size_t)slot * B + b];
+                if (reduce_batch) grad[p] += v;
+                else grad[(size_t)b * P_ + p] += v;
+            }
+        }
+    }
+    if (drift) YAO_TRY(launch_maxdiff(psi, YAO_C128, psi0, s->dtype, elems, drift));
+    else YAO_HIP(hipStreamSynchronize(st));
+    return 0;
+}
+
+void drop_plans(const yao_circuit* c)
+{
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+        if (std::get<0>(it->first) == c) it = g_plans.erase(it);
+        else ++it;
+    }
+}
+
+}  // namespace yao

@@ -6,6 +6,8 @@
 
 namespace yao {
 
+int launch_fill(double* p, size_t count, double v);
+
 int apply_one(yao_state* s, const GateRec& g, double theta)
 {
     HostMat U;
@@ -109,6 +111,8 @@ int backward_plain(yao_state* s, const yao_circuit* c, const double* params, yao
     const int nblk = adjoint_nblk(n, 1, B);
     double* partial = (double*)workspace(WS_PARTIAL, sizeof(double) * (size_t)(nslots > 0 ? nslots : 1) * B * nblk);
     if (!partial) return YAO_ENOMEM;
+    // Gates of k >= 2 launch fewer blocks than the row stride; the rest of each row stays zero.
+    if (nslots) YAO_TRY(launch_fill(partial, (size_t)nslots * B * nblk, 0.0));
     for (size_t tt = G; tt-- > 0;) {
         const GateRec& g = c->gates[tt];
         int nb = 0;

@@ -279,7 +279,8 @@ template <typename RL, int K, bool GRAD>
 __global__ __launch_bounds__(kThreads) void k_adjoint(double2* __restrict__ psi, vec2_t<RL>* __restrict__ lam,
                                                       uint64_t rows, int B, int logBc, GroupGeom<K> gg,
                                                       uint64_t cmask, uint64_t cval, AdjMats1 m1,
-                                                      const double* __restrict__ mats, double* __restrict__ partial)
+                                                      const double* __restrict__ mats, double* __restrict__ partial,
+                                                      int pstride)
 {
     constexpr int D = 1 << K;
     constexpr int DD = D * D;
@@ -333,8 +334,14 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(double2* __restrict__ psi,
     }
     if (GRAD) {
         double s = block_sum_by_slot(acc, logBc, red);
-        if ((int)threadIdx.x < (1 << logBc) && b < B) partial[(uint64_t)b * gridDim.x + blockIdx.x] = s;
+        if ((int)threadIdx.x < (1 << logBc) && b < B) partial[(uint64_t)b * pstride + blockIdx.x] = s;
     }
+}
+
+__global__ void k_fill(double* __restrict__ p, uint64_t count, double v)
+{
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (uint64_t)gridDim.x * blockDim.x)
+        p[e] = v;
 }
 
 template <int K> GroupGeom<K> make_group_geom(const int* locs)
@@ -603,7 +610,7 @@ int adjoint_nblk(int n, int k, int B)
 
 template <typename RL, int K>
 static int adjoint_k(double* psi, void* lam, int n, int B, const int* locs, CtrlSpec c, const AdjMats1& m1,
-                     const double* dm, bool grad, double* partial)
+                     const double* dm, bool grad, double* partial, int pstride)
 {
     BatchGeom bg = make_batch_geom(B);
     uint64_t rows = uint64_t(1) << (n - K);
@@ -612,16 +619,16 @@ static int adjoint_k(double* psi, void* lam, int n, int B, const int* locs, Ctrl
     GroupGeom<K> gg = make_group_geom<K>(locs);
     if (grad)
         k_adjoint<RL, K, true><<<grid, kThreads, 0, stream()>>>((double2*)psi, (vec2_t<RL>*)lam, rows, B, bg.logBc, gg,
-                                                                 c.mask, c.val, m1, dm, partial);
+                                                                 c.mask, c.val, m1, dm, partial, pstride > 0 ? pstride : nbx);
     else
         k_adjoint<RL, K, false><<<grid, kThreads, 0, stream()>>>((double2*)psi, (vec2_t<RL>*)lam, rows, B, bg.logBc, gg,
-                                                                  c.mask, c.val, m1, dm, partial);
+                                                                  c.mask, c.val, m1, dm, partial, nbx);
     YAO_HIP(hipGetLastError());
     return 0;
 }
 
-int launch_adjoint_step(double* psi, void* lam, int lam_dtype, int n, int B, const HostMat& Ud, const HostMat* M,
-                        const int* locs, CtrlSpec c, const double* dev_mats, double* partial, int* nblk)
+static int adjoint_step_impl(double* psi, void* lam, int lam_dtype, int n, int B, const HostMat& Ud, const HostMat* M,
+                             const int* locs, CtrlSpec c, const double* dev_mats, double* partial, int pstride)
 {
     const int k = Ud.k;
     AdjMats1 m1;
@@ -649,16 +656,15 @@ int launch_adjoint_step(double* psi, void* lam, int lam_dtype, int n, int B, con
         dev_mats = (const double*)ring_upload(h.data(), h.size() * sizeof(double));
         if (!dev_mats) return YAO_ENOMEM;
     }
-    *nblk = adjoint_nblk(n, k, B);
     const bool g = M != nullptr;
     const double* dm = dev_mats;
 #define YAO_ADJ_CASES(RL)                                                                  \
     switch (k) {                                                                           \
-    case 1: return adjoint_k<RL, 1>(psi, lam, n, B, locs, c, m1, dm, g, partial);          \
-    case 2: return adjoint_k<RL, 2>(psi, lam, n, B, locs, c, m1, dm, g, partial);          \
-    case 3: return adjoint_k<RL, 3>(psi, lam, n, B, locs, c, m1, dm, g, partial);          \
-    case 4: return adjoint_k<RL, 4>(psi, lam, n, B, locs, c, m1, dm, g, partial);          \
-    case 5: return adjoint_k<RL, 5>(psi, lam, n, B, locs, c, m1, dm, g, partial);          \
+    case 1: return adjoint_k<RL, 1>(psi, lam, n, B, locs, c, m1, dm, g, partial, pstride);          \
+    case 2: return adjoint_k<RL, 2>(psi, lam, n, B, locs, c, m1, dm, g, partial, pstride);          \
+    case 3: return adjoint_k<RL, 3>(psi, lam, n, B, locs, c, m1, dm, g, partial, pstride);          \
+    case 4: return adjoint_k<RL, 4>(psi, lam, n, B, locs, c, m1, dm, g, partial, pstride);          \
+    case 5: return adjoint_k<RL, 5>(psi, lam, n, B, locs, c, m1, dm, g, partial, pstride);          \
     default: return set_error(YAO_EINVAL, "k = %d not supported", k);                      \
     }
     if (lam_dtype == YAO_C64) {
@@ -667,6 +673,28 @@ int launch_adjoint_step(double* psi, void* lam, int lam_dtype, int n, int B, con
         YAO_ADJ_CASES(double)
     }
 #undef YAO_ADJ_CASES
+}
+
+int launch_adjoint_step(double* psi, void* lam, int lam_dtype, int n, int B, const HostMat& Ud, const HostMat* M,
+                        const int* locs, CtrlSpec c, const double* dev_mats, double* partial, int* nblk)
+{
+    *nblk = adjoint_nblk(n, 1, B);
+    return adjoint_step_impl(psi, lam, lam_dtype, n, B, Ud, M, locs, c, dev_mats, partial, *nblk);
+}
+
+// Same, with the per-slot partial rows pstride apart (pstride >= the launch's block count).
+int launch_adjoint_step_strided(double* psi, void* lam, int lam_dtype, int n, int B, const HostMat& Ud,
+                                const HostMat* M, const int* locs, CtrlSpec c, double* partial, int pstride)
+{
+    return adjoint_step_impl(psi, lam, lam_dtype, n, B, Ud, M, locs, c, nullptr, partial, pstride);
+}
+
+int launch_fill(double* p, size_t count, double v)
+{
+    unsigned nb = (unsigned)std::min<uint64_t>((count + 255) / 256, 4096);
+    k_fill<<<nb, 256, 0, stream()>>>(p, count, v);
+    YAO_HIP(hipGetLastError());
+    return 0;
 }
 
 }  // namespace yao

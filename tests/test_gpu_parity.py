@@ -210,3 +210,70 @@ def test_invalid_calls_leave_state_unchanged():
     with pytest.raises(yb.YaoError):
         s.apply(np.eye(4), [0, 0])
     np.testing.assert_array_equal(s.download(), psi0)
+
+
+# ---------------------------------------------------------------------------------------
+# Fused tile passes: several tiles and passes, ragged batches, controls outside the tile,
+# 2- and 3-qubit gates in LDS and wider gates as standalone launches.
+# ---------------------------------------------------------------------------------------
+
+def with_gate_of_width(circ, k, seed):
+    rng = np.random.default_rng(seed)
+    q = rng.permutation(circ.n)
+    g = w.Gate("dense", tuple(int(x) for x in q[:k]), ctrls=(int(q[k]),), cvals=(0,), G=w.random_unitary(1 << k, rng))
+    gates = list(circ.gates)
+    gates.insert(len(gates) // 2, g)
+    return w.Circuit(circ.n, gates, circ.nparams)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,B,tq", [(5, 1, 0), (9, 3, 0), (13, 1, 0), (16, 1, 0), (14, 8, 6), (12, 100, 0), (15, 2, 5)])
+def test_fused_forward_matches_oracle(dtype, n, B, tq):
+    yb.set_options(plain=0, tile_qubits=tq)
+    try:
+        circ = w.random_gate_list(n, 60, seed=1000 + n + B, kmax=3, max_ctrl=2)
+        circ = with_gate_of_width(circ, 4, n)
+        params = w.angles(n, circ.nparams)
+        psi0 = w.random_state(n, B, n)
+        s = yb.State(n, B, dtype)
+        s.upload(psi0)
+        yb.forward(s, yb.Circuit.from_workload(circ), params)
+        want = oracle.forward(circ, params, psi0)
+        assert np.abs(s.download() - want).max() <= amp_tol(dtype, len(circ.gates))
+    finally:
+        yb.set_options(tile_qubits=0)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,B,tq", [(6, 1, 0), (12, 1, 0), (15, 1, 6), (11, 5, 0), (13, 2, 5)])
+def test_fused_backward_matches_oracle(dtype, n, B, tq):
+    yb.set_options(plain=0, tile_qubits=tq)
+    try:
+        circ = w.random_gate_list(n, 50, seed=2000 + n + B, kmax=3, max_ctrl=2)
+        circ = with_gate_of_width(circ, 5, n)
+        H = w.heisenberg(n)
+        params = w.angles(n + 1, circ.nparams)
+        psi0 = w.random_state(n, B, n)
+        e_ref, g_ref, _ = oracle.adjoint(H, circ, params, psi0)
+        s = yb.State(n, B, dtype)
+        s.upload(psi0)
+        e, g, drift = yb.backward(s, yb.Circuit.from_workload(circ), params, yb.PauliSum.from_workload(H))
+        np.testing.assert_allclose(e, e_ref, atol=1e-10 if dtype == 1 else 1e-5)
+        assert np.abs(g - g_ref).max() <= grad_tol(dtype, g_ref)
+        assert drift <= (1e-11 if dtype == 1 else 1e-5)
+    finally:
+        yb.set_options(tile_qubits=0)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_fused_hea_deep(dtype):
+    """The workload ansatz at 14 qubits, depth 6: several passes and register groups per layer."""
+    n, depth = 14, 6
+    circ = w.hea_circuit(n, depth)
+    H = w.heisenberg(n)
+    params = w.angles(7, circ.nparams)
+    e_ref, g_ref, _ = oracle.adjoint(H, circ, params, w.zero_state(n))
+    s = yb.State(n, 1, dtype)
+    e, g, drift = yb.backward(s, yb.Circuit.from_workload(circ), params, yb.PauliSum.from_workload(H))
+    assert abs(e[0] - e_ref[0]) <= (1e-10 if dtype == 1 else 1e-5)
+    assert np.abs(g - g_ref).max() <= grad_tol(dtype, g_ref)
