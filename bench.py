@@ -1,0 +1,167 @@
+"""Benchmark: energy + all gradients of the 20-qubit Heisenberg VQE ansatz on one MI355X.
+
+One step = reset the register to |0...0>, run the circuit, evaluate the periodic Heisenberg
+energy, run the reversible adjoint sweep for all 1200 gradients and copy energy and
+gradients to the host -- the whole hot path, on synthetic seeded angles.
+
+Prints one JSON line. `value` is amplitude updates per second: per step, every gate of the
+circuit counts 2^n * B updates in the forward sweep and 2 * 2^n * B in the reverse sweep
+(psi and lambda). `roofline` describes the kernel family with the most GPU time, timed
+with HIP events on the library's stream during the timed steps; `cpu_baseline` is the FP64
+oracle on a bounded sample of the same workload on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "amplitude-updates/s & HBM GB/s, 20q fwd+grad; batched-adjoint vs plain speedup"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+FAMILIES = {0: "gate", 1: "adjoint", 2: "pass_fwd", 3: "pass_bwd", 4: "expect", 5: "hpsi", 6: "mfma", 7: "batch"}
+KERNEL_NAMES = {0: "k_gate1/k_gatek", 1: "k_adjoint", 2: "k_pass<fwd>", 3: "k_pass<bwd>", 4: "k_expect", 5: "k_hpsi",
+                6: "k_dense_mfma", 7: "k_batch"}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--qubits", type=int, default=20)
+    p.add_argument("--depth", type=int, default=20)
+    p.add_argument("--batch", type=int, default=1)
+    p.add_argument("--dtype", choices=["c64", "c128"], default="c64")
+    p.add_argument("--mode", choices=["reversible", "checkpoint", "auto"], default="reversible")
+    p.add_argument("--plain-steps", type=int, default=2)
+    p.add_argument("--cpu-depth", type=int, default=6, help="depth of the oracle sample")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-profile", action="store_true")
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU sharding of the state is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as w
+    from paper_1912_10877_amd import binding as yb
+
+    torch.cuda.set_device(0)
+    yb.init()
+    yb.use_torch_stream()
+    n, depth, B = args.qubits, args.depth, args.batch
+    dtype = yb.C64 if args.dtype == "c64" else yb.C128
+    mode = {"reversible": yb.GRAD_REVERSIBLE, "checkpoint": yb.GRAD_CHECKPOINT, "auto": yb.GRAD_AUTO}[args.mode]
+    circ_w = w.hea_circuit(n, depth)
+    H_w = w.heisenberg(n)
+    params = w.angles(2, circ_w.nparams)
+    circ = yb.Circuit.from_workload(circ_w)
+    H = yb.PauliSum.from_workload(H_w)
+    ngates = len(circ_w.gates)
+    tensor = torch.empty((1 << n) * B, dtype=torch.complex64 if dtype == yb.C64 else torch.complex128, device="cuda")
+    s = yb.State(n, B, dtype, tensor=tensor)
+
+    def step():
+        s.reset()
+        return yb.backward(s, circ, params, H, mode=mode)
+
+    for _ in range(args.warmup):
+        e, g, drift = step()
+    if not args.no_profile:
+        yb.lib().yao_profile_enable(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e, g, drift = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {}
+    if not args.no_profile:
+        import ctypes
+        yb.lib().yao_profile_enable(0)
+        yb.lib().yao_profile_read.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        for fam in FAMILIES:
+            nl, ms, by, fl = ctypes.c_int(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            yb.lib().yao_profile_read(fam, ctypes.byref(nl), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl))
+            if nl.value:
+                prof[fam] = (nl.value, ms.value, by.value, fl.value)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    au_step = 3.0 * ngates * (1 << n) * B
+    value = au_step / (ms_step / 1e3)
+
+    # Plain per-gate form on the same GPU and dtype, for the speedup.
+    plain_ms = None
+    if args.plain_steps > 0:
+        yb.set_options(plain=1)
+        step()
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step()
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - p0) * 1e3 / args.plain_steps
+        yb.set_options(plain=0)
+
+    roofline = None
+    if prof:
+        fam = max(prof, key=lambda f: prof[f][1])
+        nl, ms, by, fl = prof[fam]
+        gbs = by / (ms / 1e3) / 1e9
+        tfl = fl / (ms / 1e3) / 1e12
+        peak_alu = FP64_PEAK_TFLOPS if fam in (1, 3) or dtype == yb.C128 else FP32_PEAK_TFLOPS / 2
+        if gbs / HBM_PEAK_GBS >= tfl / peak_alu:
+            roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+        else:
+            roofline = {"bound": "alu", "achieved": round(tfl, 3), "peak": peak_alu, "unit": "TFLOP/s",
+                        "frac": round(tfl / peak_alu, 4), "traffic": None}
+        roofline.update({"kernel": KERNEL_NAMES[fam], "launches_per_step": nl / args.steps,
+                         "avg_launch_us": round(ms * 1e3 / nl, 2), "algo_bytes_per_launch": by / nl,
+                         "algo_flops_per_launch": fl / nl, "achieved_gbs": round(gbs, 1),
+                         "achieved_tflops": round(tfl, 3),
+                         "gpu_ms_by_family": {FAMILIES[f]: round(prof[f][1] / args.steps, 4) for f in prof}})
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cd = max(1, min(args.cpu_depth, depth))
+        sub = w.hea_circuit(n, cd)
+        sp = w.angles(2, sub.nparams)
+        c0 = time.perf_counter()
+        oracle.adjoint(H_w, sub, sp, w.zero_state(n, 1))
+        c1 = time.perf_counter()
+        au = 3.0 * len(sub.gates) * (1 << n)
+        cpu = {"value": au / (c1 - c0), "unit": "amplitude-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"FP64 C oracle, energy + adjoint gradients of the same ansatz at n={n}, depth {cd} "
+                         f"({len(sub.gates)} gates, batch 1), {c1 - c0:.2f} s wall"}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "amplitude-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": f"vqe{n}: {n}-qubit Rx.Rz.Rx + CNOT-chain ansatz, depth {depth}, "
+                               f"{circ_w.nparams} params, periodic Heisenberg energy + all gradients, "
+                               f"{args.mode} adjoint", "qubits": n, "depth": depth, "batch": B,
+                   "params": circ_w.nparams, "gates": ngates, "grad_mode": args.mode},
+        "energy": float(e[0]), "drift": drift,
+        "plain_ms_per_step": plain_ms,
+        "speedup_vs_plain": (plain_ms / ms_step) if plain_ms else None,
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

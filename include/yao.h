@@ -68,18 +68,23 @@ enum yao_gate {
 };
 
 /* Backward strategies. REVERSIBLE uncomputes the state with inverse gates (constant memory
- * in depth, Sec. "Reverse Mode"). CHECKPOINT keeps forward states and restarts each
- * backward step from them (memory grows with depth). AUTO uncomputes and falls back to the
- * stored checkpoint wherever the uncomputed state drifts past the bound. */
+ * in depth, Sec. "Reverse Mode"). CHECKPOINT cuts the circuit into segments of
+ * checkpoint_every gates, keeps the forward state at every segment end and restarts the
+ * reverse sweep of each segment from it (memory grows with depth). AUTO keeps the same
+ * states but restarts from one only where the uncomputed state differs from it by more
+ * than drift_tol. */
 enum yao_grad_mode { YAO_GRAD_REVERSIBLE = 0, YAO_GRAD_CHECKPOINT = 1, YAO_GRAD_AUTO = 2 };
 
 /* Execution options (process-wide; set before the calls they should affect).
  *   plain            1: one kernel launch per gate (the per-gate form); 0: fused tile passes.
  *   tile_qubits      qubits per fused tile (0 = chosen by the library or the autotuner).
  *   fuse_width       widest host-fused dense block, 1..5 (1 = no dense fusion).
- *   checkpoint_every passes between stored states in CHECKPOINT / AUTO mode (0 = sqrt rule).
- *   drift_tol        max |psi_uncomputed - psi_stored| accepted before falling back
- *                    (0 = 1e-5 for complex64 states, 1e-10 for complex128).
+ *   checkpoint_every gates per segment in CHECKPOINT / AUTO mode (0 = max(sqrt(#gates), 4n)).
+ *   drift_tol        max |psi_uncomputed - psi_stored| accepted by AUTO before falling back
+ *                    (0 = 1e-5 for complex64 states, 1e-10 for complex128). In REVERSIBLE
+ *                    mode a drift_tol > 0 makes yao_backward return YAO_EDRIFT when the
+ *                    uncomputed input differs from the input by more than drift_tol (the
+ *                    outputs are still written).
  *   mfma             1: dense blocks of 4 or 5 qubits on complex64 states run on FP32
  *                    matrix cores; 0: on the vector units. */
 typedef struct {
@@ -176,6 +181,29 @@ int yao_backward(yao_state* s, const yao_circuit* c, const double* params, const
 int yao_batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* circs,
                   const double* const* params, const yao_pauli_sum* const* h, double* energy,
                   double* const* grad);
+
+/* Profiling ---------------------------------------------------------------------------- */
+
+/* Kernel families whose launches the profiler can time. */
+enum yao_kernel_family {
+    YAO_KF_GATE = 0,      /* per-gate forward kernels */
+    YAO_KF_ADJOINT = 1,   /* per-gate reverse-sweep kernels */
+    YAO_KF_PASS_FWD = 2,  /* fused forward tile passes */
+    YAO_KF_PASS_BWD = 3,  /* fused reverse-sweep tile passes */
+    YAO_KF_EXPECT = 4,    /* Pauli-sum expectation */
+    YAO_KF_HPSI = 5,      /* H psi (adjoint seed) */
+    YAO_KF_MFMA = 6,      /* dense 4/5-qubit blocks on matrix cores */
+    YAO_KF_BATCH = 7,     /* persistent batch kernel */
+    YAO_KF_COUNT = 8
+};
+/* on = 1 clears earlier records and starts bracketing every launch with a pair of HIP
+ * events on the bound stream; on = 0 stops. */
+int yao_profile_enable(int on);
+/* Totals for one family since profiling was enabled: number of launches, summed GPU time
+ * between each launch's events (ms), and the algorithmic bytes and flops those launches
+ * were credited with (bytes: each state element read or written once per launch; flops:
+ * real arithmetic of the gate applications). Synchronises. */
+int yao_profile_read(int family, int* launches, double* total_ms, double* algo_bytes, double* algo_flops);
 
 #ifdef __cplusplus
 }

@@ -65,6 +65,8 @@ _SIGS = {
     "yao_forward": [P, P, P],
     "yao_backward": [P, P, P, P, I, I, P, P, P],
     "yao_batch_run": [I, P, P, P, P, P, P],
+    "yao_profile_enable": [I],
+    "yao_profile_read": [I, P, P, P, P],
 }
 
 

@@ -382,4 +382,15 @@ int yao_batch_run(int ncirc, yao_state* const* states, const yao_circuit* const*
     return batch_run(ncirc, states, circs, params, const_cast<yao_pauli_sum* const*>(h), energy, grad);
 }
 
+int yao_profile_enable(int on)
+{
+    return prof_enable(on != 0);
+}
+
+int yao_profile_read(int family, int* launches, double* total_ms, double* algo_bytes, double* algo_flops)
+{
+    if (family < 0 || family >= YAO_KF_COUNT) return set_error(YAO_EINVAL, "unknown kernel family %d", family);
+    return prof_read(family, launches, total_ms, algo_bytes, algo_flops);
+}
+
 }  // extern "C"

@@ -13,24 +13,25 @@ namespace yao {
 
 int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, const POp* ops, const PGroupDesc* groups,
                 const double* mats, double* gpartial, int pstride, int n, int B, int c, int t, int group0,
-                int ngroups, const std::vector<int>& tile_qubits);
+                int ngroups, const std::vector<int>& tile_qubits, double flops);
 int launch_fill(double* p, size_t count, double v);
 int launch_adjoint_step_strided(double* psi, void* lam, int lam_dtype, int n, int B, const HostMat& Ud,
                                 const HostMat* M, const int* locs, CtrlSpec c, double* partial, int pstride);
 
 namespace {
 
-using PlanKey = std::tuple<const yao_circuit*, uint64_t, int, int, int, int, bool>;
+using PlanKey = std::tuple<const yao_circuit*, uint64_t, int, int, int, int, int, int, bool>;
 std::map<PlanKey, Plan> g_plans;
 std::mutex g_plan_mu;
 
-const Plan& get_plan(const yao_circuit* c, int B, int t, int cb, int L, bool reverse)
+const Plan& get_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse)
 {
     std::lock_guard<std::mutex> lk(g_plan_mu);
-    PlanKey key{c, c->version, B, t, cb, L, reverse};
+    PlanKey key{c, c->version, g0, g1, B, t, cb, L, reverse};
     auto it = g_plans.find(key);
     if (it != g_plans.end()) return it->second;
-    return g_plans.emplace(key, make_plan(c, B, t, cb, L, reverse)).first->second;
+    return g_plans.emplace(key, make_plan(c, g0, g1, B, t, cb, L, reverse, reverse ? kRegBitsBwd : kRegBitsFwd))
+        .first->second;
 }
 
 int op_type_of(const HostMat& U)
@@ -38,11 +39,9 @@ int op_type_of(const HostMat& U)
     if (U.k != 1) return OT_LDSK;
     const auto& r = U.re;
     const auto& i = U.im;
-    if (r[0] == 0 && i[0] == 0 && r[3] == 0 && i[3] == 0) {
-        if (r[1] == 1 && i[1] == 0 && r[2] == 1 && i[2] == 0) return OT_SWAP;
-        return OT_ANTI;
-    }
-    if (r[1] == 0 && i[1] == 0 && r[2] == 0 && i[2] == 0) return (r[0] == 1 && i[0] == 0) ? OT_DIAG1 : OT_DIAG;
+    if (r[0] == 0 && i[0] == 0 && r[3] == 0 && i[3] == 0 && r[1] == 1 && i[1] == 0 && r[2] == 1 && i[2] == 0)
+        return OT_SWAP;
+    if (r[1] == 0 && i[1] == 0 && r[2] == 0 && i[2] == 0) return OT_DIAG;
     if (i[0] == 0 && i[1] == 0 && i[2] == 0 && i[3] == 0) return OT_REAL;
     if (i[0] == 0 && i[3] == 0 && r[1] == 0 && r[2] == 0 && r[0] == r[3] && i[1] == i[2]) return OT_RX;
     return OT_DENSE;
@@ -60,12 +59,29 @@ int gen_type_of(const GateRec& g)
     }
 }
 
+// Real flops per state element of one op (complex multiply = 6, complex add = 2).
+double op_flops(const POp& op, bool bwd)
+{
+    double f;
+    switch (op.type) {
+    case OT_SWAP: f = 0; break;
+    case OT_DIAG: case OT_REAL: case OT_RX: f = 6; break;
+    case OT_LDSK: f = 8.0 * (1 << op.k) - 2.0; break;
+    default: f = 14; break;
+    }
+    if (!bwd) return f;
+    double g = 0;
+    if (op.slot >= 0) g = op.gen == GEN_DENSE ? 16 : (op.gen == GEN_P1 ? 2 : 4);
+    return 2 * f + g;
+}
+
 // Device program of one plan for the given parameters.
 struct Program {
     std::vector<POp> ops;
     std::vector<PGroupDesc> groups;
     std::vector<double> mats;
     std::vector<int> pass_group0;   // per pass
+    std::vector<double> pass_flops; // algorithmic flops per element of the state, per pass
     std::vector<int> slot_of_gate;  // gradient slot per gate (-1)
     int nslots = 0;
 };
@@ -85,6 +101,7 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
     }
     for (const HostPass& pass : P.passes) {
         prog.pass_group0.push_back((int)prog.groups.size());
+        prog.pass_flops.push_back(0.0);
         if (pass.standalone >= 0) continue;
         uint64_t T = 0;
         for (int q : pass.tile_qubits) T |= uint64_t(1) << q;
@@ -99,7 +116,7 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
             int nr = 0;
             for (int b = 0; b < P.t; ++b)
                 if ((hg.rbits >> b) & 1) {
-                    if (nr < kRegBits) gd.rpos[nr] = b;
+                    if (nr < P.reg_bits) gd.rpos[nr] = b;
                     ++nr;
                 }
             gd.lds = hg.lds ? 1 : 0;
@@ -140,10 +157,15 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     append(prog.mats, M.im);
                 }
                 if (g.k > 1) op.type = OT_LDSK;
+                if (g.k == 1)
+                    for (int e = 0; e < 4; ++e) {
+                        op.u[e] = prog.mats[op.mat + e];
+                        op.u[4 + e] = prog.mats[op.mat + 4 + e];
+                    }
                 for (int j = 0; j < g.k; ++j) op.tpos[j] = tile_bit(g.locs[j]);
                 op.rpos = 0;
                 if (!hg.lds) {
-                    for (int j = 0; j < kRegBits; ++j)
+                    for (int j = 0; j < P.reg_bits; ++j)
                         if (gd.rpos[j] == op.tpos[0]) op.rpos = j;
                 }
                 for (int m = 0; m < g.nctrl; ++m) {
@@ -157,6 +179,7 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     }
                 }
                 prog.ops.push_back(op);
+                prog.pass_flops.back() += op_flops(op, bwd) / double(uint64_t(1) << g.nctrl);
             }
             prog.groups.push_back(gd);
         }
@@ -190,12 +213,10 @@ int upload_program(const Program& prog, DevProgram& d)
 
 }  // namespace
 
-int forward_fused(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params)
+namespace {
+
+int run_forward_plan(const Plan& P, void* data, int dtype, int n, int B, const yao_circuit* c, const double* params)
 {
-    if (c->gates.empty()) return 0;
-    int t, cb, L;
-    tile_geometry(n, B, dtype, false, &t, &cb, &L);
-    const Plan& P = get_plan(c, B, t, cb, L, false);
     Program prog;
     YAO_TRY(build_program(P, c, params, false, prog));
     DevProgram d;
@@ -209,42 +230,22 @@ int forward_fused(void* data, int dtype, int n, int B, const yao_circuit* c, con
             YAO_TRY(launch_gate(data, dtype, n, B, U, g.locs, make_ctrl(g.nctrl, g.ctrls, g.cvals)));
             continue;
         }
-        YAO_TRY(launch_pass(false, dtype, dtype, data, nullptr, d.ops, d.groups, d.mats, nullptr, 0, n, B, cb, t,
-                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits));
+        YAO_TRY(launch_pass(false, dtype, dtype, data, nullptr, d.ops, d.groups, d.mats, nullptr, 0, n, B, P.c, P.t,
+                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits,
+                            prog.pass_flops[p] * (double)(uint64_t(1) << n) * B));
     }
     return 0;
 }
 
-int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h, int mode,
-                   bool reduce_batch, double* energy, double* grad, double* drift)
+// Reverse sweep over the gates of one plan: gradient partials into gpartial (row stride W).
+int run_backward_plan(const Plan& P, const yao_circuit* c, const double* params, double* psi, void* lam,
+                      int lam_dtype, int n, int B, double* gpartial, int W, std::vector<int>* slot_of_gate)
 {
-    (void)mode;
-    const int n = s->n, B = s->batch;
-    const size_t elems = s->elems();
-    hipStream_t st = stream();
-    void* psi0 = workspace(WS_PSI0, s->bytes());
-    if (!psi0) return YAO_ENOMEM;
-    YAO_HIP(hipMemcpyAsync(psi0, s->data, s->bytes(), hipMemcpyDeviceToDevice, st));
-    YAO_TRY(forward_fused(s->data, s->dtype, n, B, c, params));
-    double* psi = (double*)workspace(WS_PSI64, elems * 16);
-    void* lam = workspace(WS_LAM, s->bytes());
-    if (!psi || !lam) return YAO_ENOMEM;
-    YAO_TRY(launch_convert(s->data, s->dtype, psi, YAO_C128, elems));
-    YAO_TRY(launch_hpsi(s->data, s->dtype, lam, s->dtype, n, B, h, energy));
-
-    int t, cb, L;
-    tile_geometry(n, B, s->dtype, true, &t, &cb, &L);
-    const Plan& P = get_plan(c, B, t, cb, L, true);
     Program prog;
     YAO_TRY(build_program(P, c, params, true, prog));
     DevProgram d;
     YAO_TRY(upload_program(prog, d));
-    const int ntiles = 1 << (n - (t - cb));
-    const int W = std::max(ntiles, adjoint_nblk(n, 1, B));
-    const int nslots = prog.nslots;
-    double* gpartial = (double*)workspace(WS_PARTIAL, sizeof(double) * (size_t)std::max(1, nslots) * B * W);
-    if (!gpartial) return YAO_ENOMEM;
-    if (nslots) YAO_TRY(launch_fill(gpartial, (size_t)nslots * B * W, 0.0));
+    if (slot_of_gate) *slot_of_gate = prog.slot_of_gate;
     for (size_t p = 0; p < P.passes.size(); ++p) {
         const HostPass& pass = P.passes[p];
         if (pass.standalone >= 0) {
@@ -256,13 +257,104 @@ int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao
             HostMat Ud = dagger(U);
             const int slot = prog.slot_of_gate[gi];
             if (slot >= 0) gate_grad_matrix(g, th, M);
-            YAO_TRY(launch_adjoint_step_strided(psi, lam, s->dtype, n, B, Ud, slot >= 0 ? &M : nullptr, g.locs,
+            YAO_TRY(launch_adjoint_step_strided(psi, lam, lam_dtype, n, B, Ud, slot >= 0 ? &M : nullptr, g.locs,
                                                 make_ctrl(g.nctrl, g.ctrls, g.cvals),
                                                 slot >= 0 ? gpartial + (size_t)slot * B * W : nullptr, W));
             continue;
         }
-        YAO_TRY(launch_pass(true, YAO_C128, s->dtype, psi, lam, d.ops, d.groups, d.mats, gpartial, W, n, B, cb, t,
-                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits));
+        YAO_TRY(launch_pass(true, YAO_C128, lam_dtype, psi, lam, d.ops, d.groups, d.mats, gpartial, W, n, B, P.c, P.t,
+                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits,
+                            prog.pass_flops[p] * (double)(uint64_t(1) << n) * B));
+    }
+    return 0;
+}
+
+int count_slots(const yao_circuit* c)
+{
+    int k = 0;
+    for (const GateRec& g : c->gates) k += (is_param_kind(g.kind) && g.param >= 0) ? 1 : 0;
+    return k;
+}
+
+}  // namespace
+
+int forward_fused_range(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params, int g0, int g1)
+{
+    if (g1 <= g0) return 0;
+    int t, cb, L;
+    tile_geometry(n, B, dtype, false, &t, &cb, &L);
+    return run_forward_plan(get_plan(c, g0, g1, B, t, cb, L, false), data, dtype, n, B, c, params);
+}
+
+int forward_fused(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params)
+{
+    return forward_fused_range(data, dtype, n, B, c, params, 0, (int)c->gates.size());
+}
+
+int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h, int mode,
+                   bool reduce_batch, double* energy, double* grad, double* drift)
+{
+    const int n = s->n, B = s->batch;
+    const size_t elems = s->elems();
+    const int G = (int)c->gates.size();
+    hipStream_t st = stream();
+    const double tol = options().drift_tol > 0 ? options().drift_tol : (s->dtype == YAO_C64 ? 1e-5 : 1e-10);
+
+    // Segments: the reversible sweep runs the circuit as one plan; the checkpointed modes cut
+    // it into gate ranges whose end states the forward keeps.
+    std::vector<int> cuts{0};
+    if (mode != YAO_GRAD_REVERSIBLE && G > 0) {
+        int len = options().checkpoint_every;
+        if (len <= 0) len = std::max((int)std::ceil(std::sqrt((double)G)), 4 * n);
+        for (int g = len; g < G; g += len) cuts.push_back(g);
+    }
+    cuts.push_back(G);
+    const int nseg = (int)cuts.size() - 1;
+
+    void* psi0 = workspace(WS_PSI0, s->bytes());
+    if (!psi0) return YAO_ENOMEM;
+    YAO_HIP(hipMemcpyAsync(psi0, s->data, s->bytes(), hipMemcpyDeviceToDevice, st));
+    char* ckpt = nullptr;
+    if (nseg > 1) {
+        ckpt = (char*)workspace(WS_CKPT, s->bytes() * (size_t)(nseg - 1));
+        if (!ckpt) return YAO_ENOMEM;
+    }
+    for (int sg = 0; sg < nseg; ++sg) {
+        YAO_TRY(forward_fused_range(s->data, s->dtype, n, B, c, params, cuts[sg], cuts[sg + 1]));
+        if (sg + 1 < nseg)
+            YAO_HIP(hipMemcpyAsync(ckpt + s->bytes() * sg, s->data, s->bytes(), hipMemcpyDeviceToDevice, st));
+    }
+    double* psi = (double*)workspace(WS_PSI64, elems * 16);
+    void* lam = workspace(WS_LAM, s->bytes());
+    if (!psi || !lam) return YAO_ENOMEM;
+    YAO_TRY(launch_convert(s->data, s->dtype, psi, YAO_C128, elems));
+    YAO_TRY(launch_hpsi(s->data, s->dtype, lam, s->dtype, n, B, h, energy));
+
+    int t, cb, L;
+    tile_geometry(n, B, s->dtype, true, &t, &cb, &L);
+    const int ntiles = 1 << (n - (t - cb));
+    const int W = std::max(ntiles, adjoint_nblk(n, 1, B));
+    const int nslots = count_slots(c);
+    double* gpartial = (double*)workspace(WS_PARTIAL, sizeof(double) * (size_t)std::max(1, nslots) * B * W);
+    if (!gpartial) return YAO_ENOMEM;
+    if (nslots) YAO_TRY(launch_fill(gpartial, (size_t)nslots * B * W, 0.0));
+    std::vector<int> slot_of_gate;
+    double worst = 0;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        if (sg + 1 < nseg) {
+            // psi now stands at the end of segment sg, where the forward kept a copy.
+            const void* ref = ckpt + s->bytes() * sg;
+            bool resync = mode == YAO_GRAD_CHECKPOINT;
+            if (mode == YAO_GRAD_AUTO) {
+                double dv = 0;
+                YAO_TRY(launch_maxdiff(psi, YAO_C128, ref, s->dtype, elems, &dv));
+                worst = std::max(worst, dv);
+                resync = dv > tol;
+            }
+            if (resync) YAO_TRY(launch_convert(ref, s->dtype, psi, YAO_C128, elems));
+        }
+        const Plan& P = get_plan(c, cuts[sg], cuts[sg + 1], B, t, cb, L, true);
+        YAO_TRY(run_backward_plan(P, c, params, psi, lam, s->dtype, n, B, gpartial, W, &slot_of_gate));
     }
     const int P_ = c->nparams;
     const size_t glen = reduce_batch ? (size_t)P_ : (size_t)P_ * B;
@@ -275,8 +367,8 @@ int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao
         if (!hs) return YAO_ENOMEM;
         YAO_HIP(hipMemcpyAsync(hs, sums, sizeof(double) * (size_t)nslots * B, hipMemcpyDeviceToHost, st));
         YAO_HIP(hipStreamSynchronize(st));
-        for (int gi = (int)c->gates.size() - 1; gi >= 0; --gi) {
-            const int slot = prog.slot_of_gate[gi];
+        for (int gi = G - 1; gi >= 0; --gi) {
+            const int slot = slot_of_gate.empty() ? -1 : slot_of_gate[gi];
             if (slot < 0) continue;
             const int p = c->gates[gi].param;
             for (int b = 0; b < B; ++b) {
@@ -286,8 +378,12 @@ int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao
             }
         }
     }
-    if (drift) YAO_TRY(launch_maxdiff(psi, YAO_C128, psi0, s->dtype, elems, drift));
-    else YAO_HIP(hipStreamSynchronize(st));
+    double dend = 0;
+    YAO_TRY(launch_maxdiff(psi, YAO_C128, psi0, s->dtype, elems, &dend));
+    if (drift) *drift = std::max(dend, worst);
+    if (mode == YAO_GRAD_REVERSIBLE && options().drift_tol > 0 && dend > options().drift_tol)
+        return set_error(YAO_EDRIFT, "uncomputed input differs from the input by %.3g > %.3g", dend,
+                         options().drift_tol);
     return 0;
 }
 

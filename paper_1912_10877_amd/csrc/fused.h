@@ -1,6 +1,6 @@
 // Fused tile passes: a pass loads a tile of 2^t elements (c batch bits and t-c chosen
 // qubits) into LDS, applies every gate whose targets lie in the tile -- in register groups of
-// kRegBits tile bits per thread -- and writes the tile back. Controls outside the tile are
+// 3 or 4 tile bits per thread -- and writes the tile back. Controls outside the tile are
 // constant over a tile and become a per-tile predicate.
 #pragma once
 
@@ -8,41 +8,44 @@
 
 namespace yao {
 
-constexpr int kRegBits = 4;       // register bits per group: 16 elements per thread
+constexpr int kRegBitsFwd = 4;    // register bits per group in the forward: 16 elements per thread
+constexpr int kRegBitsBwd = 3;    // backward: 8 elements of psi and 8 of lambda per thread
+constexpr int kMaxRegBits = 4;
 constexpr int kMaxTileBits = 13;  // 2^13 complex64 = 64 KiB of LDS
 constexpr int kMaxFusedK = 3;     // wider gates run as standalone launches between passes
-constexpr int kMaxGroupSlots = 16;  // gradient-carrying gates per register group
+constexpr int kMaxGroupSlots = 12;  // gradient-carrying gates per register group
 
 // Structure classes of a one-qubit matrix inside a pass.
 enum OpType : int {
     OT_SWAP = 0,   // X
-    OT_ANTI = 1,   // [[0, a], [b, 0]]
-    OT_DIAG1 = 2,  // diag(1, d)
-    OT_DIAG = 3,   // diag(d0, d1)
-    OT_REAL = 4,   // every entry real (Ry, H)
-    OT_RX = 5,     // [[c, -i s], [-i s, c]] with c, s real
-    OT_DENSE = 6,
-    OT_LDSK = 7    // k = 2 or 3 dense matrix applied in LDS
+    OT_DIAG = 1,   // diag(d0, d1)
+    OT_REAL = 2,   // every entry real (Ry, H)
+    OT_RX = 3,     // [[c, -i s], [-i s, c]] with c, s real
+    OT_DENSE = 4,
+    OT_LDSK = 5    // k = 2 or 3 dense matrix applied in LDS
 };
 
 // Gradient generators: M = (dU/dtheta) U^dagger restricted to the op's subspace.
 enum GenType : int { GEN_NONE = 0, GEN_X = 1, GEN_Y = 2, GEN_Z = 3, GEN_P1 = 4, GEN_DENSE = 5 };
 
-// Device op record (one gate inside a pass).
+// Device op record (one gate inside a pass), 128 bytes: everything a one-qubit op needs comes
+// in one scalar fetch, so the next op's record can be fetched while the current one computes.
 struct POp {
     int type;       // OpType
     int k;
     int gen;        // GenType (backward only)
+    int rpos;       // register position (0..register bits - 1) of a one-qubit target
     int slot;       // gradient slot (-1 none)
     int mat;        // offset in doubles into the matrix pool: U (re, im) then M (re, im)
-    int tpos[3];    // tile-bit positions of the targets, in locs order
-    int rpos;       // register position (0..kRegBits-1) of a one-qubit target
     uint32_t cmask, cval;  // controls on tile bits
     uint64_t omask, oval;  // controls on qubits outside the tile
+    double u[8];    // one-qubit matrix (forward U, backward U^dagger): re[4] then im[4]
+    int tpos[4];    // tile-bit positions of the targets, in locs order
 };
+static_assert(sizeof(POp) == 128, "op record layout");
 
 struct PGroupDesc {
-    int rpos[kRegBits];  // tile-bit positions of the register bits, ascending
+    int rpos[kMaxRegBits];  // tile-bit positions of the register bits, ascending
     int lds;             // 1: a single OT_LDSK op applied in LDS
     int op0, nops;
     int nslot;           // ops with a gradient in this group
@@ -72,18 +75,25 @@ struct HostPass {
 };
 struct Plan {
     int n = 0, B = 1, c = 0, t = 0;
+    int reg_bits = kRegBitsFwd;
+    int g0 = 0, g1 = 0;  // gate range
     bool reverse = false;
     std::vector<HostOp> ops;        // in application order (reverse order of gates if reverse)
     std::vector<HostPass> passes;
 };
 
-// Build the pass structure; gates are taken in circuit order, or reversed for the backward.
-Plan make_plan(const yao_circuit* c, int B, int t, int cbits, int low_fixed, bool reverse);
+// Build the pass structure of gates [g0, g1); taken in circuit order, or reversed for the
+// backward.
+Plan make_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cbits, int low_fixed, bool reverse,
+               int reg_bits);
 // Choose tile geometry for a state.
 void tile_geometry(int n, int B, int dtype, bool backward, int* t, int* cbits, int* low_fixed);
 
 // Drivers.
 int forward_fused(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params);
+// Gates [g0, g1) only.
+int forward_fused_range(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params, int g0,
+                        int g1);
 int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h, int mode,
                    bool reduce_batch, double* energy, double* grad, double* drift);
 // Tiles need more qubits than register bits.

@@ -196,22 +196,34 @@ __global__ __launch_bounds__(kThreads) void k_hpsi(const vec2_t<R>* __restrict__
     if (b < B) {
         for (uint64_t j = (uint64_t)blockIdx.x * rpb + (threadIdx.x >> logBc); j < rows; j += (uint64_t)gridDim.x * rpb) {
             double orr = 0, oi = 0;
-            for (int g = 0; g < ngroups; ++g) {
-                uint64_t x = groups[g].x;
-                uint64_t src = j ^ x;
-                vec2_t<R> p = psi[src * B + b];
-                double cr = 0, ci = 0;  // sum of c_t i^{ny} (-1)^{|src & z|}
-                for (int t = groups[g].t0; t < groups[g].t1; ++t) {
-                    double c = (__popcll(src & terms[t].z) & 1) ? -terms[t].c : terms[t].c;
-                    switch (terms[t].ny & 3) {
-                    case 0: cr += c; break;
-                    case 1: ci += c; break;
-                    case 2: cr -= c; break;
-                    default: ci -= c; break;
+            // Partner amplitudes of 8 X-mask groups are fetched together, then combined.
+            for (int g0 = 0; g0 < ngroups; g0 += 8) {
+                vec2_t<R> p[8];
+                uint64_t src[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    src[u] = j;
+                    if (g0 + u < ngroups) {
+                        src[u] = j ^ groups[g0 + u].x;
+                        p[u] = psi[src[u] * B + b];
                     }
                 }
-                orr += cr * p.x - ci * p.y;
-                oi += cr * p.y + ci * p.x;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (g0 + u >= ngroups) break;
+                    double cr = 0, ci = 0;  // sum of c_t i^{ny} (-1)^{|src & z|}
+                    for (int t = groups[g0 + u].t0; t < groups[g0 + u].t1; ++t) {
+                        double c = (__popcll(src[u] & terms[t].z) & 1) ? -terms[t].c : terms[t].c;
+                        switch (terms[t].ny & 3) {
+                        case 0: cr += c; break;
+                        case 1: ci += c; break;
+                        case 2: cr -= c; break;
+                        default: ci -= c; break;
+                        }
+                    }
+                    orr += cr * p[u].x - ci * p[u].y;
+                    oi += cr * p[u].y + ci * p[u].x;
+                }
             }
             vec2_t<R> a = psi[j * B + b];
             acc += (double)a.x * orr + (double)a.y * oi;
@@ -225,13 +237,18 @@ __global__ __launch_bounds__(kThreads) void k_hpsi(const vec2_t<R>* __restrict__
     if ((int)threadIdx.x < (1 << logBc) && b < B) partial[(uint64_t)b * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ void k_row_sums(const double* __restrict__ partial, int rows, int nblk, double* __restrict__ sums)
+// sums[r] = sum_j partial[r * nblk + j]: one wave per row, lane-strided sums and then a fixed
+// butterfly, so the order (and the result) is the same on every run.
+__global__ __launch_bounds__(256) void k_row_sums(const double* __restrict__ partial, int rows, int nblk,
+                                                  double* __restrict__ sums)
 {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= rows) return;
     double s = 0;
-    for (int j = 0; j < nblk; ++j) s += partial[(uint64_t)r * nblk + j];
-    sums[r] = s;
+    for (int j = lane; j < nblk; j += 64) s += partial[(uint64_t)r * nblk + j];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) sums[r] = s;
 }
 
 template <typename RA, typename RB>
@@ -386,12 +403,16 @@ int gate_typed(void* data, int n, int B, const HostMat& U, const int* locs, Ctrl
             m.re[t] = (R)U.re[t];
             m.im[t] = (R)U.im[t];
         }
-        switch (classify(U)) {
+        const double elems = (double)(uint64_t(1) << n) * B / double(uint64_t(1) << __builtin_popcountll(c.mask));
+        const int cls = classify(U);
+        const int pi = prof_begin(YAO_KF_GATE);
+        switch (cls) {
         case MC_DIAG1: k_gate1<R, MC_DIAG1><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, locs[0], logBp, B, c.mask, c.val, m); break;
         case MC_DIAG: k_gate1<R, MC_DIAG><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, locs[0], logBp, B, c.mask, c.val, m); break;
         case MC_ANTI: k_gate1<R, MC_ANTI><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, locs[0], logBp, B, c.mask, c.val, m); break;
         default: k_gate1<R, MC_DENSE><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, locs[0], logBp, B, c.mask, c.val, m); break;
         }
+        prof_end(pi, (cls == MC_DIAG1 ? 1.0 : 2.0) * elems * sizeof(V), (cls == MC_DIAG1 ? 3.0 : cls == MC_DENSE ? 14.0 : 6.0) * elems);
         YAO_HIP(hipGetLastError());
         return 0;
     }
@@ -407,6 +428,8 @@ int gate_typed(void* data, int n, int B, const HostMat& U, const int* locs, Ctrl
         dm = (const R*)ring_upload(h.data(), h.size() * sizeof(R));
         if (!dm) return YAO_ENOMEM;
     }
+    const double elems = (double)(uint64_t(1) << n) * B / double(uint64_t(1) << __builtin_popcountll(c.mask));
+    const int pi = prof_begin(YAO_KF_GATE);
     switch (k) {
     case 2: k_gatek<R, 2><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, logBp, B, make_group_geom<2>(locs), c.mask, c.val, dm, dm + dd); break;
     case 3: k_gatek<R, 3><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, logBp, B, make_group_geom<3>(locs), c.mask, c.val, dm, dm + dd); break;
@@ -414,6 +437,7 @@ int gate_typed(void* data, int n, int B, const HostMat& U, const int* locs, Ctrl
     case 5: k_gatek<R, 5><<<grid1(nwork), kThreads, 0, st>>>(psi, nwork, logBp, B, make_group_geom<5>(locs), c.mask, c.val, dm, dm + dd); break;
     default: return set_error(YAO_EINVAL, "k = %d not supported", k);
     }
+    prof_end(pi, 2.0 * elems * sizeof(V), (8.0 * (1 << k) - 2.0) * elems);
     YAO_HIP(hipGetLastError());
     return 0;
 }
@@ -455,7 +479,7 @@ int launch_gate(void* data, int dtype, int n, int B, const HostMat& U, const int
 
 int launch_row_sums(const double* partial, int rows, int nblk, double* sums)
 {
-    k_row_sums<<<(rows + 255) / 256, 256, 0, stream()>>>(partial, rows, nblk, sums);
+    k_row_sums<<<(rows + 3) / 4, 256, 0, stream()>>>(partial, rows, nblk, sums);
     YAO_HIP(hipGetLastError());
     return 0;
 }
@@ -525,12 +549,14 @@ int launch_expect(const void* data, int dtype, int n, int B, yao_pauli_sum* h, d
     double* partial = (double*)workspace(WS_PARTIAL, sizeof(double) * (size_t)B * nbx);
     if (!partial) return YAO_ENOMEM;
     dim3 grid(nbx, bg.nchunks);
+    const int pi = prof_begin(YAO_KF_EXPECT);
     if (dtype == YAO_C64)
         k_expect<float><<<grid, kThreads, 0, stream()>>>((const float2*)data, rows, B, bg.logBc, (const PGroup*)h->d_groups,
                                                          h->ngroups, (const PTerm*)h->d_terms, partial);
     else
         k_expect<double><<<grid, kThreads, 0, stream()>>>((const double2*)data, rows, B, bg.logBc, (const PGroup*)h->d_groups,
                                                           h->ngroups, (const PTerm*)h->d_terms, partial);
+    prof_end(pi, (double)rows * B * (dtype == YAO_C64 ? 8 : 16), (double)rows * B * 4.0 * h->nterms_dev);
     YAO_HIP(hipGetLastError());
     return finish_slot_sums(partial, B, nbx, energy_host);
 }
@@ -548,6 +574,7 @@ int launch_hpsi(const void* data, int dtype, void* out, int out_dtype, int n, in
     const PGroup* G = (const PGroup*)h->d_groups;
     const PTerm* T = (const PTerm*)h->d_terms;
     hipStream_t st = stream();
+    const int pi = prof_begin(YAO_KF_HPSI);
     if (dtype == YAO_C64 && out_dtype == YAO_C64)
         k_hpsi<float, float><<<grid, kThreads, 0, st>>>((const float2*)data, (float2*)out, rows, B, bg.logBc, G, h->ngroups, T, partial);
     else if (dtype == YAO_C64)
@@ -556,6 +583,7 @@ int launch_hpsi(const void* data, int dtype, void* out, int out_dtype, int n, in
         k_hpsi<double, float><<<grid, kThreads, 0, st>>>((const double2*)data, (float2*)out, rows, B, bg.logBc, G, h->ngroups, T, partial);
     else
         k_hpsi<double, double><<<grid, kThreads, 0, st>>>((const double2*)data, (double2*)out, rows, B, bg.logBc, G, h->ngroups, T, partial);
+    prof_end(pi, (double)rows * B * ((dtype == YAO_C64 ? 8 : 16) + (out_dtype == YAO_C64 ? 8 : 16)), (double)rows * B * 6.0 * h->nterms_dev);
     YAO_HIP(hipGetLastError());
     if (!energy_host) return 0;
     return finish_slot_sums(partial, B, nbx, energy_host);
@@ -617,12 +645,15 @@ static int adjoint_k(double* psi, void* lam, int n, int B, const int* locs, Ctrl
     int nbx = reduce_grid_x(rows, bg.logBc);
     dim3 grid(nbx, bg.nchunks);
     GroupGeom<K> gg = make_group_geom<K>(locs);
+    const double elems = (double)(uint64_t(1) << n) * B / double(uint64_t(1) << __builtin_popcountll(c.mask));
+    const int pi = prof_begin(YAO_KF_ADJOINT);
     if (grad)
         k_adjoint<RL, K, true><<<grid, kThreads, 0, stream()>>>((double2*)psi, (vec2_t<RL>*)lam, rows, B, bg.logBc, gg,
                                                                  c.mask, c.val, m1, dm, partial, pstride > 0 ? pstride : nbx);
     else
         k_adjoint<RL, K, false><<<grid, kThreads, 0, stream()>>>((double2*)psi, (vec2_t<RL>*)lam, rows, B, bg.logBc, gg,
                                                                   c.mask, c.val, m1, dm, partial, nbx);
+    prof_end(pi, 2.0 * elems * (16 + sizeof(vec2_t<RL>)), ((grad ? 8.0 : 0.0) + 2.0 * (8.0 * (1 << K) - 2.0)) * elems);
     YAO_HIP(hipGetLastError());
     return 0;
 }

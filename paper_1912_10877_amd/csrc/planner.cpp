@@ -3,7 +3,7 @@
 // Gates are taken in order. A gate may join the pass being formed when its targets fit in the
 // tile and it shares no qubit (target or control) with a gate that was deferred earlier in
 // this scan -- so moving it ahead of those gates cannot change the result, since operators
-// on disjoint qubits commute. The same rule, with kRegBits register bits in place of the
+// on disjoint qubits commute. The same rule, with 3 or 4 register bits in place of the
 // tile, splits a pass into register groups.
 #include <algorithm>
 
@@ -22,9 +22,11 @@ void tile_geometry(int n, int B, int dtype, bool backward, int* t, int* cbits, i
     const int c = lb < 3 ? lb : 3;
     int tq = options().tile_qubits;
     if (tq <= 0) tq = 12 - c;
-    if (tq < kRegBits + 1) tq = kRegBits + 1;
+    if (tq < kMaxRegBits + 1) tq = kMaxRegBits + 1;
     int tt = c + std::min(tq, n);
-    const int tmax = backward ? 12 : (dtype == YAO_C64 ? 13 : 12);
+    // LDS per tile element: forward 8 or 16 bytes; backward 16 (psi) + 8 or 16 (lambda), plus
+    // the gradient partials, within 160 KiB.
+    const int tmax = backward ? (dtype == YAO_C64 ? 12 : 11) : (dtype == YAO_C64 ? 13 : 12);
     if (tt > tmax) tt = tmax;
     *t = tt;
     *cbits = c;
@@ -37,20 +39,23 @@ void tile_geometry(int n, int B, int dtype, bool backward, int* t, int* cbits, i
 bool fused_supported(int n, int B)
 {
     (void)B;
-    return n >= kRegBits + 1;
+    return n >= kMaxRegBits + 1;
 }
 
-Plan make_plan(const yao_circuit* circ, int B, int t, int cbits, int low_fixed, bool reverse)
+Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits, int low_fixed, bool reverse,
+               int reg_bits)
 {
     Plan P;
+    P.reg_bits = reg_bits;
+    P.g0 = g0;
+    P.g1 = g1;
     P.n = circ->n;
     P.B = B;
     P.c = cbits;
     P.t = t;
     P.reverse = reverse;
-    const int G = (int)circ->gates.size();
-    for (int e = 0; e < G; ++e) {
-        const int gi = reverse ? G - 1 - e : e;
+    for (int e = g0; e < g1; ++e) {
+        const int gi = reverse ? g1 - 1 - (e - g0) : e;
         const GateRec& g = circ->gates[gi];
         HostOp op;
         op.gate = gi;
@@ -136,7 +141,7 @@ Plan make_plan(const yao_circuit* circ, int B, int t, int cbits, int low_fixed, 
                     grest.push_back(oi);
                     continue;
                 }
-                if (popc(R | rb) <= kRegBits) {
+                if (popc(R | rb) <= reg_bits) {
                     R |= rb;
                     gsel.push_back(oi);
                     nslot += grad ? 1 : 0;
@@ -147,7 +152,7 @@ Plan make_plan(const yao_circuit* circ, int B, int t, int cbits, int low_fixed, 
             }
             // Fill the register bits with the highest unused tile bits, which keeps the thread
             // bits on the low (contiguous) end of the tile.
-            for (int b = t - 1; b >= cbits && popc(R) < kRegBits; --b) R |= uint64_t(1) << b;
+            for (int b = t - 1; b >= cbits && popc(R) < reg_bits; --b) R |= uint64_t(1) << b;
             grp.rbits = R;
             grp.ops = gsel;
             pass.groups.push_back(grp);

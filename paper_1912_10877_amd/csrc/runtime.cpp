@@ -307,4 +307,74 @@ CtrlSpec make_ctrl(int nctrl, const int* ctrls, const int* cvals)
     return c;
 }
 
+// ---------------------------------------------------------------------------------- profiler
+namespace {
+struct ProfRec {
+    int family;
+    int ev;  // index of the start event; the end event is ev + 1
+    double bytes, flops;
+};
+bool g_prof_on = false;
+std::vector<hipEvent_t> g_prof_events;
+std::vector<ProfRec> g_prof_recs;
+size_t g_prof_next_ev = 0;
+}  // namespace
+
+int prof_enable(bool on)
+{
+    g_prof_on = on;
+    if (on) {
+        g_prof_recs.clear();
+        g_prof_next_ev = 0;
+    }
+    return 0;
+}
+
+int prof_begin(int family)
+{
+    if (!g_prof_on) return -1;
+    if (g_prof_next_ev + 2 > g_prof_events.size()) {
+        for (int i = 0; i < 256; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            g_prof_events.push_back(e);
+        }
+    }
+    const int ev = (int)g_prof_next_ev;
+    g_prof_next_ev += 2;
+    if (hipEventRecord(g_prof_events[ev], g_stream) != hipSuccess) return -1;
+    g_prof_recs.push_back(ProfRec{family, ev, 0.0, 0.0});
+    return (int)g_prof_recs.size() - 1;
+}
+
+void prof_end(int idx, double bytes, double flops)
+{
+    if (idx < 0 || idx >= (int)g_prof_recs.size()) return;
+    ProfRec& r = g_prof_recs[idx];
+    (void)hipEventRecord(g_prof_events[r.ev + 1], g_stream);
+    r.bytes = bytes;
+    r.flops = flops;
+}
+
+int prof_read(int family, int* launches, double* total_ms, double* bytes, double* flops)
+{
+    int n = 0;
+    double ms = 0, by = 0, fl = 0;
+    for (const ProfRec& r : g_prof_recs) {
+        if (r.family != family) continue;
+        YAO_HIP(hipEventSynchronize(g_prof_events[r.ev + 1]));
+        float t = 0;
+        YAO_HIP(hipEventElapsedTime(&t, g_prof_events[r.ev], g_prof_events[r.ev + 1]));
+        ++n;
+        ms += t;
+        by += r.bytes;
+        fl += r.flops;
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms;
+    if (bytes) *bytes = by;
+    if (flops) *flops = fl;
+    return 0;
+}
+
 }  // namespace yao

@@ -111,4 +111,12 @@ int launch_row_sums(const double* partial, int rows, int nblk, double* sums);
 // Pauli tables
 int pauli_upload(yao_pauli_sum* h);
 
+// ---------------------------------------------------------------------------- profiler
+// prof_begin records a start event for a launch of `family` when profiling is on (returns
+// -1 otherwise); prof_end records the matching end event and credits bytes / flops.
+int prof_begin(int family);
+void prof_end(int idx, double bytes, double flops);
+int prof_enable(bool on);
+int prof_read(int family, int* launches, double* total_ms, double* bytes, double* flops);
+
 }  // namespace yao
