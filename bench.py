@@ -43,7 +43,61 @@ def parse():
     p.add_argument("--cpu-depth", type=int, default=6, help="depth of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-profile", action="store_true")
+    p.add_argument("--batch-circuits", type=int, default=1024,
+                   help="circuits of the uneven batch measured beside the main step (0: skip)")
+    p.add_argument("--batch-steps", type=int, default=5)
     return p.parse_args()
+
+
+def bench_uneven_batch(yb, w, torch, ncirc, steps):
+    """Replays of the graph-recorded uneven batch (qubits 8..20, depth 4..16, complex64) against
+    the same circuits run one by one through the per-gate form and through the fused form."""
+    import numpy as np
+
+    spec = w.hetero_batch_spec(ncirc)
+    states, circs, hams, params = [], [], [], []
+    for n, d, seed in spec:
+        c = w.hea_circuit(n, d)
+        states.append(yb.State(n, 1, yb.C64))
+        circs.append(yb.Circuit.from_workload(c))
+        hams.append(yb.PauliSum.from_workload(w.heisenberg(n)))
+        params.append(w.angles(seed, c.nparams))
+    gates = sum(3 * n * d + (n - 1) * d for n, d, _ in spec)
+    au = sum(3.0 * (3 * n * d + (n - 1) * d) * (1 << n) for n, d, _ in spec)
+    t0 = time.perf_counter()
+    yb.batch_run(states, circs, params, hams)  # autotune + record
+    torch.cuda.synchronize()
+    t_record = time.perf_counter() - t0
+    yb.batch_run(states, circs, params, hams)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e, g = yb.batch_run(states, circs, params, hams)
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - t0) * 1e3 / steps
+
+    def loop():
+        for i in range(ncirc):
+            states[i].reset()
+            yb.backward(states[i], circs[i], params[i], hams[i])
+        torch.cuda.synchronize()
+
+    loop()
+    t0 = time.perf_counter()
+    loop()
+    fused_loop_ms = (time.perf_counter() - t0) * 1e3
+    yb.set_options(plain=1)
+    t0 = time.perf_counter()
+    loop()
+    plain_ms = (time.perf_counter() - t0) * 1e3
+    yb.set_options(plain=0)
+    return {"workload": f"{ncirc} circuits, qubits uniform 8..20, depth uniform 4..16, Rx.Rz.Rx + CNOT-chain "
+                        "ansatz, periodic Heisenberg energy + all gradients per circuit, complex64",
+            "circuits": ncirc, "gates": gates, "ms_per_batch": batch_ms,
+            "amplitude_updates_per_s": au / (batch_ms / 1e3), "record_s": t_record,
+            "fused_loop_ms": fused_loop_ms, "plain_loop_ms": plain_ms,
+            "speedup_vs_plain": plain_ms / batch_ms, "speedup_vs_fused_loop": fused_loop_ms / batch_ms,
+            "energy_sum": float(np.sum(e))}
 
 
 def main():
@@ -133,6 +187,10 @@ def main():
                          "achieved_tflops": round(tfl, 3),
                          "gpu_ms_by_family": {FAMILIES[f]: round(prof[f][1] / args.steps, 4) for f in prof}})
 
+    batch = None
+    if args.batch_circuits > 0:
+        batch = bench_uneven_batch(yb, w, torch, args.batch_circuits, args.batch_steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -158,7 +216,7 @@ def main():
         "energy": float(e[0]), "drift": drift,
         "plain_ms_per_step": plain_ms,
         "speedup_vs_plain": (plain_ms / ms_step) if plain_ms else None,
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "uneven_batch": batch,
     }
     print(json.dumps(out))
 

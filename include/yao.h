@@ -86,7 +86,10 @@ enum yao_grad_mode { YAO_GRAD_REVERSIBLE = 0, YAO_GRAD_CHECKPOINT = 1, YAO_GRAD_
  *                    uncomputed input differs from the input by more than drift_tol (the
  *                    outputs are still written).
  *   mfma             1: dense blocks of 4 or 5 qubits on complex64 states run on FP32
- *                    matrix cores; 0: on the vector units. */
+ *                    matrix cores; 0: on the vector units.
+ *   autotune         1: yao_batch_run picks, per qubit count, the fusion width (1..5) of the
+ *                    forward sweep and the tile qubits of both sweeps by timing candidates
+ *                    when it first sees a batch; 0: it takes fuse_width and tile_qubits. */
 typedef struct {
     int plain;
     int tile_qubits;
@@ -94,6 +97,7 @@ typedef struct {
     int checkpoint_every;
     double drift_tol;
     int mfma;
+    int autotune;
 } yao_options;
 
 /* Library ------------------------------------------------------------------------------ */
@@ -149,6 +153,11 @@ int yao_expect(const yao_state* s, const yao_pauli_sum* h, double* energy);
  * energy[b] = Re <psi_b|H psi_b> from the same pass. out must match s in n, batch, dtype. */
 int yao_hpsi(const yao_state* s, const yao_pauli_sum* h, yao_state* out, double* energy);
 
+/* re[b] + i im[b] = <a_b|b_b> for every batch slot, accumulated in FP64 (the overlap behind
+ * the fidelity |<a|b>|^2 of App. "Gate Learning"). a and b must have equal n and batch; their
+ * dtypes may differ. Synchronises. */
+int yao_inner(const yao_state* a, const yao_state* b, double* re, double* im);
+
 /* Circuits ---------------------------------------------------------------------------- */
 
 int yao_circuit_create(int n, yao_circuit** out);
@@ -176,8 +185,13 @@ int yao_backward(yao_state* s, const yao_circuit* c, const double* params, const
 
 /* Energy and gradient of ncirc independent circuits, each on its own single-slot state
  * (n may differ between circuits) starting from |0...0>; energy[c] and grad[c] (length
- * nparams of circuit c) are host arrays. All circuits run in one persistent launch
- * replayed from a HIP graph; states[c] ends holding circuit c's output. Synchronises. */
+ * nparams of circuit c) are host arrays. Every state must have batch 1, at least 5 qubits
+ * and the dtype of states[0]. The first call with a given list of circuits, states and
+ * observables records the whole batch (resets, forward sweeps, H psi, reverse sweeps and
+ * gradient sums of every circuit, spread over several streams) into one HIP graph; calls
+ * with the same lists upload the new parameters in one copy and replay that graph. A
+ * circuit changed by yao_circuit_push since is recorded anew. states[c] ends holding
+ * circuit c's output state. The graph is replayed on the bound stream. Synchronises. */
 int yao_batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* circs,
                   const double* const* params, const yao_pauli_sum* const* h, double* energy,
                   double* const* grad);

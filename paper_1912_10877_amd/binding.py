@@ -30,7 +30,8 @@ class YaoError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("plain", ctypes.c_int), ("tile_qubits", ctypes.c_int), ("fuse_width", ctypes.c_int),
-                ("checkpoint_every", ctypes.c_int), ("drift_tol", ctypes.c_double), ("mfma", ctypes.c_int)]
+                ("checkpoint_every", ctypes.c_int), ("drift_tol", ctypes.c_double), ("mfma", ctypes.c_int),
+                ("autotune", ctypes.c_int)]
 
 
 _lib = None
@@ -58,6 +59,7 @@ _SIGS = {
     "yao_pauli_sum_destroy": [P],
     "yao_expect": [P, P, P],
     "yao_hpsi": [P, P, P, P],
+    "yao_inner": [P, P, P, P],
     "yao_circuit_create": [I, PP],
     "yao_circuit_destroy": [P],
     "yao_circuit_push": [P, I, I, D, P, P, I, I, P, P],
@@ -273,6 +275,14 @@ def hpsi(state: State, H: PauliSum, out: State, with_energy=True):
     e = np.zeros(state.batch) if with_energy else None
     _check(lib().yao_hpsi(state.h, H.h, out.h, _ptr(e)))
     return e
+
+
+def inner(a: State, b: State) -> np.ndarray:
+    """<a_b|b_b> per batch slot (complex128 numpy array)."""
+    re = np.zeros(a.batch)
+    im = np.zeros(a.batch)
+    _check(lib().yao_inner(a.h, b.h, _ptr(re), _ptr(im)))
+    return re + 1j * im
 
 
 def forward(state: State, circ: Circuit, params):

@@ -172,6 +172,7 @@ int yao_state_wrap(void* dev_ptr, int n, int batch, enum yao_dtype dt, yao_state
 int yao_state_destroy(yao_state* s)
 {
     if (!s) return 0;
+    drop_batch(s);
     if (s->owns && s->data) {
         hipError_t e = hipFree(s->data);
         delete s;
@@ -266,6 +267,7 @@ int yao_pauli_sum_create(int n, int nterms, const double* coef, const uint64_t* 
 int yao_pauli_sum_destroy(yao_pauli_sum* h)
 {
     if (!h) return 0;
+    drop_batch(h);
     if (h->d_groups) (void)hipFree(h->d_groups);
     if (h->d_terms) (void)hipFree(h->d_terms);
     delete h;
@@ -292,6 +294,15 @@ int yao_hpsi(const yao_state* s, const yao_pauli_sum* h, yao_state* out, double*
     return launch_hpsi(s->data, s->dtype, out->data, out->dtype, s->n, s->batch, const_cast<yao_pauli_sum*>(h), energy);
 }
 
+int yao_inner(const yao_state* a, const yao_state* b, double* re, double* im)
+{
+    YAO_TRY(check_state(a));
+    YAO_TRY(check_state(b));
+    if (!re || !im) return set_error(YAO_EINVAL, "re or im is NULL");
+    if (a->n != b->n || a->batch != b->batch) return set_error(YAO_EINVAL, "states differ in n or batch");
+    return launch_inner(a->data, a->dtype, b->data, b->dtype, a->n, a->batch, re, im);
+}
+
 // ------------------------------------------------------------------------------- circuits
 int yao_circuit_create(int n, yao_circuit** out)
 {
@@ -309,7 +320,9 @@ int yao_circuit_create(int n, yao_circuit** out)
 int yao_circuit_destroy(yao_circuit* c)
 {
     if (!c) return 0;
+    drop_batch(c);
     drop_plans(c);
+    drop_fused(c);
     delete c;
     return 0;
 }

@@ -11,6 +11,12 @@ static bool use_fused(const yao_state* s)
 
 int forward(yao_state* s, const yao_circuit* c, const double* params)
 {
+    // Forward-only sweeps may fold runs of gates into dense blocks of up to fuse_width qubits.
+    const int width = options().fuse_width;
+    if (width > 1 && !c->gates.empty()) {
+        c = fused_circuit(c, params, width);
+        params = nullptr;
+    }
     if (use_fused(s)) return forward_fused(s->data, s->dtype, s->n, s->batch, c, params);
     return forward_plain(s->data, s->dtype, s->n, s->batch, c, params);
 }
@@ -20,16 +26,6 @@ int backward(yao_state* s, const yao_circuit* c, const double* params, yao_pauli
 {
     if (use_fused(s)) return backward_fused(s, c, params, h, mode, reduce_batch, energy, grad, drift);
     return backward_plain(s, c, params, h, reduce_batch, energy, grad, drift);
-}
-
-int batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* circs, const double* const* params,
-              yao_pauli_sum* const* h, double* energy, double* const* grad)
-{
-    for (int c = 0; c < ncirc; ++c) {
-        YAO_TRY(launch_reset(states[c]));
-        YAO_TRY(backward(states[c], circs[c], params[c], h[c], YAO_GRAD_REVERSIBLE, false, energy + c, grad[c], nullptr));
-    }
-    return 0;
 }
 
 }  // namespace yao

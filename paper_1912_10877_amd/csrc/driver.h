@@ -10,9 +10,17 @@ int apply_one(yao_state* s, const GateRec& g, double theta);
 int forward(yao_state* s, const yao_circuit* c, const double* params);
 int backward(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h, int mode, bool reduce_batch,
              double* energy, double* grad, double* drift);
+// Graph-recorded batch of circuits (driver_batch.cpp); drop_batch forgets a recorded batch
+// that uses the circuit, state or observable obj.
 int batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* circs, const double* const* params,
               yao_pauli_sum* const* h, double* energy, double* const* grad);
+void drop_batch(const void* obj);
 void drop_plans(const yao_circuit* c);
+
+// Dense-block fusion for forward sweeps (fusion.cpp).
+std::vector<GateRec> fuse_gates(const yao_circuit* c, const double* params, int width);
+const yao_circuit* fused_circuit(const yao_circuit* c, const double* params, int width);
+void drop_fused(const yao_circuit* c);
 
 // Per-gate form.
 int forward_plain(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params);

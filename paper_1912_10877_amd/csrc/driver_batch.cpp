@@ -1,0 +1,547 @@
+// Batches of independent circuits of uneven size (the batched registers of Sec. "Batched
+// Quantum Registers", taken to circuits that differ): every circuit's reset, forward passes,
+// H psi with its energy, reverse passes and gradient sums are recorded once into one HIP
+// graph, spread over a few streams so that small circuits run beside large ones. Later calls
+// with the same circuits rebuild only the parameter-dependent op records and matrices on the
+// host, copy them to the device in one transfer and replay the graph.
+//
+// The forward sweep of each circuit may fold gates into dense blocks (fusion.cpp); the width
+// of those blocks and the tile sizes of both sweeps are chosen per qubit count by timing the
+// candidates on the first batch that has that qubit count (the autotuner below).
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <tuple>
+
+#include "driver.h"
+#include "fused.h"
+
+namespace yao {
+
+int launch_fill(double* p, size_t count, double v);
+void set_stream(hipStream_t s);
+int prepare_pass_kernels();
+
+namespace {
+
+constexpr int kBanks = 4;  // streams of the graph
+
+struct Tune {
+    int width = 1;  // dense fusion width of the forward sweep
+    int tq_f = 0;   // tile qubits of the forward passes (0: default)
+    int tq_b = 0;   // of the reverse passes
+};
+std::map<std::pair<int, int>, Tune> g_tune;  // (n, dtype)
+
+struct Item {
+    int idx = 0;  // position in the caller's arrays
+    const yao_circuit* c = nullptr;
+    const yao_circuit* fc = nullptr;  // circuit of the forward sweep (c, or its fused form)
+    uint64_t fc_version = 0;
+    yao_state* s = nullptr;
+    yao_pauli_sum* h = nullptr;
+    Tune tune;
+    const Plan* fwd = nullptr;
+    const Plan* bwd = nullptr;
+    Program pf, pb;
+    DevProgram df{}, db{};
+    size_t off_f = 0, off_b = 0, bytes_f = 0, bytes_b = 0;  // program blobs
+    int bank = 0;
+    int nslots = 0;
+    int W = 0;                    // partial-sum row stride of the reverse passes
+    size_t out_e = 0, out_g = 0;  // positions in the output block
+    double cost = 0;
+};
+
+using Key = std::vector<std::tuple<const yao_circuit*, uint64_t, const yao_state*, const yao_pauli_sum*, int>>;
+
+struct Cache {
+    Key key;
+    yao_options opt{};
+    std::vector<Item> items;  // recording order
+    char* d_prog = nullptr;
+    char* h_prog = nullptr;
+    size_t prog_bytes = 0;
+    double* d_out = nullptr;
+    double* h_out = nullptr;
+    size_t nout = 0;
+    double* psi64[kBanks] = {};
+    void* lam[kBanks] = {};
+    double* gpart[kBanks] = {};
+    double* hpart[kBanks] = {};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double algo_bytes = 0, algo_flops = 0;
+};
+
+Cache* g_cache = nullptr;
+hipStream_t g_capture = nullptr;
+hipStream_t g_bank[kBanks] = {};
+hipEvent_t g_fork = nullptr, g_join[kBanks] = {};
+
+void free_cache(Cache* c)
+{
+    if (!c) return;
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->d_prog) (void)hipFree(c->d_prog);
+    if (c->h_prog) (void)hipHostFree(c->h_prog);
+    if (c->d_out) (void)hipFree(c->d_out);
+    if (c->h_out) (void)hipHostFree(c->h_out);
+    for (int b = 0; b < kBanks; ++b) {
+        if (c->psi64[b]) (void)hipFree(c->psi64[b]);
+        if (c->lam[b]) (void)hipFree(c->lam[b]);
+        if (c->gpart[b]) (void)hipFree(c->gpart[b]);
+        if (c->hpart[b]) (void)hipFree(c->hpart[b]);
+    }
+    delete c;
+}
+
+int dev_alloc(void** p, size_t bytes)
+{
+    if (hipMalloc(p, bytes ? bytes : 256) != hipSuccess) return set_error(YAO_ENOMEM, "batch buffer of %zu bytes", bytes);
+    return 0;
+}
+
+int host_alloc(void** p, size_t bytes)
+{
+    if (hipHostMalloc(p, bytes ? bytes : 256, hipHostMallocDefault) != hipSuccess)
+        return set_error(YAO_ENOMEM, "pinned batch buffer of %zu bytes", bytes);
+    return 0;
+}
+
+int ensure_streams()
+{
+    if (g_fork) return 0;
+    YAO_HIP(hipStreamCreateWithFlags(&g_capture, hipStreamNonBlocking));
+    for (int b = 0; b < kBanks; ++b) {
+        YAO_HIP(hipStreamCreateWithFlags(&g_bank[b], hipStreamNonBlocking));
+        YAO_HIP(hipEventCreateWithFlags(&g_join[b], hipEventDisableTiming));
+    }
+    YAO_HIP(hipEventCreateWithFlags(&g_fork, hipEventDisableTiming));
+    return 0;
+}
+
+int count_param_slots(const yao_circuit* c)
+{
+    int k = 0;
+    for (const GateRec& g : c->gates) k += (is_param_kind(g.kind) && g.param >= 0) ? 1 : 0;
+    return k;
+}
+
+const Plan& plan_for(const yao_circuit* c, int n, int dtype, bool bwd, int tq)
+{
+    int t, cb, L;
+    tile_geometry_tq(n, 1, dtype, bwd, tq, &t, &cb, &L);
+    return get_plan(c, 0, (int)c->gates.size(), 1, t, cb, L, bwd);
+}
+
+int reverse_stride(int n, int dtype, int tq)
+{
+    int t, cb, L;
+    tile_geometry_tq(n, 1, dtype, true, tq, &t, &cb, &L);
+    return std::max(1 << (n - (t - cb)), adjoint_nblk(n, 1, 1));
+}
+
+// The circuit the forward sweep of c runs for a fusion width, refreshed for these parameters.
+const yao_circuit* forward_circuit(const yao_circuit* c, const double* params, int width)
+{
+    if (width <= 1 || c->gates.empty()) return c;
+    return fused_circuit(c, params, width);
+}
+
+// A program uploaded to a private buffer (for the autotuner's trial runs).
+struct TrialProgram {
+    char* d = nullptr;
+    DevProgram dp{};
+    ~TrialProgram()
+    {
+        if (d) (void)hipFree(d);
+    }
+    int load(const Program& p, hipStream_t st)
+    {
+        const size_t bytes = program_blob_bytes(p);
+        std::vector<char> h(bytes);
+        YAO_TRY(dev_alloc((void**)&d, bytes));
+        pack_program(p, h.data(), d, dp);
+        YAO_HIP(hipMemcpyAsync(d, h.data(), bytes, hipMemcpyHostToDevice, st));
+        YAO_HIP(hipStreamSynchronize(st));
+        return 0;
+    }
+};
+
+struct TrialBuffers {
+    double* psi64 = nullptr;
+    void* lam = nullptr;
+    double* gpart = nullptr;
+    double* hpart = nullptr;
+    double* e = nullptr;
+    ~TrialBuffers()
+    {
+        if (psi64) (void)hipFree(psi64);
+        if (lam) (void)hipFree(lam);
+        if (gpart) (void)hipFree(gpart);
+        if (hpart) (void)hipFree(hpart);
+        if (e) (void)hipFree(e);
+    }
+};
+
+// Median of three timed runs of fn (after one untimed run), in milliseconds.
+template <typename F> int time_ms(hipStream_t st, F fn, double* ms)
+{
+    hipEvent_t e0, e1;
+    YAO_HIP(hipEventCreate(&e0));
+    YAO_HIP(hipEventCreate(&e1));
+    int rc = fn();
+    double v[3] = {0, 0, 0};
+    for (int r = 0; r < 3 && !rc; ++r) {
+        if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(YAO_EHIP, "event record");
+        if (!rc) rc = fn();
+        if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = set_error(YAO_EHIP, "event record");
+        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = set_error(YAO_EHIP, "event sync");
+        float f = 0;
+        if (!rc && hipEventElapsedTime(&f, e0, e1) != hipSuccess) rc = set_error(YAO_EHIP, "elapsed time");
+        v[r] = f;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::sort(v, v + 3);
+    *ms = v[1];
+    return rc;
+}
+
+// Candidate tile qubit counts of a state: the default, and smaller tiles when the state has
+// more qubits than a tile (more workgroups, more passes).
+std::vector<int> tile_candidates(int n, int dtype, bool bwd)
+{
+    std::vector<int> out{0};
+    int t0, cb, L;
+    tile_geometry_tq(n, 1, dtype, bwd, 0, &t0, &cb, &L);
+    if (t0 - cb >= n) return out;
+    for (int tq = t0 - cb - 1; tq >= std::max(kMaxRegBits + 1, t0 - cb - 3); --tq) out.push_back(tq);
+    return out;
+}
+
+// Pick the fusion width and tile sizes for circuits like c (on state s, observable h) by timing.
+int autotune(const yao_circuit* c, const double* params, yao_state* s, yao_pauli_sum* h, Tune* best)
+{
+    hipStream_t st = g_capture;
+    const int n = s->n, dt = s->dtype;
+    set_stream(st);
+    const size_t N = size_t(1) << n;
+    // Forward: width x tile.
+    double best_f = 1e300;
+    for (int w = 1; w <= 5; ++w) {
+        if (w > n) break;
+        for (int tq : tile_candidates(n, dt, false)) {
+            const yao_circuit* fc = forward_circuit(c, params, w);
+            const double* fp = fc == c ? params : nullptr;
+            const Plan& P = plan_for(fc, n, dt, false, tq);
+            Program prog;
+            YAO_TRY(build_program(P, fc, fp, false, dt, prog));
+            TrialProgram tp;
+            YAO_TRY(tp.load(prog, st));
+            double ms = 0;
+            YAO_TRY(time_ms(st, [&] { return launch_forward_passes(P, prog, tp.dp, s->data, dt, n, 1, fc, fp); }, &ms));
+            if (ms < best_f) {
+                best_f = ms;
+                best->width = w;
+                best->tq_f = tq;
+            }
+        }
+    }
+    // Reverse sweep: tile only (gradients need the gates one by one).
+    const int nslots = count_param_slots(c);
+    if (nslots == 0) return 0;
+    TrialBuffers tb;
+    size_t gp = 1;
+    for (int tq : tile_candidates(n, dt, true)) gp = std::max(gp, (size_t)nslots * reverse_stride(n, dt, tq));
+    YAO_TRY(dev_alloc((void**)&tb.psi64, 16 * N));
+    YAO_TRY(dev_alloc(&tb.lam, s->elem_bytes() * N));
+    YAO_TRY(dev_alloc((void**)&tb.gpart, sizeof(double) * gp));
+    YAO_TRY(dev_alloc((void**)&tb.hpart, sizeof(double) * hpsi_partial_doubles(n, 1)));
+    YAO_TRY(dev_alloc((void**)&tb.e, sizeof(double)));
+    double best_b = 1e300;
+    for (int tq : tile_candidates(n, dt, true)) {
+        const Plan& P = plan_for(c, n, dt, true, tq);
+        Program prog;
+        YAO_TRY(build_program(P, c, params, true, dt, prog));
+        TrialProgram tp;
+        YAO_TRY(tp.load(prog, st));
+        const int W = reverse_stride(n, dt, tq);
+        double ms = 0;
+        YAO_TRY(launch_fill_basis(s->data, dt, n, 1));
+        YAO_TRY(launch_convert(s->data, dt, tb.psi64, YAO_C128, N));
+        YAO_TRY(launch_hpsi_dev(s->data, dt, tb.lam, dt, n, 1, h, tb.hpart, tb.e));
+        YAO_TRY(time_ms(
+            st,
+            [&] {
+                YAO_TRY(launch_fill(tb.gpart, (size_t)nslots * W, 0.0));
+                return launch_backward_passes(P, prog, tp.dp, c, params, tb.psi64, tb.lam, dt, n, 1, tb.gpart, W);
+            },
+            &ms));
+        if (ms < best_b) {
+            best_b = ms;
+            best->tq_b = tq;
+        }
+    }
+    return 0;
+}
+
+// Host programs of every item for these parameters, packed into the pinned blob. Returns 1
+// if a program no longer has the size the graph was recorded with.
+int build_programs(Cache& C, const double* const* params, bool first)
+{
+    for (Item& it : C.items) {
+        const double* p = params[it.idx];
+        const yao_circuit* fc = forward_circuit(it.c, p, it.tune.width);
+        if (!first && (fc != it.fc || fc->version != it.fc_version)) return 1;
+        it.fc = fc;
+        it.fc_version = fc->version;
+        const double* fp = fc == it.c ? p : nullptr;
+        if (first) {
+            it.fwd = &plan_for(fc, it.s->n, it.s->dtype, false, it.tune.tq_f);
+            it.bwd = &plan_for(it.c, it.s->n, it.s->dtype, true, it.tune.tq_b);
+        }
+        it.pf = Program();
+        it.pb = Program();
+        YAO_TRY(build_program(*it.fwd, fc, fp, false, it.s->dtype, it.pf));
+        if (it.nslots) YAO_TRY(build_program(*it.bwd, it.c, p, true, it.s->dtype, it.pb));
+        const size_t bf = program_blob_bytes(it.pf), bb = it.nslots ? program_blob_bytes(it.pb) : 0;
+        if (!first && (bf != it.bytes_f || bb != it.bytes_b)) return 1;
+        it.bytes_f = bf;
+        it.bytes_b = bb;
+    }
+    return 0;
+}
+
+void pack_all(Cache& C)
+{
+    for (Item& it : C.items) {
+        pack_program(it.pf, C.h_prog + it.off_f, C.d_prog + it.off_f, it.df);
+        if (it.nslots) pack_program(it.pb, C.h_prog + it.off_b, C.d_prog + it.off_b, it.db);
+    }
+}
+
+int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit* const* circs,
+                const double* const* params, yao_pauli_sum* const* h)
+{
+    C.opt = options();
+    C.items.resize(ncirc);
+    for (int i = 0; i < ncirc; ++i) {
+        Item& it = C.items[i];
+        it.idx = i;
+        it.c = circs[i];
+        it.s = states[i];
+        it.h = h[i];
+        const int n = it.s->n;
+        if (!fused_supported(n, 1)) return set_error(YAO_EINVAL, "batch circuit %d has %d qubits; needs >= 5", i, n);
+        YAO_TRY(pauli_upload(it.h));
+        it.nslots = count_param_slots(it.c);
+        it.cost = (double)(it.c->gates.size() + 1) * (double)(uint64_t(1) << n);
+    }
+    // Tuning per qubit count, on the deepest circuit of that count.
+    std::map<std::pair<int, int>, int> rep;
+    for (int i = 0; i < ncirc; ++i) {
+        auto k = std::make_pair(C.items[i].s->n, C.items[i].s->dtype);
+        auto r = rep.find(k);
+        if (r == rep.end() || C.items[r->second].c->gates.size() < C.items[i].c->gates.size()) rep[k] = i;
+    }
+    for (auto& kv : rep) {
+        Tune t;
+        t.width = std::max(1, C.opt.fuse_width);
+        t.tq_f = t.tq_b = C.opt.tile_qubits;
+        if (C.opt.autotune) {
+            auto f = g_tune.find(kv.first);
+            if (f != g_tune.end()) {
+                t = f->second;
+            } else {
+                const Item& it = C.items[kv.second];
+                YAO_TRY(autotune(it.c, params[it.idx], it.s, it.h, &t));
+                g_tune[kv.first] = t;
+            }
+        }
+        for (Item& it : C.items)
+            if (it.s->n == kv.first.first && it.s->dtype == kv.first.second) it.tune = t;
+    }
+    YAO_TRY(build_programs(C, params, true));
+    for (Item& it : C.items) it.W = reverse_stride(it.s->n, it.s->dtype, it.tune.tq_b);
+
+    // Largest circuits first, each on the least loaded stream.
+    std::stable_sort(C.items.begin(), C.items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    double load[kBanks] = {};
+    size_t psi_b[kBanks] = {}, lam_b[kBanks] = {}, gp_b[kBanks] = {}, hp_b[kBanks] = {};
+    size_t nout = 0, off = 0;
+    for (Item& it : C.items) {
+        int best = 0;
+        for (int b = 1; b < kBanks; ++b)
+            if (load[b] < load[best]) best = b;
+        it.bank = best;
+        load[best] += it.cost;
+        const size_t N = size_t(1) << it.s->n;
+        psi_b[best] = std::max(psi_b[best], 16 * N);
+        lam_b[best] = std::max(lam_b[best], it.s->elem_bytes() * N);
+        gp_b[best] = std::max(gp_b[best], sizeof(double) * (size_t)std::max(1, it.nslots) * it.W);
+        hp_b[best] = std::max(hp_b[best], sizeof(double) * hpsi_partial_doubles(it.s->n, 1));
+        it.out_e = nout++;
+        it.off_f = off;
+        off += it.bytes_f;
+        it.off_b = off;
+        off += it.bytes_b;
+    }
+    for (Item& it : C.items) {
+        it.out_g = nout;
+        nout += it.nslots;
+    }
+    C.nout = nout;
+    C.prog_bytes = off;
+    YAO_TRY(dev_alloc((void**)&C.d_prog, C.prog_bytes));
+    YAO_TRY(host_alloc((void**)&C.h_prog, C.prog_bytes));
+    YAO_TRY(dev_alloc((void**)&C.d_out, sizeof(double) * C.nout));
+    YAO_TRY(host_alloc((void**)&C.h_out, sizeof(double) * C.nout));
+    for (int b = 0; b < kBanks; ++b) {
+        YAO_TRY(dev_alloc((void**)&C.psi64[b], psi_b[b]));
+        YAO_TRY(dev_alloc(&C.lam[b], lam_b[b]));
+        YAO_TRY(dev_alloc((void**)&C.gpart[b], gp_b[b]));
+        YAO_TRY(dev_alloc((void**)&C.hpart[b], hp_b[b]));
+    }
+    pack_all(C);
+    // Algorithmic traffic and flops of one replay (every pass reads and writes its states once).
+    for (const Item& it : C.items) {
+        const double N = (double)(uint64_t(1) << it.s->n);
+        const double s = (double)it.s->elem_bytes();
+        for (size_t p = 0; p < it.fwd->passes.size(); ++p) {
+            C.algo_bytes += 2.0 * s * N;
+            C.algo_flops += it.pf.pass_flops[p] * N;
+        }
+        C.algo_bytes += 2.0 * s * N + 16.0 * N;  // H psi reads psi, writes lambda; FP64 copy
+        if (!it.nslots) continue;
+        for (size_t p = 0; p < it.bwd->passes.size(); ++p) {
+            C.algo_bytes += 2.0 * (16.0 + s) * N;
+            C.algo_flops += it.pb.pass_flops[p] * N;
+        }
+    }
+    return 0;
+}
+
+int record(Cache& C)
+{
+    YAO_TRY(prepare_pass_kernels());
+    hipStream_t cs = g_capture;
+    YAO_HIP(hipStreamSynchronize(cs));
+    YAO_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    prof_suspend(true);
+    int rc = 0;
+    do {
+        if (hipEventRecord(g_fork, cs) != hipSuccess) {
+            rc = set_error(YAO_EHIP, "fork record");
+            break;
+        }
+        for (int b = 0; b < kBanks && !rc; ++b)
+            if (hipStreamWaitEvent(g_bank[b], g_fork, 0) != hipSuccess) rc = set_error(YAO_EHIP, "fork wait");
+        if (rc) break;
+        for (Item& it : C.items) {
+            const int n = it.s->n, dt = it.s->dtype, bk = it.bank;
+            set_stream(g_bank[bk]);
+            if ((rc = launch_fill_basis(it.s->data, dt, n, 1))) break;
+            if ((rc = launch_forward_passes(*it.fwd, it.pf, it.df, it.s->data, dt, n, 1, it.fc, nullptr))) break;
+            if ((rc = launch_hpsi_dev(it.s->data, dt, C.lam[bk], dt, n, 1, it.h, C.hpart[bk], C.d_out + it.out_e)))
+                break;
+            if (it.nslots == 0) continue;
+            if ((rc = launch_convert(it.s->data, dt, C.psi64[bk], YAO_C128, size_t(1) << n))) break;
+            if ((rc = launch_fill(C.gpart[bk], (size_t)it.nslots * it.W, 0.0))) break;
+            if ((rc = launch_backward_passes(*it.bwd, it.pb, it.db, it.c, nullptr, C.psi64[bk], C.lam[bk], dt, n, 1,
+                                             C.gpart[bk], it.W)))
+                break;
+            if ((rc = launch_row_sums(C.gpart[bk], it.nslots, it.W, C.d_out + it.out_g))) break;
+        }
+        if (rc) break;
+        for (int b = 0; b < kBanks; ++b) {
+            if (hipEventRecord(g_join[b], g_bank[b]) != hipSuccess || hipStreamWaitEvent(cs, g_join[b], 0) != hipSuccess) {
+                rc = set_error(YAO_EHIP, "join");
+                break;
+            }
+        }
+    } while (0);
+    prof_suspend(false);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (rc || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc ? rc : hip_fail(e, "hipStreamEndCapture");
+    }
+    C.graph = graph;
+    YAO_HIP(hipGraphInstantiate(&C.exec, graph, nullptr, nullptr, 0));
+    return 0;
+}
+
+bool same_options(const yao_options& a, const yao_options& b)
+{
+    return a.tile_qubits == b.tile_qubits && a.fuse_width == b.fuse_width && a.mfma == b.mfma &&
+           a.autotune == b.autotune;
+}
+
+}  // namespace
+
+int batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* circs, const double* const* params,
+              yao_pauli_sum* const* h, double* energy, double* const* grad)
+{
+    YAO_TRY(ensure_streams());
+    const hipStream_t origin = stream();
+    Key key;
+    for (int i = 0; i < ncirc; ++i) key.emplace_back(circs[i], circs[i]->version, states[i], h[i], states[i]->dtype);
+    bool fresh = !g_cache || g_cache->key != key || !same_options(g_cache->opt, options());
+    if (!fresh) {
+        const int r = build_programs(*g_cache, params, false);
+        if (r < 0) return r;
+        if (r == 1) fresh = true;
+        else pack_all(*g_cache);
+    }
+    if (fresh) {
+        YAO_HIP(hipStreamSynchronize(origin));
+        free_cache(g_cache);
+        g_cache = new Cache;
+        g_cache->key = key;
+        int rc = build_cache(*g_cache, ncirc, states, circs, params, h);
+        if (!rc) rc = record(*g_cache);
+        set_stream(origin);
+        if (rc) {
+            free_cache(g_cache);
+            g_cache = nullptr;
+            return rc;
+        }
+    }
+    Cache& C = *g_cache;
+    const int pi = prof_begin(YAO_KF_BATCH);
+    YAO_HIP(hipMemcpyAsync(C.d_prog, C.h_prog, C.prog_bytes, hipMemcpyHostToDevice, origin));
+    YAO_HIP(hipGraphLaunch(C.exec, origin));
+    prof_end(pi, C.algo_bytes, C.algo_flops);
+    YAO_HIP(hipMemcpyAsync(C.h_out, C.d_out, sizeof(double) * C.nout, hipMemcpyDeviceToHost, origin));
+    YAO_HIP(hipStreamSynchronize(origin));
+    for (const Item& it : C.items) {
+        energy[it.idx] = C.h_out[it.out_e];
+        const int P = it.c->nparams;
+        double* g = grad[it.idx];
+        for (int p = 0; p < P; ++p) g[p] = 0.0;
+        if (!it.nslots) continue;
+        for (int gi = (int)it.c->gates.size() - 1; gi >= 0; --gi) {
+            const int slot = it.pb.slot_of_gate[gi];
+            if (slot >= 0) g[it.c->gates[gi].param] += C.h_out[it.out_g + slot];
+        }
+    }
+    return 0;
+}
+
+void drop_batch(const void* obj)
+{
+    if (!g_cache) return;
+    for (const Item& it : g_cache->items)
+        if ((const void*)it.c == obj || (const void*)it.s == obj || (const void*)it.h == obj) {
+            (void)hipDeviceSynchronize();
+            free_cache(g_cache);
+            g_cache = nullptr;
+            return;
+        }
+}
+
+}  // namespace yao

@@ -13,16 +13,12 @@ namespace yao {
 
 int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, const POp* ops, const PGroupDesc* groups,
                 const double* mats, double* gpartial, int pstride, int n, int B, int c, int t, int group0,
-                int ngroups, const std::vector<int>& tile_qubits, double flops);
+                int ngroups, const std::vector<int>& tile_qubits, double flops, int op_first, int nops);
 int launch_fill(double* p, size_t count, double v);
-int launch_adjoint_step_strided(double* psi, void* lam, int lam_dtype, int n, int B, const HostMat& Ud,
-                                const HostMat* M, const int* locs, CtrlSpec c, double* partial, int pstride);
-
-namespace {
 
 using PlanKey = std::tuple<const yao_circuit*, uint64_t, int, int, int, int, int, int, bool>;
-std::map<PlanKey, Plan> g_plans;
-std::mutex g_plan_mu;
+static std::map<PlanKey, Plan> g_plans;
+static std::mutex g_plan_mu;
 
 const Plan& get_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse)
 {
@@ -75,23 +71,12 @@ double op_flops(const POp& op, bool bwd)
     return 2 * f + g;
 }
 
-// Device program of one plan for the given parameters.
-struct Program {
-    std::vector<POp> ops;
-    std::vector<PGroupDesc> groups;
-    std::vector<double> mats;
-    std::vector<int> pass_group0;   // per pass
-    std::vector<double> pass_flops; // algorithmic flops per element of the state, per pass
-    std::vector<int> slot_of_gate;  // gradient slot per gate (-1)
-    int nslots = 0;
-};
-
-void append(std::vector<double>& v, const std::vector<double>& a)
+static void append(std::vector<double>& v, const std::vector<double>& a)
 {
     v.insert(v.end(), a.begin(), a.end());
 }
 
-int build_program(const Plan& P, const yao_circuit* c, const double* params, bool bwd, Program& prog)
+int build_program(const Plan& P, const yao_circuit* c, const double* params, bool bwd, int dtype, Program& prog)
 {
     const int G = (int)c->gates.size();
     prog.slot_of_gate.assign(G, -1);
@@ -101,8 +86,32 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
     }
     for (const HostPass& pass : P.passes) {
         prog.pass_group0.push_back((int)prog.groups.size());
+        prog.pass_op0.push_back((int)prog.ops.size());
+        prog.pass_nops.push_back(0);
         prog.pass_flops.push_back(0.0);
-        if (pass.standalone >= 0) continue;
+        prog.pass_mat.push_back(-1);
+        if (pass.standalone >= 0) {
+            // A gate wider than a pass takes: its matrices go to the pool in the form its own
+            // launch reads.
+            const int gi = P.ops[pass.standalone].gate;
+            const GateRec& g = c->gates[gi];
+            const double th = gate_theta(g, params);
+            HostMat U;
+            if (!gate_matrix(g, th, U)) return set_error(YAO_EINVAL, "bad gate %d", gi);
+            if (!bwd) {
+                prog.pass_mat.back() = (int)encode_gate_matrix(dtype, P.n, P.B, U, prog.mats);
+            } else {
+                HostMat Ud = dagger(U), M;
+                if (prog.slot_of_gate[gi] >= 0) gate_grad_matrix(g, th, M);
+                else M.resize(g.k);
+                prog.pass_mat.back() = (int)prog.mats.size();
+                append(prog.mats, Ud.re);
+                append(prog.mats, Ud.im);
+                append(prog.mats, M.re);
+                append(prog.mats, M.im);
+            }
+            continue;
+        }
         uint64_t T = 0;
         for (int q : pass.tile_qubits) T |= uint64_t(1) << q;
         auto tile_bit = [&](int q) {
@@ -120,7 +129,8 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     ++nr;
                 }
             gd.lds = hg.lds ? 1 : 0;
-            gd.op0 = (int)prog.ops.size();
+            gd.op0 = (int)prog.ops.size() - prog.pass_op0.back();
+            prog.pass_nops.back() += (int)hg.ops.size();
             gd.nops = (int)hg.ops.size();
             gd.nslot = 0;
             for (int oi : hg.ops) {
@@ -187,54 +197,99 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
     return 0;
 }
 
-struct DevProgram {
-    POp* ops;
-    PGroupDesc* groups;
-    double* mats;
-};
+static size_t al256(size_t v)
+{
+    return (v + 255) & ~size_t(255);
+}
 
-int upload_program(const Program& prog, DevProgram& d)
+size_t program_blob_bytes(const Program& prog)
+{
+    return al256(prog.ops.size() * sizeof(POp)) + al256(prog.groups.size() * sizeof(PGroupDesc)) +
+           al256(prog.mats.size() * sizeof(double)) + 256;
+}
+
+// Lay the program out at host (to be copied to dev); d receives the device addresses.
+void pack_program(const Program& prog, char* host, char* dev, DevProgram& d)
 {
     const size_t so = prog.ops.size() * sizeof(POp);
     const size_t sg = prog.groups.size() * sizeof(PGroupDesc);
     const size_t sm = prog.mats.size() * sizeof(double);
-    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
-    std::vector<char> blob(al(so) + al(sg) + al(sm) + 256, 0);
-    if (so) memcpy(blob.data(), prog.ops.data(), so);
-    if (sg) memcpy(blob.data() + al(so), prog.groups.data(), sg);
-    if (sm) memcpy(blob.data() + al(so) + al(sg), prog.mats.data(), sm);
-    char* dev = (char*)upload_to(WS_MAT, blob.data(), blob.size());
-    if (!dev) return YAO_ENOMEM;
+    memset(host, 0, program_blob_bytes(prog));
+    if (so) memcpy(host, prog.ops.data(), so);
+    if (sg) memcpy(host + al256(so), prog.groups.data(), sg);
+    if (sm) memcpy(host + al256(so) + al256(sg), prog.mats.data(), sm);
     d.ops = (POp*)dev;
-    d.groups = (PGroupDesc*)(dev + al(so));
-    d.mats = (double*)(dev + al(so) + al(sg));
+    d.groups = (PGroupDesc*)(dev + al256(so));
+    d.mats = (double*)(dev + al256(so) + al256(sg));
+}
+
+static int upload_program(const Program& prog, DevProgram& d)
+{
+    std::vector<char> blob(program_blob_bytes(prog));
+    char* dev = (char*)workspace(WS_MAT, blob.size());
+    if (!dev) return YAO_ENOMEM;
+    pack_program(prog, blob.data(), dev, d);
+    if (!upload_to(WS_MAT, blob.data(), blob.size())) return YAO_ENOMEM;
     return 0;
 }
 
-}  // namespace
+int launch_forward_passes(const Plan& P, const Program& prog, const DevProgram& d, void* data, int dtype, int n, int B,
+                          const yao_circuit* c, const double* params)
+{
+    for (size_t p = 0; p < P.passes.size(); ++p) {
+        const HostPass& pass = P.passes[p];
+        if (pass.standalone >= 0) {
+            // The matrix is read from the program; the launch takes only its size from U.
+            const GateRec& g = c->gates[P.ops[pass.standalone].gate];
+            HostMat U;
+            U.k = g.k;
+            YAO_TRY(launch_gate(data, dtype, n, B, U, g.locs, make_ctrl(g.nctrl, g.ctrls, g.cvals),
+                                d.mats + prog.pass_mat[p]));
+            continue;
+        }
+        YAO_TRY(launch_pass(false, dtype, dtype, data, nullptr, d.ops, d.groups, d.mats, nullptr, 0, n, B, P.c, P.t,
+                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits,
+                            prog.pass_flops[p] * (double)(uint64_t(1) << n) * B, prog.pass_op0[p],
+                            prog.pass_nops[p]));
+    }
+    return 0;
+}
+
+int launch_backward_passes(const Plan& P, const Program& prog, const DevProgram& d, const yao_circuit* c,
+                           const double* params, double* psi, void* lam, int lam_dtype, int n, int B, double* gpartial,
+                           int W)
+{
+    for (size_t p = 0; p < P.passes.size(); ++p) {
+        const HostPass& pass = P.passes[p];
+        if (pass.standalone >= 0) {
+            // Matrices come from the program; the launch takes only their size from Ud and M.
+            const int gi = P.ops[pass.standalone].gate;
+            const GateRec& g = c->gates[gi];
+            HostMat Ud, M;
+            Ud.k = M.k = g.k;
+            const int slot = prog.slot_of_gate[gi];
+            YAO_TRY(launch_adjoint_step_strided(psi, lam, lam_dtype, n, B, Ud, slot >= 0 ? &M : nullptr, g.locs,
+                                                make_ctrl(g.nctrl, g.ctrls, g.cvals), d.mats + prog.pass_mat[p],
+                                                slot >= 0 ? gpartial + (size_t)slot * B * W : nullptr, W));
+            continue;
+        }
+        YAO_TRY(launch_pass(true, YAO_C128, lam_dtype, psi, lam, d.ops, d.groups, d.mats, gpartial, W, n, B, P.c, P.t,
+                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits,
+                            prog.pass_flops[p] * (double)(uint64_t(1) << n) * B, prog.pass_op0[p],
+                            prog.pass_nops[p]));
+    }
+    return 0;
+}
 
 namespace {
 
 int run_forward_plan(const Plan& P, void* data, int dtype, int n, int B, const yao_circuit* c, const double* params)
 {
     Program prog;
-    YAO_TRY(build_program(P, c, params, false, prog));
+    YAO_TRY(build_program(P, c, params, false, dtype, prog));
     DevProgram d;
     YAO_TRY(upload_program(prog, d));
-    for (size_t p = 0; p < P.passes.size(); ++p) {
-        const HostPass& pass = P.passes[p];
-        if (pass.standalone >= 0) {
-            const GateRec& g = c->gates[P.ops[pass.standalone].gate];
-            HostMat U;
-            gate_matrix(g, gate_theta(g, params), U);
-            YAO_TRY(launch_gate(data, dtype, n, B, U, g.locs, make_ctrl(g.nctrl, g.ctrls, g.cvals)));
-            continue;
-        }
-        YAO_TRY(launch_pass(false, dtype, dtype, data, nullptr, d.ops, d.groups, d.mats, nullptr, 0, n, B, P.c, P.t,
-                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits,
-                            prog.pass_flops[p] * (double)(uint64_t(1) << n) * B));
-    }
-    return 0;
+    return launch_forward_passes(P, prog, d, data, dtype, n, B, c, params);
 }
 
 // Reverse sweep over the gates of one plan: gradient partials into gpartial (row stride W).
@@ -242,31 +297,11 @@ int run_backward_plan(const Plan& P, const yao_circuit* c, const double* params,
                       int lam_dtype, int n, int B, double* gpartial, int W, std::vector<int>* slot_of_gate)
 {
     Program prog;
-    YAO_TRY(build_program(P, c, params, true, prog));
+    YAO_TRY(build_program(P, c, params, true, lam_dtype, prog));
     DevProgram d;
     YAO_TRY(upload_program(prog, d));
     if (slot_of_gate) *slot_of_gate = prog.slot_of_gate;
-    for (size_t p = 0; p < P.passes.size(); ++p) {
-        const HostPass& pass = P.passes[p];
-        if (pass.standalone >= 0) {
-            const int gi = P.ops[pass.standalone].gate;
-            const GateRec& g = c->gates[gi];
-            const double th = gate_theta(g, params);
-            HostMat U, M;
-            gate_matrix(g, th, U);
-            HostMat Ud = dagger(U);
-            const int slot = prog.slot_of_gate[gi];
-            if (slot >= 0) gate_grad_matrix(g, th, M);
-            YAO_TRY(launch_adjoint_step_strided(psi, lam, lam_dtype, n, B, Ud, slot >= 0 ? &M : nullptr, g.locs,
-                                                make_ctrl(g.nctrl, g.ctrls, g.cvals),
-                                                slot >= 0 ? gpartial + (size_t)slot * B * W : nullptr, W));
-            continue;
-        }
-        YAO_TRY(launch_pass(true, YAO_C128, lam_dtype, psi, lam, d.ops, d.groups, d.mats, gpartial, W, n, B, P.c, P.t,
-                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits,
-                            prog.pass_flops[p] * (double)(uint64_t(1) << n) * B));
-    }
-    return 0;
+    return launch_backward_passes(P, prog, d, c, params, psi, lam, lam_dtype, n, B, gpartial, W);
 }
 
 int count_slots(const yao_circuit* c)

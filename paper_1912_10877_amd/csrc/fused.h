@@ -14,6 +14,7 @@ constexpr int kMaxRegBits = 4;
 constexpr int kMaxTileBits = 13;  // 2^13 complex64 = 64 KiB of LDS
 constexpr int kMaxFusedK = 3;     // wider gates run as standalone launches between passes
 constexpr int kMaxGroupSlots = 12;  // gradient-carrying gates per register group
+constexpr int kMaxPassOps = 80;     // op records of a pass, staged in LDS at the start of the pass
 
 // Structure classes of a one-qubit matrix inside a pass.
 enum OpType : int {
@@ -86,8 +87,41 @@ struct Plan {
 // backward.
 Plan make_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cbits, int low_fixed, bool reverse,
                int reg_bits);
-// Choose tile geometry for a state.
+// Choose tile geometry for a state (tile qubits from the options, 0 = default).
 void tile_geometry(int n, int B, int dtype, bool backward, int* t, int* cbits, int* low_fixed);
+// The same for an explicit number of tile qubits (<= 0: default).
+void tile_geometry_tq(int n, int B, int dtype, bool backward, int tq, int* t, int* cbits, int* low_fixed);
+
+// Device program of one plan for given parameters (built on the host, copied in one block).
+struct Program {
+    std::vector<POp> ops;
+    std::vector<PGroupDesc> groups;
+    std::vector<double> mats;
+    std::vector<int> pass_group0;   // per pass
+    std::vector<int> pass_op0;      // first op record of the pass; group op0 is relative to it
+    std::vector<int> pass_nops;
+    std::vector<double> pass_flops; // algorithmic flops per element of the state, per pass
+    std::vector<int> pass_mat;      // standalone passes: offset in doubles of their matrices in mats
+    std::vector<int> slot_of_gate;  // gradient slot per gate (-1)
+    int nslots = 0;
+};
+struct DevProgram {
+    POp* ops;
+    PGroupDesc* groups;
+    double* mats;
+};
+const Plan& get_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse);
+// dtype: the state's (forward) or the adjoint state's (backward) precision.
+int build_program(const Plan& P, const yao_circuit* c, const double* params, bool bwd, int dtype, Program& prog);
+size_t program_blob_bytes(const Program& prog);
+void pack_program(const Program& prog, char* host, char* dev, DevProgram& d);
+// Launch the passes of a plan whose program is already in device memory (no host sync, no
+// copies: capturable in a graph).
+int launch_forward_passes(const Plan& P, const Program& prog, const DevProgram& d, void* data, int dtype, int n, int B,
+                          const yao_circuit* c, const double* params);
+int launch_backward_passes(const Plan& P, const Program& prog, const DevProgram& d, const yao_circuit* c,
+                           const double* params, double* psi, void* lam, int lam_dtype, int n, int B, double* gpartial,
+                           int W);
 
 // Drivers.
 int forward_fused(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params);

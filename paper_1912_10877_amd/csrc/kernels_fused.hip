@@ -10,6 +10,9 @@
 // first adds 2 Re <lambda|M|psi> over the tile (eq. outer-product reduced to the parameter),
 // then applies U^dagger to both (eq. apply-back). Per-thread gradient partials go to LDS and
 // are reduced once per register group, in a fixed order.
+//
+// The pass's op records are copied to LDS together with the tile; LDS reads complete in
+// order, so the record of the next op is fetched while the current op computes.
 #include "fused.h"
 
 namespace yao {
@@ -19,41 +22,18 @@ namespace {
 struct PassArgs {
     void* psi;
     void* lam;
-    const POp* ops;
-    const PGroupDesc* groups;
+    const POp* ops;         // the pass's records: ops[0 .. nops)
+    const PGroupDesc* groups;  // the pass's groups: groups[0 .. ngroups), op0 relative to ops
     const double* mats;
     double* gpartial;       // [slot][B][pstride]
     int n, B, c, t;
-    int group0, ngroups;
+    int ngroups, nops;
     int ntq, nnt;
     int ntiles;
     int pstride;
     int tile_qubits[kMaxTileBits];
     int nontile_qubits[40];
 };
-
-// The pass program is read-only for the whole launch; reading it through the constant
-// address space lets the uniform fetches go to scalar registers.
-template <typename T> struct ConstRef {
-    const T* p;
-    __device__ __forceinline__ T operator[](int i) const
-    {
-        static_assert(sizeof(T) % 4 == 0, "word-sized records");
-        using W = const uint32_t __attribute__((address_space(4)))*;
-        const W src = (W)(p + i);
-        uint32_t buf[sizeof(T) / 4];
-#pragma unroll
-        for (int w = 0; w < (int)(sizeof(T) / 4); ++w) buf[w] = src[w];
-        T out;
-        __builtin_memcpy(&out, buf, sizeof(T));
-        return out;
-    }
-    __device__ __forceinline__ T operator*() const { return (*this)[0]; }
-};
-template <typename T> __device__ __forceinline__ ConstRef<T> as_const(const T* p)
-{
-    return ConstRef<T>{p};
-}
 
 __device__ __forceinline__ uint32_t swz(uint32_t e)
 {
@@ -66,6 +46,38 @@ template <typename V, typename RR> __device__ __forceinline__ V mkv(RR a, RR b)
     v.x = a;
     v.y = b;
     return v;
+}
+
+__device__ __forceinline__ int sc(int v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ uint64_t sc64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Control fields of an op record, made wave-uniform (scalar registers).
+struct OpCtl {
+    int type, gen, rpos, slot, mat;
+    uint32_t cmask, cval;
+    uint64_t omask, oval;
+};
+__device__ __forceinline__ OpCtl op_ctl(const POp& r)
+{
+    OpCtl o;
+    o.type = sc(r.type);
+    o.gen = sc(r.gen);
+    o.rpos = sc(r.rpos);
+    o.slot = sc(r.slot);
+    o.mat = sc(r.mat);
+    o.cmask = (uint32_t)sc((int)r.cmask);
+    o.cval = (uint32_t)sc((int)r.cval);
+    o.omask = sc64(r.omask);
+    o.oval = sc64(r.oval);
+    return o;
 }
 
 // ------------------------------------------------------------------------------ pair updates
@@ -236,12 +248,12 @@ template <int RB> __device__ __forceinline__ uint64_t tile_off(const PassArgs& a
 // Tile index of register element r in a register group, split into the per-thread part
 // (ethr) and the per-register part (er[r], the same for every thread).
 template <int RB>
-__device__ __forceinline__ void group_index(const PGroupDesc& G, int t, int th, uint32_t& ethr,
+__device__ __forceinline__ void group_index(const int (&rpos)[kMaxRegBits], int t, int th, uint32_t& ethr,
                                             uint32_t (&er)[1 << RB])
 {
     uint32_t rmask = 0;
 #pragma unroll
-    for (int j = 0; j < RB; ++j) rmask |= 1u << G.rpos[j];
+    for (int j = 0; j < RB; ++j) rmask |= 1u << rpos[j];
     uint32_t v = 0;
     int k = 0;
     for (int b = 0; b < t; ++b) {
@@ -254,9 +266,35 @@ __device__ __forceinline__ void group_index(const PGroupDesc& G, int t, int th, 
     for (int r = 0; r < (1 << RB); ++r) {
         uint32_t e = 0;
 #pragma unroll
-        for (int j = 0; j < RB; ++j) e |= ((uint32_t)(r >> j) & 1u) << G.rpos[j];
+        for (int j = 0; j < RB; ++j) e |= ((uint32_t)(r >> j) & 1u) << rpos[j];
         er[r] = e;
     }
+}
+
+// Copy the pass's op records and group descriptors to LDS (16-byte words).
+__device__ __forceinline__ void stage_program(const PassArgs& a, POp* lops, PGroupDesc* lgrp, int th, int nthr)
+{
+    const uint4* so = (const uint4*)a.ops;
+    uint4* dop = (uint4*)lops;
+    for (int i = th; i < a.nops * (int)(sizeof(POp) / 16); i += nthr) dop[i] = so[i];
+    const uint4* sg = (const uint4*)a.groups;
+    uint4* dg = (uint4*)lgrp;
+    for (int i = th; i < a.ngroups * (int)(sizeof(PGroupDesc) / 16); i += nthr) dg[i] = sg[i];
+}
+
+struct GroupCtl {
+    int lds, op0, nops;
+    int rpos[kMaxRegBits];
+};
+__device__ __forceinline__ GroupCtl group_ctl(const PGroupDesc& g)
+{
+    GroupCtl o;
+    o.lds = sc(g.lds);
+    o.op0 = sc(g.op0);
+    o.nops = sc(g.nops);
+#pragma unroll
+    for (int j = 0; j < kMaxRegBits; ++j) o.rpos[j] = sc(g.rpos[j]);
+    return o;
 }
 
 // Reduce the per-thread partials red[s * nthr + th] (s < S) to one value per (slot, batch
@@ -290,11 +328,11 @@ template <int K> struct LdsGeom {
     uint32_t off[1 << K];
 };
 
-template <int K> __device__ __forceinline__ LdsGeom<K> lds_geom(const POp& op)
+template <int K> __device__ __forceinline__ LdsGeom<K> lds_geom(const int* tpos)
 {
     LdsGeom<K> g;
 #pragma unroll
-    for (int i = 0; i < K; ++i) g.sorted[i] = op.tpos[i];
+    for (int i = 0; i < K; ++i) g.sorted[i] = tpos[i];
 #pragma unroll
     for (int i = 0; i < K; ++i)
 #pragma unroll
@@ -309,7 +347,7 @@ template <int K> __device__ __forceinline__ LdsGeom<K> lds_geom(const POp& op)
         uint32_t o = 0;
 #pragma unroll
         for (int j = 0; j < K; ++j)
-            if ((s >> j) & 1) o |= 1u << op.tpos[j];
+            if ((s >> j) & 1) o |= 1u << tpos[j];
         g.off[s] = o;
     }
     return g;
@@ -326,15 +364,18 @@ template <int K> __device__ __forceinline__ uint32_t lds_base(uint32_t gidx, con
 }
 
 template <typename RP, int K>
-__device__ __noinline__ void lds_op_fwd(vec2_t<RP>* lp, const POp* __restrict__ opp, const double* m, int t, int th, int nthr)
+__device__ __noinline__ void lds_op_fwd(vec2_t<RP>* lp, const POp* rec, const double* m, int t, int th, int nthr)
 {
     using VP = vec2_t<RP>;
     constexpr int D = 1 << K, DD = D * D;
-    const POp op = *as_const(opp);
-    const LdsGeom<K> g = lds_geom<K>(op);
+    int tpos[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) tpos[j] = sc(rec->tpos[j]);
+    const uint32_t cmask = (uint32_t)sc((int)rec->cmask), cval = (uint32_t)sc((int)rec->cval);
+    const LdsGeom<K> g = lds_geom<K>(tpos);
     for (int gidx = th; gidx < (1 << (t - K)); gidx += nthr) {
         const uint32_t eb = lds_base<K>((uint32_t)gidx, g);
-        if ((eb & op.cmask) != op.cval) continue;
+        if ((eb & cmask) != cval) continue;
         VP v[D];
 #pragma unroll
         for (int s = 0; s < D; ++s) v[s] = lp[swz(eb | g.off[s])];
@@ -353,19 +394,23 @@ __device__ __noinline__ void lds_op_fwd(vec2_t<RP>* lp, const POp* __restrict__ 
 }
 
 template <typename RL, int K>
-__device__ __noinline__ double lds_op_bwd(double2* lp, vec2_t<RL>* ll, const POp* __restrict__ opp, const double* m, int t, int th,
+__device__ __noinline__ double lds_op_bwd(double2* lp, vec2_t<RL>* ll, const POp* rec, const double* m, int t, int th,
                                           int nthr)
 {
     using VL = vec2_t<RL>;
     constexpr int D = 1 << K, DD = D * D;
-    const POp op = *as_const(opp);
-    const LdsGeom<K> g = lds_geom<K>(op);
+    int tpos[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) tpos[j] = sc(rec->tpos[j]);
+    const uint32_t cmask = (uint32_t)sc((int)rec->cmask), cval = (uint32_t)sc((int)rec->cval);
+    const bool grad = sc(rec->slot) >= 0;
+    const LdsGeom<K> g = lds_geom<K>(tpos);
     const double* Mr = m + 2 * DD;
     const double* Mi = m + 3 * DD;
     double acc = 0;
     for (int gidx = th; gidx < (1 << (t - K)); gidx += nthr) {
         const uint32_t eb = lds_base<K>((uint32_t)gidx, g);
-        if ((eb & op.cmask) != op.cval) continue;
+        if ((eb & cmask) != cval) continue;
         double2 p[D], l[D];
 #pragma unroll
         for (int s = 0; s < D; ++s) {
@@ -373,7 +418,7 @@ __device__ __noinline__ double lds_op_bwd(double2* lp, vec2_t<RL>* ll, const POp
             const VL w = ll[swz(eb | g.off[s])];
             l[s] = make_double2((double)w.x, (double)w.y);
         }
-        if (op.slot >= 0) {
+        if (grad) {
 #pragma unroll
             for (int r = 0; r < D; ++r) {
                 double x = 0, y = 0;
@@ -414,8 +459,11 @@ __global__ __launch_bounds__(512) void k_pass_fwd(PassArgs a)
     const int nthr = 1 << (t - RB);
     const int th = threadIdx.x;
     VP* lp = (VP*)smem;
+    POp* lops = (POp*)(smem + (sizeof(VP) << t));
+    PGroupDesc* lgrp = (PGroupDesc*)(lops + kMaxPassOps);
     const TileCtx tc = tile_ctx<RB>(a, th);
     VP* gp = (VP*)a.psi;
+    stage_program(a, lops, lgrp, th, nthr);
 #pragma unroll
     for (int r = 0; r < N; ++r) {
         VP v = mkv<VP, RP>((RP)0, (RP)0);
@@ -425,33 +473,34 @@ __global__ __launch_bounds__(512) void k_pass_fwd(PassArgs a)
     __syncthreads();
 
     for (int gi = 0; gi < a.ngroups; ++gi) {
-        const PGroupDesc G = as_const(a.groups)[a.group0 + gi];
+        const GroupCtl G = group_ctl(lgrp[gi]);
         if (G.lds) {
-            const POp op = as_const(a.ops)[G.op0];
-            if ((tc.base & op.omask) == op.oval) {
-                if (op.k == 2) lds_op_fwd<RP, 2>(lp, a.ops + G.op0, a.mats + op.mat, t, th, nthr);
-                else lds_op_fwd<RP, 3>(lp, a.ops + G.op0, a.mats + op.mat, t, th, nthr);
+            const POp* rec = lops + G.op0;
+            const uint64_t omask = sc64(rec->omask), oval = sc64(rec->oval);
+            if ((tc.base & omask) == oval) {
+                const double* m = a.mats + sc(rec->mat);
+                if (sc(rec->k) == 2) lds_op_fwd<RP, 2>(lp, rec, m, t, th, nthr);
+                else lds_op_fwd<RP, 3>(lp, rec, m, t, th, nthr);
             }
             __syncthreads();
             continue;
         }
         uint32_t ethr, er[N];
-        group_index<RB>(G, t, th, ethr, er);
+        group_index<RB>(G.rpos, t, th, ethr, er);
         VP x[N];
 #pragma unroll
         for (int r = 0; r < N; ++r) x[r] = lp[swz(ethr | er[r])];
-        // The next op's record is fetched before the current op computes.
-        POp op = as_const(a.ops)[G.op0];
+        POp raw = lops[G.op0];
         for (int oi = 0; oi < G.nops; ++oi) {
-            POp nxt;
-            if (oi + 1 < G.nops) nxt = as_const(a.ops)[G.op0 + oi + 1];
-            if ((tc.base & op.omask) == op.oval) {
-                RP mr[4], mi[4];
+            const OpCtl op = op_ctl(raw);
+            RP mr[4], mi[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    mr[q] = (RP)op.u[q];
-                    mi[q] = (RP)op.u[4 + q];
-                }
+            for (int q = 0; q < 4; ++q) {
+                mr[q] = (RP)raw.u[q];
+                mi[q] = (RP)raw.u[4 + q];
+            }
+            if (oi + 1 < G.nops) raw = lops[G.op0 + oi + 1];  // next record, in flight during this op
+            if ((tc.base & op.omask) == op.oval) {
 #define YAO_FWD_CASE(J)                                                                       \
     case J:                                                                                   \
         if (op.cmask) op_apply<J, true, RP>(x, op.type, mr, mi, ethr, er, op.cmask, op.cval); \
@@ -460,7 +509,6 @@ __global__ __launch_bounds__(512) void k_pass_fwd(PassArgs a)
                 switch (op.rpos) { YAO_FWD_CASE(0) YAO_FWD_CASE(1) YAO_FWD_CASE(2) YAO_FWD_CASE(3) }
 #undef YAO_FWD_CASE
             }
-            op = nxt;
         }
 #pragma unroll
         for (int r = 0; r < N; ++r) lp[swz(ethr | er[r])] = x[r];
@@ -487,9 +535,12 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
     VL* ll = (VL*)(smem + ((size_t)16 << t));
     double* red = (double*)(smem + ((size_t)(16 + sizeof(VL)) << t));
     int* sl = (int*)(red + kMaxGroupSlots * nthr);
+    POp* lops = (POp*)(sl + 16);
+    PGroupDesc* lgrp = (PGroupDesc*)(lops + kMaxPassOps);
     const TileCtx tc = tile_ctx<RB>(a, th);
     double2* gp = (double2*)a.psi;
     VL* gl = (VL*)a.lam;
+    stage_program(a, lops, lgrp, th, nthr);
 #pragma unroll
     for (int r = 0; r < N; ++r) {
         double2 v = make_double2(0.0, 0.0);
@@ -506,27 +557,30 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
     __syncthreads();
 
     for (int gi = 0; gi < a.ngroups; ++gi) {
-        const PGroupDesc G = as_const(a.groups)[a.group0 + gi];
+        const GroupCtl G = group_ctl(lgrp[gi]);
         if (G.lds) {
-            const POp op = as_const(a.ops)[G.op0];
+            const POp* rec = lops + G.op0;
+            const uint64_t omask = sc64(rec->omask), oval = sc64(rec->oval);
+            const int slot = sc(rec->slot);
             double g = 0;
-            if ((tc.base & op.omask) == op.oval) {
-                if (op.k == 2) g = lds_op_bwd<RL, 2>(lp, ll, a.ops + G.op0, a.mats + op.mat, t, th, nthr);
-                else g = lds_op_bwd<RL, 3>(lp, ll, a.ops + G.op0, a.mats + op.mat, t, th, nthr);
+            if ((tc.base & omask) == oval) {
+                const double* m = a.mats + sc(rec->mat);
+                if (sc(rec->k) == 2) g = lds_op_bwd<RL, 2>(lp, ll, rec, m, t, th, nthr);
+                else g = lds_op_bwd<RL, 3>(lp, ll, rec, m, t, th, nthr);
             }
-            if (op.slot >= 0) {
+            if (slot >= 0) {
                 red[th] = g;
-                if (th == 0) sl[0] = op.slot;
+                if (th == 0) sl[0] = slot;
             }
             __syncthreads();
-            if (op.slot >= 0) {
+            if (slot >= 0) {
                 group_reduce(a.gpartial, a.B, a.pstride, a.c, red, sl, 1, nthr, th);
                 __syncthreads();
             }
             continue;
         }
         uint32_t ethr, er[N];
-        group_index<RB>(G, t, th, ethr, er);
+        group_index<RB>(G.rpos, t, th, ethr, er);
         double2 x[N], y[N];
 #pragma unroll
         for (int r = 0; r < N; ++r) {
@@ -536,16 +590,15 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
             y[r] = make_double2((double)w.x, (double)w.y);
         }
         int nslot = 0;
-        // The next op's record is fetched before the current op computes.
-        POp op = as_const(a.ops)[G.op0];
+        POp raw = lops[G.op0];
         for (int oi = 0; oi < G.nops; ++oi) {
-            POp nxt;
-            if (oi + 1 < G.nops) nxt = as_const(a.ops)[G.op0 + oi + 1];
+            const OpCtl op = op_ctl(raw);
+            double m[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) m[q] = raw.u[q];
+            if (oi + 1 < G.nops) raw = lops[G.op0 + oi + 1];  // next record, in flight during this op
             double g = 0;
             if ((tc.base & op.omask) == op.oval) {
-                double m[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) m[q] = op.u[q];
                 const double* gm = a.mats + op.mat + 8;  // M of a dense generator
 #define YAO_BWD_CASE(J)                                                                                       \
     case J:                                                                                                   \
@@ -567,7 +620,6 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
                 if (th == 0) sl[nslot] = op.slot;
                 ++nslot;
             }
-            op = nxt;
         }
 #pragma unroll
         for (int r = 0; r < N; ++r) {
@@ -605,31 +657,44 @@ template <typename K> int set_lds_limit(K kernel)
 
 }  // namespace
 
+// Raise the dynamic LDS limit of every pass kernel ahead of a graph capture.
+int prepare_pass_kernels()
+{
+    YAO_TRY(set_lds_limit(k_pass_fwd<float>));
+    YAO_TRY(set_lds_limit(k_pass_fwd<double>));
+    YAO_TRY(set_lds_limit(k_pass_bwd<float>));
+    YAO_TRY(set_lds_limit(k_pass_bwd<double>));
+    return 0;
+}
+
 size_t pass_lds_bytes(bool bwd, int t, int psi_bytes, int lam_bytes)
 {
-    if (!bwd) return (size_t)psi_bytes << t;
+    const size_t prog = (sizeof(POp) + sizeof(PGroupDesc)) * kMaxPassOps;
+    if (!bwd) return ((size_t)psi_bytes << t) + prog;
     const size_t nthr = size_t(1) << (t - kRegBitsBwd);
-    return ((size_t)(16 + lam_bytes) << t) + sizeof(double) * kMaxGroupSlots * nthr + sizeof(int) * kMaxGroupSlots;
+    return ((size_t)(16 + lam_bytes) << t) + sizeof(double) * kMaxGroupSlots * nthr + sizeof(int) * 16 + prog;
 }
 
 int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, const POp* ops, const PGroupDesc* groups,
                 const double* mats, double* gpartial, int pstride, int n, int B, int c, int t, int group0,
-                int ngroups, const std::vector<int>& tile_qubits, double flops)
+                int ngroups, const std::vector<int>& tile_qubits, double flops, int op_first, int nops)
 {
+    if (nops > kMaxPassOps || ngroups > kMaxPassOps)
+        return set_error(YAO_EINVAL, "pass of %d ops exceeds the staged program size", nops);
     PassArgs a;
     memset(&a, 0, sizeof(a));
     a.psi = psi;
     a.lam = lam;
-    a.ops = ops;
-    a.groups = groups;
+    a.ops = ops + op_first;
+    a.groups = groups + group0;
     a.mats = mats;
     a.gpartial = gpartial;
     a.n = n;
     a.B = B;
     a.c = c;
     a.t = t;
-    a.group0 = group0;
     a.ngroups = ngroups;
+    a.nops = nops;
     a.ntq = (int)tile_qubits.size();
     uint64_t T = 0;
     for (int j = 0; j < a.ntq; ++j) {

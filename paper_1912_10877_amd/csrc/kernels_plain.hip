@@ -285,6 +285,32 @@ __global__ __launch_bounds__(kThreads) void k_maxdiff(const vec2_t<RA>* __restri
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// <a_b|b_b> per batch slot: real parts to partial[b][blk], imaginary parts to
+// partial[B + b][blk].
+template <typename RA, typename RB>
+__global__ __launch_bounds__(kThreads) void k_inner(const vec2_t<RA>* __restrict__ a, const vec2_t<RB>* __restrict__ b,
+                                                    uint64_t rows, int B, int logBc, double* __restrict__ partial)
+{
+    __shared__ double red[kThreads];
+    const int bb = threadIdx.x & ((1 << logBc) - 1);
+    const int s = blockIdx.y * (1 << logBc) + bb;
+    const int rpb = kThreads >> logBc;
+    double re = 0, im = 0;
+    if (s < B) {
+        for (uint64_t i = (uint64_t)blockIdx.x * rpb + (threadIdx.x >> logBc); i < rows; i += (uint64_t)gridDim.x * rpb) {
+            const vec2_t<RA> u = a[i * B + s];
+            const vec2_t<RB> v = b[i * B + s];
+            re += (double)u.x * v.x + (double)u.y * v.y;
+            im += (double)u.x * v.y - (double)u.y * v.x;
+        }
+    }
+    double r1 = block_sum_by_slot(re, logBc, red);
+    if ((int)threadIdx.x < (1 << logBc) && s < B) partial[(uint64_t)s * gridDim.x + blockIdx.x] = r1;
+    __syncthreads();
+    double r2 = block_sum_by_slot(im, logBc, red);
+    if ((int)threadIdx.x < (1 << logBc) && s < B) partial[(uint64_t)(B + s) * gridDim.x + blockIdx.x] = r2;
+}
+
 // -------------------------------------------------------------------------------- adjoint step
 // One gate of the reverse sweep (eq. apply-back): gradient partial 2 Re <lam|M|psi> over the
 // controlled subspace, then psi <- Ud psi (FP64) and lam <- Ud lam. Rows are pair rows.
@@ -416,6 +442,10 @@ int gate_typed(void* data, int n, int B, const HostMat& U, const int* locs, Ctrl
         YAO_HIP(hipGetLastError());
         return 0;
     }
+    if constexpr (sizeof(R) == 4) {
+        // Dense 4- and 5-qubit blocks on complex64 states go to the FP32 matrix cores.
+        if (options().mfma && mfma_supported(k, n, B)) return launch_dense_mfma((float2*)data, n, B, U, locs, c, dev_mat);
+    }
     // k >= 2: the matrix, rounded once to R (re block then im block), lives in device memory.
     const size_t dd = size_t(1) << (2 * k);
     const R* dm = (const R*)dev_mat;
@@ -469,6 +499,28 @@ int launch_fill_basis(void* data, int dtype, int n, int B)
 int launch_reset(yao_state* s)
 {
     return launch_fill_basis(s->data, s->dtype, s->n, s->batch);
+}
+
+size_t encode_gate_matrix(int dtype, int n, int B, const HostMat& U, std::vector<double>& pool)
+{
+    pool.resize((pool.size() + 3) & ~size_t(3));  // 32-byte aligned within the pool
+    const size_t off = pool.size();
+    const size_t dd = size_t(1) << (2 * U.k);
+    if (dtype == YAO_C64 && options().mfma && mfma_supported(U.k, n, B)) {
+        pool.resize(off + 2 * dd);  // 4 dd floats
+        mfma_encode(U, (float*)(pool.data() + off));
+    } else if (dtype == YAO_C64) {
+        pool.resize(off + dd);  // 2 dd floats
+        float* f = (float*)(pool.data() + off);
+        for (size_t t = 0; t < dd; ++t) {
+            f[t] = (float)U.re[t];
+            f[dd + t] = (float)U.im[t];
+        }
+    } else {
+        pool.insert(pool.end(), U.re.begin(), U.re.end());
+        pool.insert(pool.end(), U.im.begin(), U.im.end());
+    }
+    return off;
 }
 
 int launch_gate(void* data, int dtype, int n, int B, const HostMat& U, const int* locs, CtrlSpec c, const void* dev_mat)
@@ -589,6 +641,37 @@ int launch_hpsi(const void* data, int dtype, void* out, int out_dtype, int n, in
     return finish_slot_sums(partial, B, nbx, energy_host);
 }
 
+size_t hpsi_partial_doubles(int n, int B)
+{
+    BatchGeom bg = make_batch_geom(B);
+    return (size_t)B * reduce_grid_x(uint64_t(1) << n, bg.logBc);
+}
+
+// H psi with the energy left in device memory (energy_dev[b]); nothing synchronises, so the
+// launches can be captured in a graph. partial holds hpsi_partial_doubles(n, B) doubles.
+int launch_hpsi_dev(const void* data, int dtype, void* out, int out_dtype, int n, int B, const yao_pauli_sum* h,
+                    double* partial, double* energy_dev)
+{
+    if (!h->d_groups) return set_error(YAO_EINVAL, "observable tables not uploaded");
+    BatchGeom bg = make_batch_geom(B);
+    const uint64_t rows = uint64_t(1) << n;
+    const int nbx = reduce_grid_x(rows, bg.logBc);
+    dim3 grid(nbx, bg.nchunks);
+    const PGroup* G = (const PGroup*)h->d_groups;
+    const PTerm* T = (const PTerm*)h->d_terms;
+    hipStream_t st = stream();
+    if (dtype == YAO_C64 && out_dtype == YAO_C64)
+        k_hpsi<float, float><<<grid, kThreads, 0, st>>>((const float2*)data, (float2*)out, rows, B, bg.logBc, G, h->ngroups, T, partial);
+    else if (dtype == YAO_C64)
+        k_hpsi<float, double><<<grid, kThreads, 0, st>>>((const float2*)data, (double2*)out, rows, B, bg.logBc, G, h->ngroups, T, partial);
+    else if (out_dtype == YAO_C64)
+        k_hpsi<double, float><<<grid, kThreads, 0, st>>>((const double2*)data, (float2*)out, rows, B, bg.logBc, G, h->ngroups, T, partial);
+    else
+        k_hpsi<double, double><<<grid, kThreads, 0, st>>>((const double2*)data, (double2*)out, rows, B, bg.logBc, G, h->ngroups, T, partial);
+    YAO_HIP(hipGetLastError());
+    return launch_row_sums(partial, B, nbx, energy_dev);
+}
+
 int launch_convert(const void* src, int src_dtype, void* dst, int dst_dtype, size_t elems)
 {
     unsigned nb = (unsigned)std::min<uint64_t>((elems + kThreads - 1) / kThreads, 65536);
@@ -602,6 +685,33 @@ int launch_convert(const void* src, int src_dtype, void* dst, int dst_dtype, siz
     else
         k_convert<double, double><<<nb, kThreads, 0, st>>>((const double2*)src, (double2*)dst, elems);
     YAO_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_inner(const void* a, int a_dtype, const void* b, int b_dtype, int n, int B, double* re, double* im)
+{
+    BatchGeom bg = make_batch_geom(B);
+    const uint64_t rows = uint64_t(1) << n;
+    const int nbx = reduce_grid_x(rows, bg.logBc);
+    double* partial = (double*)workspace(WS_PARTIAL, sizeof(double) * 2 * (size_t)B * nbx);
+    if (!partial) return YAO_ENOMEM;
+    dim3 grid(nbx, bg.nchunks);
+    hipStream_t st = stream();
+    if (a_dtype == YAO_C64 && b_dtype == YAO_C64)
+        k_inner<float, float><<<grid, kThreads, 0, st>>>((const float2*)a, (const float2*)b, rows, B, bg.logBc, partial);
+    else if (a_dtype == YAO_C64)
+        k_inner<float, double><<<grid, kThreads, 0, st>>>((const float2*)a, (const double2*)b, rows, B, bg.logBc, partial);
+    else if (b_dtype == YAO_C64)
+        k_inner<double, float><<<grid, kThreads, 0, st>>>((const double2*)a, (const float2*)b, rows, B, bg.logBc, partial);
+    else
+        k_inner<double, double><<<grid, kThreads, 0, st>>>((const double2*)a, (const double2*)b, rows, B, bg.logBc, partial);
+    YAO_HIP(hipGetLastError());
+    std::vector<double> both(2 * (size_t)B);
+    YAO_TRY(finish_slot_sums(partial, 2 * B, nbx, both.data()));
+    for (int s = 0; s < B; ++s) {
+        re[s] = both[s];
+        im[s] = both[B + s];
+    }
     return 0;
 }
 
@@ -715,9 +825,10 @@ int launch_adjoint_step(double* psi, void* lam, int lam_dtype, int n, int B, con
 
 // Same, with the per-slot partial rows pstride apart (pstride >= the launch's block count).
 int launch_adjoint_step_strided(double* psi, void* lam, int lam_dtype, int n, int B, const HostMat& Ud,
-                                const HostMat* M, const int* locs, CtrlSpec c, double* partial, int pstride)
+                                const HostMat* M, const int* locs, CtrlSpec c, const double* dev_mats, double* partial,
+                                int pstride)
 {
-    return adjoint_step_impl(psi, lam, lam_dtype, n, B, Ud, M, locs, c, nullptr, partial, pstride);
+    return adjoint_step_impl(psi, lam, lam_dtype, n, B, Ud, M, locs, c, dev_mats, partial, pstride);
 }
 
 int launch_fill(double* p, size_t count, double v)

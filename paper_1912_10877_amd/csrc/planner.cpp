@@ -18,9 +18,13 @@ static int popc(uint64_t v)
 
 void tile_geometry(int n, int B, int dtype, bool backward, int* t, int* cbits, int* low_fixed)
 {
+    tile_geometry_tq(n, B, dtype, backward, options().tile_qubits, t, cbits, low_fixed);
+}
+
+void tile_geometry_tq(int n, int B, int dtype, bool backward, int tq, int* t, int* cbits, int* low_fixed)
+{
     const int lb = ilog2_ceil((uint64_t)B);
     const int c = lb < 3 ? lb : 3;
-    int tq = options().tile_qubits;
     if (tq <= 0) tq = 12 - c;
     if (tq < kMaxRegBits + 1) tq = kMaxRegBits + 1;
     int tt = c + std::min(tq, n);
@@ -87,7 +91,7 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
         for (int oi : remaining) {
             const HostOp& op = P.ops[oi];
             const int k = circ->gates[op.gate].k;
-            if ((op.qmask & blocked) || k > kMaxFusedK) {
+            if ((op.qmask & blocked) || k > kMaxFusedK || (int)sel.size() >= kMaxPassOps) {
                 blocked |= op.qmask;
                 rest.push_back(oi);
                 continue;

@@ -61,6 +61,7 @@ void default_options(yao_options& o)
     o.checkpoint_every = 0;
     o.drift_tol = 0.0;
     o.mfma = 1;
+    o.autotune = 1;
 }
 
 int ensure_device()
@@ -330,9 +331,16 @@ int prof_enable(bool on)
     return 0;
 }
 
+static bool g_prof_suspended = false;
+
+void prof_suspend(bool on)
+{
+    g_prof_suspended = on;
+}
+
 int prof_begin(int family)
 {
-    if (!g_prof_on) return -1;
+    if (!g_prof_on || g_prof_suspended) return -1;
     if (g_prof_next_ev + 2 > g_prof_events.size()) {
         for (int i = 0; i < 256; ++i) {
             hipEvent_t e;

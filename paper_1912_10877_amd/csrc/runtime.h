@@ -88,13 +88,23 @@ int launch_fill_basis(void* data, int dtype, int n, int B);
 // type) or, when dev_mat is null, from a ring upload.
 int launch_gate(void* data, int dtype, int n, int B, const HostMat& U, const int* locs, CtrlSpec c,
                 const void* dev_mat = nullptr);
+// Device form of a k >= 2 matrix as launch_gate reads it from dev_mat for this state (the FP32
+// real form of the matrix-core path, else re block then im block in the state's real type),
+// appended to pool (8-byte words); returns its offset in words.
+size_t encode_gate_matrix(int dtype, int n, int B, const HostMat& U, std::vector<double>& pool);
 // energy[b] (host) = Re <psi|H|psi>.
 int launch_expect(const void* data, int dtype, int n, int B, yao_pauli_sum* h, double* energy_host);
 // out = H psi; energy[b] (host, may be null) from the same pass. out_dtype may differ.
 int launch_hpsi(const void* data, int dtype, void* out, int out_dtype, int n, int B, yao_pauli_sum* h,
                 double* energy_host);
+// The same with the energy left on the device and no synchronisation (graph-capturable).
+size_t hpsi_partial_doubles(int n, int B);
+int launch_hpsi_dev(const void* data, int dtype, void* out, int out_dtype, int n, int B, const yao_pauli_sum* h,
+                    double* partial, double* energy_dev);
 // Precision conversion / copies between states of equal shape.
 int launch_convert(const void* src, int src_dtype, void* dst, int dst_dtype, size_t elems);
+// <a_b|b_b> per batch slot (host results), FP64 accumulation.
+int launch_inner(const void* a, int a_dtype, const void* b, int b_dtype, int n, int B, double* re, double* im);
 // max |a - b| over the elements (host result).
 int launch_maxdiff(const void* a, int a_dtype, const void* b, int b_dtype, size_t elems, double* out);
 
@@ -105,11 +115,21 @@ int launch_maxdiff(const void* a, int a_dtype, const void* b, int b_dtype, size_
 int launch_adjoint_step(double* psi, void* lam, int lam_dtype, int n, int B, const HostMat& Ud, const HostMat* M,
                         const int* locs, CtrlSpec c, const double* dev_mats, double* partial, int* nblk);
 int adjoint_nblk(int n, int k, int B);
+// The same with the per-slot partial rows pstride apart (pstride >= the launch's block count).
+int launch_adjoint_step_strided(double* psi, void* lam, int lam_dtype, int n, int B, const HostMat& Ud,
+                                const HostMat* M, const int* locs, CtrlSpec c, const double* dev_mats, double* partial,
+                                int pstride);
 // sums[r] = sum_j partial[r * nblk + j] for r < rows (device), sequential per row.
 int launch_row_sums(const double* partial, int rows, int nblk, double* sums);
 
 // Pauli tables
 int pauli_upload(yao_pauli_sum* h);
+
+// Dense 4/5-qubit gates on complex64 states through the FP32 matrix cores.
+bool mfma_supported(int k, int n, int B);
+void mfma_encode(const HostMat& U, float* out);  // 4 * 4^k floats
+int launch_dense_mfma(float2* psi, int n, int B, const HostMat& U, const int* locs, CtrlSpec c,
+                      const void* dev_mat = nullptr);
 
 // ---------------------------------------------------------------------------- profiler
 // prof_begin records a start event for a launch of `family` when profiling is on (returns
@@ -117,6 +137,8 @@ int pauli_upload(yao_pauli_sum* h);
 int prof_begin(int family);
 void prof_end(int idx, double bytes, double flops);
 int prof_enable(bool on);
+// While suspended (graph capture), prof_begin records nothing.
+void prof_suspend(bool on);
 int prof_read(int family, int* launches, double* total_ms, double* bytes, double* flops);
 
 }  // namespace yao

@@ -1,0 +1,174 @@
+"""GPU parity of the graph-recorded batch of uneven circuits (yao_batch_run) against the oracle:
+energies and every gradient per circuit, replays with new parameters, autotuned and forced
+fusion widths, re-recording after a circuit changes, and the full 1024-circuit workload on
+sampled circuits."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+yb = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    global yb
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1912_10877_amd import binding
+
+    yb = binding
+    yb.init()
+    yield
+    yb.set_options(plain=0, tile_qubits=0, fuse_width=1, autotune=1)
+
+
+def tol(dtype):
+    # complex64 sweeps: |dE| <= 1e-5 and gradients within 1e-4 of the largest component;
+    # complex128: rounding of FP64 arithmetic over a few hundred gates.
+    return (1e-5, 1e-4) if dtype == 0 else (1e-10, 1e-9)
+
+
+def make_batch(spec, dtype):
+    states, circs, hams, params, refs = [], [], [], [], []
+    for n, d, seed in spec:
+        c = w.hea_circuit(n, d)
+        H = w.heisenberg(n)
+        states.append(yb.State(n, 1, dtype))
+        circs.append(yb.Circuit.from_workload(c))
+        hams.append(yb.PauliSum.from_workload(H))
+        params.append(w.angles(seed, c.nparams))
+        refs.append((c, H))
+    return states, circs, hams, params, refs
+
+
+def check(e, g, params, refs, dtype, which=None):
+    te, tg = tol(dtype)
+    for i in (range(len(refs)) if which is None else which):
+        c, H = refs[i]
+        e_ref, g_ref, _ = oracle.adjoint(H, c, params[i], w.zero_state(c.n))
+        assert abs(e[i] - e_ref[0]) <= te, (i, c.n, e[i], e_ref[0])
+        scale = max(1.0, float(np.abs(g_ref[0]).max()))
+        err = float(np.abs(g[i] - g_ref[0]).max())
+        assert err <= tg * scale, (i, c.n, err)
+
+
+SMALL = w.hetero_batch_spec(ncirc=24, seed=7, nmin=5, nmax=11, dmin=1, dmax=4)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_uneven_batch_matches_oracle(dtype):
+    states, circs, hams, params, refs = make_batch(SMALL, dtype)
+    e, g = yb.batch_run(states, circs, params, hams)
+    check(e, g, params, refs, dtype)
+
+
+def test_replays_with_new_parameters_and_eager_work_between():
+    """The recorded graph is replayed with new angles; eager work on the bound stream runs
+    between the replays; every replay matches the oracle."""
+    states, circs, hams, params, refs = make_batch(SMALL[:10], 0)
+    other = yb.State(9, 2, 0)
+    H9 = yb.PauliSum.from_workload(w.heisenberg(9))
+    for r in range(3):
+        ps = [w.angles(5000 + 37 * r + i, len(p)) for i, p in enumerate(params)]
+        e, g = yb.batch_run(states, circs, ps, hams)
+        check(e, g, ps, [refs[i] for i in range(len(refs))], 0)
+        yb.expect(other, H9)  # eager work between replays
+        # the state of every circuit ends holding its output
+        c0, _ = refs[0]
+        out = states[0].download()
+        ref = oracle.forward(c0, ps[0], w.zero_state(c0.n))
+        assert np.abs(out - ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("width,tq", [(2, 6), (3, 0), (4, 7), (5, 0)])
+def test_forced_fusion_width_and_tile(width, tq):
+    """Fusion widths 4 and 5 put standalone dense blocks (matrix cores for complex64) into the
+    graph; their matrices come from the uploaded program."""
+    yb.set_options(autotune=0, fuse_width=width, tile_qubits=tq)
+    try:
+        spec = [(n, d, 300 + i) for i, (n, d) in enumerate([(6, 2), (9, 3), (10, 2), (13, 2), (8, 4)])]
+        states, circs, hams, params, refs = make_batch(spec, 0)
+        e, g = yb.batch_run(states, circs, params, hams)
+        check(e, g, params, refs, 0)
+        ps = [w.angles(77 + i, len(p)) for i, p in enumerate(params)]
+        e, g = yb.batch_run(states, circs, ps, hams)
+        check(e, g, ps, refs, 0)
+    finally:
+        yb.set_options(autotune=1, fuse_width=1, tile_qubits=0)
+
+
+def test_autotuned_equals_untuned():
+    spec = [(14, 3, 11), (12, 5, 12), (7, 2, 13)]
+    states, circs, hams, params, refs = make_batch(spec, 0)
+    e1, g1 = yb.batch_run(states, circs, params, hams)
+    yb.set_options(autotune=0)
+    try:
+        e2, g2 = yb.batch_run(states, circs, params, hams)
+    finally:
+        yb.set_options(autotune=1)
+    assert np.abs(np.array(e1) - np.array(e2)).max() <= 2e-5
+    for a, b in zip(g1, g2):
+        assert np.abs(a - b).max() <= 2e-4 * max(1.0, float(np.abs(b).max()))
+    check(e1, g1, params, refs, 0)
+
+
+def test_changed_circuit_is_recorded_anew():
+    spec = [(6, 2, 21), (8, 2, 22)]
+    states, circs, hams, params, refs = make_batch(spec, 1)
+    e, g = yb.batch_run(states, circs, params, hams)
+    check(e, g, params, refs, 1)
+    # Append one more parametrised layer to circuit 1 (same parameter indices reused).
+    c1, H1 = refs[1]
+    extra = w.Circuit(c1.n, list(c1.gates) + [w.Gate("Ry", (3,), param=0)], c1.nparams)
+    circs[1].push("Ry", (3,), param=0)
+    refs[1] = (extra, H1)
+    e, g = yb.batch_run(states, circs, params, hams)
+    check(e, g, params, refs, 1)
+
+
+def test_circuit_without_parameters_and_observable_only():
+    c = w.ghz_circuit(7)
+    H = w.heisenberg(7)
+    s = yb.State(7, 1, 1)
+    e, g = yb.batch_run([s], [yb.Circuit.from_workload(c)], [np.zeros(0)], [yb.PauliSum.from_workload(H)])
+    e_ref = oracle.energy(H, c, [], w.zero_state(7))
+    assert abs(e[0] - e_ref[0]) <= 1e-12
+    assert len(g[0]) == 0
+
+
+def test_rejects_unsupported_states():
+    c = w.hea_circuit(4, 1)
+    s = yb.State(4, 1, 0)
+    with pytest.raises(RuntimeError):
+        yb.batch_run([s], [yb.Circuit.from_workload(c)], [w.angles(1, c.nparams)],
+                     [yb.PauliSum.from_workload(w.heisenberg(4))])
+    c6 = w.hea_circuit(6, 1)
+    s2 = yb.State(6, 2, 0)
+    with pytest.raises(RuntimeError):
+        yb.batch_run([s2], [yb.Circuit.from_workload(c6)], [w.angles(1, c6.nparams)],
+                     [yb.PauliSum.from_workload(w.heisenberg(6))])
+
+
+def test_full_1024_circuit_workload_sampled():
+    """1024 circuits, qubits uniform in 8..20 and depth in 4..16: sampled circuits against the
+    oracle, every circuit against its own eager fused backward."""
+    spec = w.hetero_batch_spec()
+    states, circs, hams, params, refs = make_batch(spec, 0)
+    e, g = yb.batch_run(states, circs, params, hams)
+    e2, g2 = yb.batch_run(states, circs, params, hams)  # replay
+    assert np.array_equal(np.array(e), np.array(e2))
+    for a, b in zip(g, g2):
+        assert np.array_equal(a, b)
+    small = [i for i, (n, d, _) in enumerate(spec) if n <= 12]
+    big = [i for i, (n, d, _) in enumerate(spec) if n >= 16]
+    check(e, g, params, refs, 0, which=small[:6] + big[:1])
+    for i in range(0, len(spec), 16):
+        states[i].reset()
+        ee, gg, _ = yb.backward(states[i], circs[i], params[i], hams[i])
+        assert abs(ee[0] - e[i]) <= 2e-5
+        assert np.abs(gg[0] - g[i]).max() <= 2e-4 * max(1.0, float(np.abs(gg).max()))

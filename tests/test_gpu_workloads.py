@@ -151,3 +151,60 @@ def test_forward_25q_energy(dtype):
     yb.forward(s, yb.Circuit.from_workload(circ), w.angles(1, circ.nparams))
     e = yb.expect(s, yb.PauliSum.from_workload(w.heisenberg(n)))
     assert abs(e[0] - gold["energy"][0]) <= (1e-9 if dtype == 1 else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("width", [2, 3, 4, 5])
+def test_forward_with_dense_fusion_matches_oracle(dtype, width):
+    """Forward sweeps folding gates into dense blocks of up to `width` qubits (4 and 5 run on
+    FP32 matrix cores for complex64 states)."""
+    yb.set_options(fuse_width=width)
+    try:
+        n = 11
+        circ = w.random_gate_list(n, 70, seed=4000 + width, kmax=3, max_ctrl=2)
+        params = w.angles(width, circ.nparams)
+        psi0 = w.random_state(n, 3, width)
+        s = yb.State(n, 3, dtype)
+        s.upload(psi0)
+        yb.forward(s, yb.Circuit.from_workload(circ), params)
+        want = oracle.forward(circ, params, psi0)
+        tol = 1e-11 if dtype == 1 else 2e-5
+        assert np.abs(s.download() - want).max() <= tol
+    finally:
+        yb.set_options(fuse_width=1)
+
+
+@pytest.mark.parametrize("mfma", [1, 0])
+def test_random_circuit_20q_fused_5q_blocks(mfma):
+    """Precision workload family at 20 qubits with 5-qubit fusion on complex64 (matrix cores
+    when mfma = 1) against the oracle's observables, and its fidelity with the complex128
+    unfused path."""
+    gold = golden("rand20_observables.txt")
+    n = 20
+    circ = yb.Circuit.from_workload(w.random_circuit(n, 24, seed=5))
+    ref = yb.State(n, 1, 1)
+    yb.forward(ref, circ, [])
+    yb.set_options(fuse_width=5, mfma=mfma)
+    try:
+        s = yb.State(n, 1, 0)
+        yb.forward(s, circ, [])
+    finally:
+        yb.set_options(fuse_width=1, mfma=1)
+    zz = yb.PauliSum.from_workload(w.pauli_sum(n, [(1.0, "ZZ" + "I" * (n - 2))]))
+    assert abs(yb.expect(s, zz)[0] - gold["zz01"][0]) <= 2e-5
+    assert abs(yb.expect(ref, zz)[0] - gold["zz01"][0]) <= 1e-10
+    fid = abs(yb.inner(ref, s)[0]) ** 2
+    assert fid >= 1 - 1e-5
+    assert abs(abs(yb.inner(ref, ref)[0]) - 1) <= 1e-12
+
+
+def test_inner_product_matches_numpy():
+    n, B = 9, 4
+    a = w.random_state(n, B, 1)
+    b = w.random_state(n, B, 2)
+    sa, sb = yb.State(n, B, 1), yb.State(n, B, 0)
+    sa.upload(a)
+    sb.upload(b)
+    got = yb.inner(sa, sb)
+    want = np.sum(a.conj() * b.astype(np.complex64).astype(np.complex128), axis=0)
+    np.testing.assert_allclose(got, want, atol=1e-12)
