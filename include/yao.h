@@ -78,7 +78,11 @@ enum yao_grad_mode { YAO_GRAD_REVERSIBLE = 0, YAO_GRAD_CHECKPOINT = 1, YAO_GRAD_
 /* Execution options (process-wide; set before the calls they should affect).
  *   plain            1: one kernel launch per gate (the per-gate form); 0: fused tile passes.
  *   tile_qubits      qubits per fused tile (0 = chosen by the library or the autotuner).
- *   fuse_width       widest host-fused dense block, 1..5 (1 = no dense fusion).
+ *   fuse_width       fusion of forward sweeps (yao_forward, the forward sweep of a
+ *                    REVERSIBLE yao_backward, yao_batch_run) when autotune is 0: 0 = none,
+ *                    1 = runs of one-qubit gates on one qubit merged into one matrix,
+ *                    2..5 = gates folded into dense blocks of up to that many qubits (the
+ *                    reverse sweep always takes the gates one by one).
  *   checkpoint_every gates per segment in CHECKPOINT / AUTO mode (0 = max(sqrt(#gates), 4n)).
  *   drift_tol        max |psi_uncomputed - psi_stored| accepted by AUTO before falling back
  *                    (0 = 1e-5 for complex64 states, 1e-10 for complex128). In REVERSIBLE
@@ -87,9 +91,13 @@ enum yao_grad_mode { YAO_GRAD_REVERSIBLE = 0, YAO_GRAD_CHECKPOINT = 1, YAO_GRAD_
  *                    outputs are still written).
  *   mfma             1: dense blocks of 4 or 5 qubits on complex64 states run on FP32
  *                    matrix cores; 0: on the vector units.
- *   autotune         1: yao_batch_run picks, per qubit count, the fusion width (1..5) of the
- *                    forward sweep and the tile qubits of both sweeps by timing candidates
- *                    when it first sees a batch; 0: it takes fuse_width and tile_qubits. */
+ *   autotune         1 (default): the library picks the fusion width of forward sweeps
+ *                    per circuit and state shape (and, in yao_batch_run, per qubit count
+ *                    together with the tile qubits of both sweeps) by timing the candidates
+ *                    on the device the first time it meets them; the state is restored after
+ *                    the trials. Which candidate wins depends on timings, so results may
+ *                    differ in the last bits between processes. 0: fuse_width and
+ *                    tile_qubits are taken as given. */
 typedef struct {
     int plain;
     int tile_qubits;

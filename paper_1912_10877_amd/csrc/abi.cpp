@@ -4,6 +4,7 @@
 #include <cstdio>
 
 #include "driver.h"
+#include "tuner.h"
 #include "runtime.h"
 
 using namespace yao;
@@ -321,6 +322,7 @@ int yao_circuit_destroy(yao_circuit* c)
 {
     if (!c) return 0;
     drop_batch(c);
+    drop_tuning(c);
     drop_plans(c);
     drop_fused(c);
     delete c;

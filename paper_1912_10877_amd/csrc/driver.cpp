@@ -1,6 +1,7 @@
 // Choice between the per-gate form and the fused tile passes, and batches of circuits.
 #include "driver.h"
 #include "fused.h"
+#include "tuner.h"
 
 namespace yao {
 
@@ -11,14 +12,15 @@ static bool use_fused(const yao_state* s)
 
 int forward(yao_state* s, const yao_circuit* c, const double* params)
 {
-    // Forward-only sweeps may fold runs of gates into dense blocks of up to fuse_width qubits.
-    const int width = options().fuse_width;
-    if (width > 1 && !c->gates.empty()) {
-        c = fused_circuit(c, params, width);
-        params = nullptr;
-    }
-    if (use_fused(s)) return forward_fused(s->data, s->dtype, s->n, s->batch, c, params);
-    return forward_plain(s->data, s->dtype, s->n, s->batch, c, params);
+    // Forward-only sweeps may fold gates into dense blocks (fusion.cpp): at options().fuse_width,
+    // or at the width the autotuner found fastest for this circuit and state shape.
+    const bool fused = use_fused(s);
+    int width = options().fuse_width;
+    if (fused) YAO_TRY(pick_forward_width(c, params, s->data, s->dtype, s->n, s->batch, &width));
+    const double* fp = params;
+    c = forward_circuit(c, params, width, &fp);
+    if (fused) return forward_fused(s->data, s->dtype, s->n, s->batch, c, fp);
+    return forward_plain(s->data, s->dtype, s->n, s->batch, c, fp);
 }
 
 int backward(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h, int mode, bool reduce_batch,

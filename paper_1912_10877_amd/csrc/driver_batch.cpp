@@ -15,6 +15,7 @@
 
 #include "driver.h"
 #include "fused.h"
+#include "tuner.h"
 
 namespace yao {
 
@@ -27,7 +28,7 @@ namespace {
 constexpr int kBanks = 4;  // streams of the graph
 
 struct Tune {
-    int width = 1;  // dense fusion width of the forward sweep
+    int width = 0;  // fusion width of the forward sweep (0: none)
     int tq_f = 0;   // tile qubits of the forward passes (0: default)
     int tq_b = 0;   // of the reverse passes
 };
@@ -143,33 +144,6 @@ int reverse_stride(int n, int dtype, int tq)
     return std::max(1 << (n - (t - cb)), adjoint_nblk(n, 1, 1));
 }
 
-// The circuit the forward sweep of c runs for a fusion width, refreshed for these parameters.
-const yao_circuit* forward_circuit(const yao_circuit* c, const double* params, int width)
-{
-    if (width <= 1 || c->gates.empty()) return c;
-    return fused_circuit(c, params, width);
-}
-
-// A program uploaded to a private buffer (for the autotuner's trial runs).
-struct TrialProgram {
-    char* d = nullptr;
-    DevProgram dp{};
-    ~TrialProgram()
-    {
-        if (d) (void)hipFree(d);
-    }
-    int load(const Program& p, hipStream_t st)
-    {
-        const size_t bytes = program_blob_bytes(p);
-        std::vector<char> h(bytes);
-        YAO_TRY(dev_alloc((void**)&d, bytes));
-        pack_program(p, h.data(), d, dp);
-        YAO_HIP(hipMemcpyAsync(d, h.data(), bytes, hipMemcpyHostToDevice, st));
-        YAO_HIP(hipStreamSynchronize(st));
-        return 0;
-    }
-};
-
 struct TrialBuffers {
     double* psi64 = nullptr;
     void* lam = nullptr;
@@ -185,30 +159,6 @@ struct TrialBuffers {
         if (e) (void)hipFree(e);
     }
 };
-
-// Median of three timed runs of fn (after one untimed run), in milliseconds.
-template <typename F> int time_ms(hipStream_t st, F fn, double* ms)
-{
-    hipEvent_t e0, e1;
-    YAO_HIP(hipEventCreate(&e0));
-    YAO_HIP(hipEventCreate(&e1));
-    int rc = fn();
-    double v[3] = {0, 0, 0};
-    for (int r = 0; r < 3 && !rc; ++r) {
-        if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(YAO_EHIP, "event record");
-        if (!rc) rc = fn();
-        if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = set_error(YAO_EHIP, "event record");
-        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = set_error(YAO_EHIP, "event sync");
-        float f = 0;
-        if (!rc && hipEventElapsedTime(&f, e0, e1) != hipSuccess) rc = set_error(YAO_EHIP, "elapsed time");
-        v[r] = f;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    std::sort(v, v + 3);
-    *ms = v[1];
-    return rc;
-}
 
 // Candidate tile qubit counts of a state: the default, and smaller tiles when the state has
 // more qubits than a tile (more workgroups, more passes).
@@ -229,20 +179,12 @@ int autotune(const yao_circuit* c, const double* params, yao_state* s, yao_pauli
     const int n = s->n, dt = s->dtype;
     set_stream(st);
     const size_t N = size_t(1) << n;
-    // Forward: width x tile.
+    // Forward: fusion width x tile.
     double best_f = 1e300;
-    for (int w = 1; w <= 5; ++w) {
-        if (w > n) break;
+    for (int w = 0; w <= std::min(5, n); ++w) {
         for (int tq : tile_candidates(n, dt, false)) {
-            const yao_circuit* fc = forward_circuit(c, params, w);
-            const double* fp = fc == c ? params : nullptr;
-            const Plan& P = plan_for(fc, n, dt, false, tq);
-            Program prog;
-            YAO_TRY(build_program(P, fc, fp, false, dt, prog));
-            TrialProgram tp;
-            YAO_TRY(tp.load(prog, st));
             double ms = 0;
-            YAO_TRY(time_ms(st, [&] { return launch_forward_passes(P, prog, tp.dp, s->data, dt, n, 1, fc, fp); }, &ms));
+            YAO_TRY(time_forward(c, params, s->data, dt, n, 1, w, tq, &ms));
             if (ms < best_f) {
                 best_f = ms;
                 best->width = w;
@@ -267,14 +209,14 @@ int autotune(const yao_circuit* c, const double* params, yao_state* s, yao_pauli
         Program prog;
         YAO_TRY(build_program(P, c, params, true, dt, prog));
         TrialProgram tp;
-        YAO_TRY(tp.load(prog, st));
+        YAO_TRY(tp.load(prog));
         const int W = reverse_stride(n, dt, tq);
         double ms = 0;
         YAO_TRY(launch_fill_basis(s->data, dt, n, 1));
         YAO_TRY(launch_convert(s->data, dt, tb.psi64, YAO_C128, N));
         YAO_TRY(launch_hpsi_dev(s->data, dt, tb.lam, dt, n, 1, h, tb.hpart, tb.e));
         YAO_TRY(time_ms(
-            st,
+            3,
             [&] {
                 YAO_TRY(launch_fill(tb.gpart, (size_t)nslots * W, 0.0));
                 return launch_backward_passes(P, prog, tp.dp, c, params, tb.psi64, tb.lam, dt, n, 1, tb.gpart, W);
@@ -294,11 +236,11 @@ int build_programs(Cache& C, const double* const* params, bool first)
 {
     for (Item& it : C.items) {
         const double* p = params[it.idx];
-        const yao_circuit* fc = forward_circuit(it.c, p, it.tune.width);
+        const double* fp = nullptr;
+        const yao_circuit* fc = forward_circuit(it.c, p, it.tune.width, &fp);
         if (!first && (fc != it.fc || fc->version != it.fc_version)) return 1;
         it.fc = fc;
         it.fc_version = fc->version;
-        const double* fp = fc == it.c ? p : nullptr;
         if (first) {
             it.fwd = &plan_for(fc, it.s->n, it.s->dtype, false, it.tune.tq_f);
             it.bwd = &plan_for(it.c, it.s->n, it.s->dtype, true, it.tune.tq_b);
@@ -349,7 +291,7 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
     }
     for (auto& kv : rep) {
         Tune t;
-        t.width = std::max(1, C.opt.fuse_width);
+        t.width = C.opt.fuse_width;
         t.tq_f = t.tq_b = C.opt.tile_qubits;
         if (C.opt.autotune) {
             auto f = g_tune.find(kv.first);

@@ -8,6 +8,7 @@
 
 #include "driver.h"
 #include "fused.h"
+#include "tuner.h"
 
 namespace yao {
 
@@ -354,7 +355,16 @@ int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao
         ckpt = (char*)workspace(WS_CKPT, s->bytes() * (size_t)(nseg - 1));
         if (!ckpt) return YAO_ENOMEM;
     }
-    for (int sg = 0; sg < nseg; ++sg) {
+    if (nseg == 1) {
+        // One segment: the forward sweep only has to produce the final state, so it may run
+        // with gates folded into dense blocks; the reverse sweep still takes them one by one.
+        int width = 0;
+        YAO_TRY(pick_forward_width(c, params, s->data, s->dtype, n, B, &width));
+        const double* fp = params;
+        const yao_circuit* fc = forward_circuit(c, params, width, &fp);
+        YAO_TRY(forward_fused(s->data, s->dtype, n, B, fc, fp));
+    }
+    for (int sg = 0; sg < nseg && nseg > 1; ++sg) {
         YAO_TRY(forward_fused_range(s->data, s->dtype, n, B, c, params, cuts[sg], cuts[sg + 1]));
         if (sg + 1 < nseg)
             YAO_HIP(hipMemcpyAsync(ckpt + s->bytes() * sg, s->data, s->bytes(), hipMemcpyDeviceToDevice, st));

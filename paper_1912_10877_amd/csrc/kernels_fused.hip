@@ -33,6 +33,7 @@ struct PassArgs {
     int pstride;
     int tile_qubits[kMaxTileBits];
     int nontile_qubits[40];
+    uint64_t rofs[1 << kMaxRegBits];  // element offset (x B) of load register r from the thread's first
 };
 
 __device__ __forceinline__ uint32_t swz(uint32_t e)
@@ -205,8 +206,10 @@ __device__ __forceinline__ double op_grad(const double2 (&x)[N], const double2 (
 struct TileCtx {
     uint64_t base;   // amplitude index bits outside the tile
     uint64_t dth;    // this thread's deposited qubit bits for the load/store mapping
+    uint64_t toff;   // element offset of the thread's register 0: (base | dth) * B + bidx
     int b0, bl;      // first batch slot of the tile, this thread's slot offset
-    bool bvalid;
+    int bidx;        // batch slot this thread loads: b0 + bl, clamped to the last slot
+    bool bvalid;     // b0 + bl < B: only then does the thread store
 };
 
 // Load/store mapping: element e = th + r * nthr; the low c bits of th are the batch slot, the
@@ -230,19 +233,16 @@ template <int RB> __device__ __forceinline__ TileCtx tile_ctx(const PassArgs& a,
     tc.b0 = blockIdx.y << c;
     tc.bl = th & ((1 << c) - 1);
     tc.bvalid = tc.b0 + tc.bl < a.B;
+    tc.bidx = tc.bvalid ? tc.b0 + tc.bl : a.B - 1;
+    tc.toff = (base | dth) * (uint64_t)a.B + (uint64_t)tc.bidx;
     return tc;
 }
 
+// The register bits of the load mapping are tile qubits whose offsets are the same for every
+// thread: the host passes them per register.
 template <int RB> __device__ __forceinline__ uint64_t tile_off(const PassArgs& a, const TileCtx& tc, int r)
 {
-    uint64_t dr = 0;
-    const int j0 = a.t - RB - a.c;
-#pragma unroll
-    for (int j = 0; j < kMaxTileBits; ++j) {
-        const int rb = j - j0;
-        if (rb >= 0 && rb < RB) dr |= (uint64_t)((r >> rb) & 1) << a.tile_qubits[j];
-    }
-    return (tc.base | tc.dth | dr) * (uint64_t)a.B + (uint64_t)(tc.b0 + tc.bl);
+    return tc.toff + a.rofs[r];
 }
 
 // Tile index of register element r in a register group, split into the per-thread part
@@ -271,15 +271,38 @@ __device__ __forceinline__ void group_index(const int (&rpos)[kMaxRegBits], int 
     }
 }
 
-// Copy the pass's op records and group descriptors to LDS (16-byte words).
-__device__ __forceinline__ void stage_program(const PassArgs& a, POp* lops, PGroupDesc* lgrp, int th, int nthr)
+// The pass's op records and group descriptors are copied to LDS in 16-byte words. The first
+// kProgRegs words of every thread are loaded together with the tile (one wait for both);
+// indices are clamped so that every load is in bounds.
+constexpr int kProgRegs = 4;
+static_assert(sizeof(POp) % 16 == 0 && sizeof(PGroupDesc) % 16 == 0, "16-byte program words");
+
+__device__ __forceinline__ const uint4* prog_src(const PassArgs& a, int i, int nwo)
 {
-    const uint4* so = (const uint4*)a.ops;
-    uint4* dop = (uint4*)lops;
-    for (int i = th; i < a.nops * (int)(sizeof(POp) / 16); i += nthr) dop[i] = so[i];
-    const uint4* sg = (const uint4*)a.groups;
-    uint4* dg = (uint4*)lgrp;
-    for (int i = th; i < a.ngroups * (int)(sizeof(PGroupDesc) / 16); i += nthr) dg[i] = sg[i];
+    return i < nwo ? (const uint4*)a.ops + i : (const uint4*)a.groups + (i - nwo);
+}
+__device__ __forceinline__ uint4* prog_dst(POp* lops, PGroupDesc* lgrp, int i, int nwo)
+{
+    return i < nwo ? (uint4*)lops + i : (uint4*)lgrp + (i - nwo);
+}
+
+__device__ __forceinline__ void prog_load(const PassArgs& a, int th, int nthr, uint4 (&w)[kProgRegs])
+{
+    const int nwo = a.nops * (int)(sizeof(POp) / 16);
+    const int tot = nwo + a.ngroups * (int)(sizeof(PGroupDesc) / 16);
+#pragma unroll
+    for (int k = 0; k < kProgRegs; ++k) w[k] = *prog_src(a, min(th + k * nthr, tot - 1), nwo);
+}
+
+__device__ __forceinline__ void prog_store(const PassArgs& a, POp* lops, PGroupDesc* lgrp, int th, int nthr,
+                                           const uint4 (&w)[kProgRegs])
+{
+    const int nwo = a.nops * (int)(sizeof(POp) / 16);
+    const int tot = nwo + a.ngroups * (int)(sizeof(PGroupDesc) / 16);
+    // Unconditional: a clamped index writes the word it loaded, so duplicates are identical.
+#pragma unroll
+    for (int k = 0; k < kProgRegs; ++k) *prog_dst(lops, lgrp, min(th + k * nthr, tot - 1), nwo) = w[k];
+    for (int i = th + kProgRegs * nthr; i < tot; i += nthr) *prog_dst(lops, lgrp, i, nwo) = *prog_src(a, i, nwo);
 }
 
 struct GroupCtl {
@@ -463,12 +486,17 @@ __global__ __launch_bounds__(512) void k_pass_fwd(PassArgs a)
     PGroupDesc* lgrp = (PGroupDesc*)(lops + kMaxPassOps);
     const TileCtx tc = tile_ctx<RB>(a, th);
     VP* gp = (VP*)a.psi;
-    stage_program(a, lops, lgrp, th, nthr);
+    // Every load is in bounds (slots past B read the last slot and are never stored), so all
+    // of them are issued before the first wait.
+    {
+        uint4 w[kProgRegs];
+        prog_load(a, th, nthr, w);
+        VP v[N];
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-        VP v = mkv<VP, RP>((RP)0, (RP)0);
-        if (tc.bvalid) v = gp[tile_off<RB>(a, tc, r)];
-        lp[swz((uint32_t)th + (uint32_t)r * nthr)] = v;
+        for (int r = 0; r < N; ++r) v[r] = gp[tile_off<RB>(a, tc, r)];
+        prog_store(a, lops, lgrp, th, nthr, w);
+#pragma unroll
+        for (int r = 0; r < N; ++r) lp[swz((uint32_t)th + (uint32_t)r * nthr)] = v[r];
     }
     __syncthreads();
 
@@ -540,19 +568,24 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
     const TileCtx tc = tile_ctx<RB>(a, th);
     double2* gp = (double2*)a.psi;
     VL* gl = (VL*)a.lam;
-    stage_program(a, lops, lgrp, th, nthr);
+    {
+        uint4 pw[kProgRegs];
+        prog_load(a, th, nthr, pw);
+        double2 v[N];
+        VL w[N];
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-        double2 v = make_double2(0.0, 0.0);
-        VL w = mkv<VL, RL>((RL)0, (RL)0);
-        if (tc.bvalid) {
+        for (int r = 0; r < N; ++r) {
             const uint64_t off = tile_off<RB>(a, tc, r);
-            v = gp[off];
-            w = gl[off];
+            v[r] = gp[off];
+            w[r] = gl[off];
         }
-        const uint32_t e = swz((uint32_t)th + (uint32_t)r * nthr);
-        lp[e] = v;
-        ll[e] = w;
+        prog_store(a, lops, lgrp, th, nthr, pw);
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            const uint32_t e = swz((uint32_t)th + (uint32_t)r * nthr);
+            lp[e] = v[r];
+            ll[e] = w[r];
+        }
     }
     __syncthreads();
 
@@ -704,6 +737,16 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
     a.nnt = 0;
     for (int q = 0; q < n; ++q)
         if (!((T >> q) & 1)) a.nontile_qubits[a.nnt++] = q;
+    {
+        const int RB = bwd ? kRegBitsBwd : kRegBitsFwd;
+        const int j0 = t - RB - c;
+        for (int r = 0; r < (1 << RB); ++r) {
+            uint64_t d = 0;
+            for (int rb = 0; rb < RB; ++rb)
+                if ((r >> rb) & 1) d |= uint64_t(1) << tile_qubits[j0 + rb];
+            a.rofs[r] = d * (uint64_t)B;
+        }
+    }
     a.ntiles = 1 << a.nnt;
     a.pstride = pstride > a.ntiles ? pstride : a.ntiles;
     const int Bc = 1 << c;

@@ -57,7 +57,7 @@ void default_options(yao_options& o)
 {
     o.plain = 0;
     o.tile_qubits = 0;
-    o.fuse_width = 1;
+    o.fuse_width = 0;
     o.checkpoint_every = 0;
     o.drift_tol = 0.0;
     o.mfma = 1;

@@ -35,6 +35,7 @@ enum WsSlot {
     WS_MAT,         // gate matrices and pass programs
     WS_CKPT,        // checkpoints
     WS_SEG,         // segment states of the checkpointed backward
+    WS_TUNE,        // copy of a state while schedules are timed on it
     WS_MISC,
     WS_COUNT
 };

@@ -24,7 +24,7 @@ def gpu():
     yb = binding
     yb.init()
     yield
-    yb.set_options(plain=0, tile_qubits=0, fuse_width=1, autotune=1)
+    yb.set_options(plain=0, tile_qubits=0, fuse_width=0, autotune=1)
 
 
 def tol(dtype):
@@ -99,7 +99,7 @@ def test_forced_fusion_width_and_tile(width, tq):
         e, g = yb.batch_run(states, circs, ps, hams)
         check(e, g, ps, refs, 0)
     finally:
-        yb.set_options(autotune=1, fuse_width=1, tile_qubits=0)
+        yb.set_options(autotune=1, fuse_width=0, tile_qubits=0)
 
 
 def test_autotuned_equals_untuned():

@@ -154,11 +154,11 @@ def test_forward_25q_energy(dtype):
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
-@pytest.mark.parametrize("width", [2, 3, 4, 5])
+@pytest.mark.parametrize("width", [1, 2, 3, 4, 5])
 def test_forward_with_dense_fusion_matches_oracle(dtype, width):
     """Forward sweeps folding gates into dense blocks of up to `width` qubits (4 and 5 run on
-    FP32 matrix cores for complex64 states)."""
-    yb.set_options(fuse_width=width)
+    FP32 matrix cores for complex64 states; 1 merges runs of one-qubit gates)."""
+    yb.set_options(fuse_width=width, autotune=0)
     try:
         n = 11
         circ = w.random_gate_list(n, 70, seed=4000 + width, kmax=3, max_ctrl=2)
@@ -171,7 +171,7 @@ def test_forward_with_dense_fusion_matches_oracle(dtype, width):
         tol = 1e-11 if dtype == 1 else 2e-5
         assert np.abs(s.download() - want).max() <= tol
     finally:
-        yb.set_options(fuse_width=1)
+        yb.set_options(fuse_width=0, autotune=1)
 
 
 @pytest.mark.parametrize("mfma", [1, 0])
@@ -183,13 +183,14 @@ def test_random_circuit_20q_fused_5q_blocks(mfma):
     n = 20
     circ = yb.Circuit.from_workload(w.random_circuit(n, 24, seed=5))
     ref = yb.State(n, 1, 1)
-    yb.forward(ref, circ, [])
-    yb.set_options(fuse_width=5, mfma=mfma)
+    yb.set_options(autotune=0)
     try:
+        yb.forward(ref, circ, [])
+        yb.set_options(fuse_width=5, mfma=mfma)
         s = yb.State(n, 1, 0)
         yb.forward(s, circ, [])
     finally:
-        yb.set_options(fuse_width=1, mfma=1)
+        yb.set_options(fuse_width=0, mfma=1, autotune=1)
     zz = yb.PauliSum.from_workload(w.pauli_sum(n, [(1.0, "ZZ" + "I" * (n - 2))]))
     assert abs(yb.expect(s, zz)[0] - gold["zz01"][0]) <= 2e-5
     assert abs(yb.expect(ref, zz)[0] - gold["zz01"][0]) <= 1e-10
