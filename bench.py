@@ -25,8 +25,27 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 FAMILIES = {0: "gate", 1: "adjoint", 2: "pass_fwd", 3: "pass_bwd", 4: "expect", 5: "hpsi", 6: "mfma", 7: "batch"}
-KERNEL_NAMES = {0: "k_gate1/k_gatek", 1: "k_adjoint", 2: "k_pass<fwd>", 3: "k_pass<bwd>", 4: "k_expect", 5: "k_hpsi",
+KERNEL_NAMES = {0: "k_gate1/k_gatek", 1: "k_adjoint", 2: "k_pass_fwd", 3: "k_pass_bwd", 4: "k_expect", 5: "k_hpsi",
                 6: "k_dense_mfma", 7: "k_batch"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summaries
+    (profiles/*.txt), or None when none covers the kernel as its source stands now."""
+    import glob
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1912_10877_amd", "csrc", "kernels_fused.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        fields = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        if fields.get("kernel") == kernel and fields.get("source_sha256") == sha and "traffic_bytes_per_launch" in fields:
+            return float(fields["traffic_bytes_per_launch"])
+    return None
 
 
 def parse():
@@ -40,12 +59,14 @@ def parse():
     p.add_argument("--dtype", choices=["c64", "c128"], default="c64")
     p.add_argument("--mode", choices=["reversible", "checkpoint", "auto"], default="reversible")
     p.add_argument("--plain-steps", type=int, default=2)
-    p.add_argument("--cpu-depth", type=int, default=6, help="depth of the oracle sample")
+    p.add_argument("--cpu-depth", type=int, default=20, help="depth of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-profile", action="store_true")
     p.add_argument("--batch-circuits", type=int, default=1024,
                    help="circuits of the uneven batch measured beside the main step (0: skip)")
     p.add_argument("--batch-steps", type=int, default=5)
+    p.add_argument("--fuse-width", type=int, default=-1,
+                   help="forward fusion width 0..5 with the autotuner off (-1: autotuned)")
     return p.parse_args()
 
 
@@ -86,11 +107,12 @@ def bench_uneven_batch(yb, w, torch, ncirc, steps):
     t0 = time.perf_counter()
     loop()
     fused_loop_ms = (time.perf_counter() - t0) * 1e3
-    yb.set_options(plain=1)
+    saved = yb.get_options()
+    yb.set_options(plain=1, fuse_width=0)
     t0 = time.perf_counter()
     loop()
     plain_ms = (time.perf_counter() - t0) * 1e3
-    yb.set_options(plain=0)
+    yb.set_options(plain=0, fuse_width=saved.fuse_width)
     return {"workload": f"{ncirc} circuits, qubits uniform 8..20, depth uniform 4..16, Rx.Rz.Rx + CNOT-chain "
                         "ansatz, periodic Heisenberg energy + all gradients per circuit, complex64",
             "circuits": ncirc, "gates": gates, "ms_per_batch": batch_ms,
@@ -115,6 +137,8 @@ def main():
     torch.cuda.set_device(0)
     yb.init()
     yb.use_torch_stream()
+    if args.fuse_width >= 0:
+        yb.set_options(autotune=0, fuse_width=args.fuse_width)
     n, depth, B = args.qubits, args.depth, args.batch
     dtype = yb.C64 if args.dtype == "c64" else yb.C128
     mode = {"reversible": yb.GRAD_REVERSIBLE, "checkpoint": yb.GRAD_CHECKPOINT, "auto": yb.GRAD_AUTO}[args.mode]
@@ -158,7 +182,8 @@ def main():
     # Plain per-gate form on the same GPU and dtype, for the speedup.
     plain_ms = None
     if args.plain_steps > 0:
-        yb.set_options(plain=1)
+        saved = yb.get_options()
+        yb.set_options(plain=1, fuse_width=0)
         step()
         torch.cuda.synchronize()
         p0 = time.perf_counter()
@@ -166,7 +191,7 @@ def main():
             step()
         torch.cuda.synchronize()
         plain_ms = (time.perf_counter() - p0) * 1e3 / args.plain_steps
-        yb.set_options(plain=0)
+        yb.set_options(plain=0, fuse_width=saved.fuse_width)
 
     roofline = None
     if prof:
@@ -181,6 +206,8 @@ def main():
         else:
             roofline = {"bound": "alu", "achieved": round(tfl, 3), "peak": peak_alu, "unit": "TFLOP/s",
                         "frac": round(tfl / peak_alu, 4), "traffic": None}
+        if dtype == yb.C64 and fam in (2, 3):
+            roofline["traffic"] = measured_traffic("k_pass_bwd<float>" if fam == 3 else "k_pass_fwd<float>")
         roofline.update({"kernel": KERNEL_NAMES[fam], "launches_per_step": nl / args.steps,
                          "avg_launch_us": round(ms * 1e3 / nl, 2), "algo_bytes_per_launch": by / nl,
                          "algo_flops_per_launch": fl / nl, "achieved_gbs": round(gbs, 1),
@@ -212,7 +239,8 @@ def main():
         "config": {"workload": f"vqe{n}: {n}-qubit Rx.Rz.Rx + CNOT-chain ansatz, depth {depth}, "
                                f"{circ_w.nparams} params, periodic Heisenberg energy + all gradients, "
                                f"{args.mode} adjoint", "qubits": n, "depth": depth, "batch": B,
-                   "params": circ_w.nparams, "gates": ngates, "grad_mode": args.mode},
+                   "params": circ_w.nparams, "gates": ngates, "grad_mode": args.mode,
+                   "forward_fusion": "autotuned" if args.fuse_width < 0 else args.fuse_width},
         "energy": float(e[0]), "drift": drift,
         "plain_ms_per_step": plain_ms,
         "speedup_vs_plain": (plain_ms / ms_step) if plain_ms else None,

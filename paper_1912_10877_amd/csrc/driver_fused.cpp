@@ -168,11 +168,15 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     append(prog.mats, M.im);
                 }
                 if (g.k > 1) op.type = OT_LDSK;
-                if (g.k == 1)
-                    for (int e = 0; e < 4; ++e) {
-                        op.u[e] = prog.mats[op.mat + e];
-                        op.u[4 + e] = prog.mats[op.mat + 4 + e];
+                if (g.k == 1) {
+                    // The forward kernel of complex64 states reads the 2x2 matrix as float[8].
+                    if (!bwd && dtype == YAO_C64) {
+                        float* f = (float*)op.u;
+                        for (int e = 0; e < 8; ++e) f[e] = (float)prog.mats[op.mat + e];
+                    } else {
+                        for (int e = 0; e < 8; ++e) op.u[e] = prog.mats[op.mat + e];
                     }
+                }
                 for (int j = 0; j < g.k; ++j) op.tpos[j] = tile_bit(g.locs[j]);
                 op.rpos = 0;
                 if (!hg.lds) {

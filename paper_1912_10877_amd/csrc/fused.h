@@ -40,7 +40,8 @@ struct POp {
     int mat;        // offset in doubles into the matrix pool: U (re, im) then M (re, im)
     uint32_t cmask, cval;  // controls on tile bits
     uint64_t omask, oval;  // controls on qubits outside the tile
-    double u[8];    // one-qubit matrix (forward U, backward U^dagger): re[4] then im[4]
+    double u[8];    // one-qubit matrix (forward U, backward U^dagger): re[4] then im[4]; in
+                    // forward programs of complex64 states the same entries as float[8]
     int tpos[4];    // tile-bit positions of the targets, in locs order
 };
 static_assert(sizeof(POp) == 128, "op record layout");

@@ -81,6 +81,46 @@ __device__ __forceinline__ OpCtl op_ctl(const POp& r)
     return o;
 }
 
+// Control fields and the one-qubit matrix of an op, wave-uniform. The matrix is read in the
+// precision MR: the host stores float entries (u viewed as float[8]) in programs for complex64
+// forward sweeps, double entries otherwise.
+template <typename MR> struct OpS {
+    OpCtl c;
+    MR m[8];  // re[4], im[4]
+};
+__device__ __forceinline__ double sc_f64(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    return __builtin_bit_cast(double, sc64(b));
+}
+__device__ __forceinline__ float sc_f32(float v)
+{
+    return __builtin_bit_cast(float, sc(__builtin_bit_cast(int, v)));
+}
+template <typename MR> __device__ __forceinline__ OpS<MR> load_op(const POp& r)
+{
+    OpS<MR> o;
+    o.c = op_ctl(r);
+    if constexpr (sizeof(MR) == 4) {
+        const float* f = (const float*)r.u;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o.m[q] = sc_f32(f[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o.m[q] = sc_f64(r.u[q]);
+    }
+    // A tile that fails the op's controls on qubits outside the tile skips every pair: the
+    // pair predicate then asks for bit 31 of a tile index, which is never set.
+    return o;
+}
+__device__ __forceinline__ void fold_outer_controls(OpCtl& c, uint64_t base)
+{
+    if ((base & c.omask) != c.oval) {
+        c.cmask = 0x80000000u;
+        c.cval = 0x80000000u;
+    }
+}
+
 // ------------------------------------------------------------------------------ pair updates
 // Apply a one-qubit matrix of structure TYPE to the pair (a, b); m = {re[4], im[4]}.
 template <int TYPE, typename RR, typename V>
@@ -518,25 +558,23 @@ __global__ __launch_bounds__(512) void k_pass_fwd(PassArgs a)
         VP x[N];
 #pragma unroll
         for (int r = 0; r < N; ++r) x[r] = lp[swz(ethr | er[r])];
-        POp raw = lops[G.op0];
+        // The record of op oi + 1 is read from LDS while op oi computes and is moved to scalar
+        // registers at the end of op oi.
+        OpS<RP> cur = load_op<RP>(lops[G.op0]);
         for (int oi = 0; oi < G.nops; ++oi) {
-            const OpCtl op = op_ctl(raw);
-            RP mr[4], mi[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                mr[q] = (RP)raw.u[q];
-                mi[q] = (RP)raw.u[4 + q];
-            }
-            if (oi + 1 < G.nops) raw = lops[G.op0 + oi + 1];  // next record, in flight during this op
-            if ((tc.base & op.omask) == op.oval) {
+            const POp nxt = lops[G.op0 + min(oi + 1, G.nops - 1)];
+            OpCtl op = cur.c;
+            fold_outer_controls(op, tc.base);
+            const RP* mr = cur.m;
+            const RP* mi = cur.m + 4;
 #define YAO_FWD_CASE(J)                                                                       \
     case J:                                                                                   \
         if (op.cmask) op_apply<J, true, RP>(x, op.type, mr, mi, ethr, er, op.cmask, op.cval); \
         else op_apply<J, false, RP>(x, op.type, mr, mi, ethr, er, 0u, 0u);                    \
         break;
-                switch (op.rpos) { YAO_FWD_CASE(0) YAO_FWD_CASE(1) YAO_FWD_CASE(2) YAO_FWD_CASE(3) }
+            switch (op.rpos) { YAO_FWD_CASE(0) YAO_FWD_CASE(1) YAO_FWD_CASE(2) default: YAO_FWD_CASE(3) }
 #undef YAO_FWD_CASE
-            }
+            cur = load_op<RP>(nxt);
         }
 #pragma unroll
         for (int r = 0; r < N; ++r) lp[swz(ethr | er[r])] = x[r];
@@ -623,16 +661,14 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
             y[r] = make_double2((double)w.x, (double)w.y);
         }
         int nslot = 0;
-        POp raw = lops[G.op0];
+        OpS<double> cur = load_op<double>(lops[G.op0]);
         for (int oi = 0; oi < G.nops; ++oi) {
-            const OpCtl op = op_ctl(raw);
-            double m[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) m[q] = raw.u[q];
-            if (oi + 1 < G.nops) raw = lops[G.op0 + oi + 1];  // next record, in flight during this op
+            const POp nxt = lops[G.op0 + min(oi + 1, G.nops - 1)];
+            OpCtl op = cur.c;
+            fold_outer_controls(op, tc.base);
+            const double* m = cur.m;
             double g = 0;
-            if ((tc.base & op.omask) == op.oval) {
-                const double* gm = a.mats + op.mat + 8;  // M of a dense generator
+            const double* gm = a.mats + op.mat + 8;  // M of a dense generator
 #define YAO_BWD_CASE(J)                                                                                       \
     case J:                                                                                                   \
         if (op.cmask) {                                                                                       \
@@ -645,14 +681,14 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
             op_apply<J, false, double>(y, op.type, m, m + 4, ethr, er, 0u, 0u);                               \
         }                                                                                                     \
         break;
-                switch (op.rpos) { YAO_BWD_CASE(0) YAO_BWD_CASE(1) YAO_BWD_CASE(2) }
+            switch (op.rpos) { YAO_BWD_CASE(0) YAO_BWD_CASE(1) default: YAO_BWD_CASE(2) }
 #undef YAO_BWD_CASE
-            }
             if (op.slot >= 0) {
                 red[nslot * nthr + th] = g;
                 if (th == 0) sl[nslot] = op.slot;
                 ++nslot;
             }
+            cur = load_op<double>(nxt);
         }
 #pragma unroll
         for (int r = 0; r < N; ++r) {
