@@ -14,7 +14,8 @@ namespace yao {
 
 int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, const POp* ops, const PGroupDesc* groups,
                 const double* mats, double* gpartial, int pstride, int n, int B, int c, int t, int group0,
-                int ngroups, const std::vector<int>& tile_qubits, double flops, int op_first, int nops);
+                int ngroups, const std::vector<int>& tile_qubits, double flops, int op_first, int nops,
+                const double* dmats, int dm_words);
 int launch_fill(double* p, size_t count, double v);
 
 using PlanKey = std::tuple<const yao_circuit*, uint64_t, int, int, int, int, int, int, bool>;
@@ -91,6 +92,10 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
         prog.pass_nops.push_back(0);
         prog.pass_flops.push_back(0.0);
         prog.pass_mat.push_back(-1);
+        prog.pass_dmat0.push_back(0);
+        prog.pass_dmat_words.push_back(0);
+        std::vector<double> dense;  // this pass's dense block matrices, in the order of their ops
+        int ndense = 0;
         if (pass.standalone >= 0) {
             // A gate wider than a pass takes: its matrices go to the pool in the form its own
             // launch reads.
@@ -129,7 +134,7 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     if (nr < P.reg_bits) gd.rpos[nr] = b;
                     ++nr;
                 }
-            gd.lds = hg.lds ? 1 : 0;
+            gd.lds = hg.dense ? 2 : (hg.lds ? 1 : 0);
             gd.op0 = (int)prog.ops.size() - prog.pass_op0.back();
             prog.pass_nops.back() += (int)hg.ops.size();
             gd.nops = (int)hg.ops.size();
@@ -168,6 +173,66 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     append(prog.mats, M.im);
                 }
                 if (g.k > 1) op.type = OT_LDSK;
+                if (hg.dense) {
+                    // The gate as a 16 x 16 matrix on the group's register bits (index bit j <->
+                    // tile bit gd.rpos[j]) with its controls on those bits folded in, stored in
+                    // the state's precision: rows of re[16] then im[16].
+                    int tp[kMaxDenseK], cpos[8];
+                    for (int j = 0; j < g.k; ++j) {
+                        tp[j] = -1;
+                        for (int r = 0; r < kRegBitsFwd; ++r)
+                            if (gd.rpos[r] == tile_bit(g.locs[j])) tp[j] = r;
+                        if (tp[j] < 0) return set_error(YAO_EINVAL, "dense block target outside its register bits");
+                    }
+                    for (int m = 0; m < g.nctrl; ++m) {
+                        cpos[m] = -1;
+                        if ((T >> g.ctrls[m]) & 1)
+                            for (int r = 0; r < kRegBitsFwd; ++r)
+                                if (gd.rpos[r] == tile_bit(g.ctrls[m])) cpos[m] = r;
+                    }
+                    const int D = 1 << kRegBitsFwd, du = 1 << g.k;
+                    std::vector<double> Fr((size_t)D * D, 0.0), Fi((size_t)D * D, 0.0);
+                    for (int c = 0; c < D; ++c) {
+                        bool pass_ok = true;
+                        for (int m = 0; m < g.nctrl; ++m)
+                            if (cpos[m] >= 0) pass_ok &= ((c >> cpos[m]) & 1) == g.cvals[m];
+                        if (!pass_ok) {
+                            Fr[(size_t)c * D + c] = 1.0;
+                            continue;
+                        }
+                        int sin = 0, clear = c;
+                        for (int j = 0; j < g.k; ++j) {
+                            sin |= ((c >> tp[j]) & 1) << j;
+                            clear &= ~(1 << tp[j]);
+                        }
+                        for (int so = 0; so < du; ++so) {
+                            int r = clear;
+                            for (int j = 0; j < g.k; ++j) r |= ((so >> j) & 1) << tp[j];
+                            Fr[(size_t)r * D + c] += U.re[(size_t)so * du + sin];
+                            Fi[(size_t)r * D + c] += U.im[(size_t)so * du + sin];
+                        }
+                    }
+                    // op.mat is the block's ordinal among the pass's dense blocks. Complex64
+                    // passes run the block on the FP32 matrix cores and take it row-major
+                    // (16 x 16 complex); complex128 passes take it column-major: column c
+                    // holds re[16] then im[16].
+                    op.mat = ndense++;
+                    if (dtype == YAO_C64) {
+                        const size_t at = dense.size();
+                        dense.resize(at + (size_t)D * D);  // 2 D^2 floats
+                        float* f = (float*)(dense.data() + at);
+                        for (int r = 0; r < D; ++r)
+                            for (int c = 0; c < D; ++c) {
+                                f[2 * (r * D + c)] = (float)Fr[(size_t)r * D + c];
+                                f[2 * (r * D + c) + 1] = (float)Fi[(size_t)r * D + c];
+                            }
+                    } else {
+                        for (int c = 0; c < D; ++c) {
+                            for (int r = 0; r < D; ++r) dense.push_back(Fr[(size_t)r * D + c]);
+                            for (int r = 0; r < D; ++r) dense.push_back(Fi[(size_t)r * D + c]);
+                        }
+                    }
+                }
                 if (g.k == 1) {
                     // The forward kernel of complex64 states reads the 2x2 matrix as float[8].
                     if (!bwd && dtype == YAO_C64) {
@@ -185,6 +250,10 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                 }
                 for (int m = 0; m < g.nctrl; ++m) {
                     const int q = g.ctrls[m];
+                    bool folded = false;  // a control on a dense block's register bit is in its matrix
+                    if (hg.dense && ((T >> q) & 1))
+                        for (int r = 0; r < kRegBitsFwd; ++r) folded |= gd.rpos[r] == tile_bit(q);
+                    if (folded) continue;
                     if ((T >> q) & 1) {
                         op.cmask |= 1u << tile_bit(q);
                         if (g.cvals[m]) op.cval |= 1u << tile_bit(q);
@@ -197,6 +266,13 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                 prog.pass_flops.back() += op_flops(op, bwd) / double(uint64_t(1) << g.nctrl);
             }
             prog.groups.push_back(gd);
+        }
+        if (ndense > kMaxPassDense) return set_error(YAO_EINVAL, "pass holds %d dense blocks", ndense);
+        if (!dense.empty()) {
+            prog.mats.resize((prog.mats.size() + 1) & ~size_t(1));  // 16-byte words
+            prog.pass_dmat0.back() = (int)prog.mats.size();
+            prog.pass_dmat_words.back() = (int)(dense.size() / 2);
+            prog.mats.insert(prog.mats.end(), dense.begin(), dense.end());
         }
     }
     return 0;
@@ -255,7 +331,7 @@ int launch_forward_passes(const Plan& P, const Program& prog, const DevProgram& 
         YAO_TRY(launch_pass(false, dtype, dtype, data, nullptr, d.ops, d.groups, d.mats, nullptr, 0, n, B, P.c, P.t,
                             prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits,
                             prog.pass_flops[p] * (double)(uint64_t(1) << n) * B, prog.pass_op0[p],
-                            prog.pass_nops[p]));
+                            prog.pass_nops[p], d.mats + prog.pass_dmat0[p], prog.pass_dmat_words[p]));
     }
     return 0;
 }
@@ -281,7 +357,7 @@ int launch_backward_passes(const Plan& P, const Program& prog, const DevProgram&
         YAO_TRY(launch_pass(true, YAO_C128, lam_dtype, psi, lam, d.ops, d.groups, d.mats, gpartial, W, n, B, P.c, P.t,
                             prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits,
                             prog.pass_flops[p] * (double)(uint64_t(1) << n) * B, prog.pass_op0[p],
-                            prog.pass_nops[p]));
+                            prog.pass_nops[p], nullptr, 0));
     }
     return 0;
 }

@@ -12,9 +12,11 @@ constexpr int kRegBitsFwd = 4;    // register bits per group in the forward: 16 
 constexpr int kRegBitsBwd = 3;    // backward: 8 elements of psi and 8 of lambda per thread
 constexpr int kMaxRegBits = 4;
 constexpr int kMaxTileBits = 13;  // 2^13 complex64 = 64 KiB of LDS
-constexpr int kMaxFusedK = 3;     // wider gates run as standalone launches between passes
+constexpr int kMaxFusedK = 3;     // reverse passes: wider gates run as standalone launches
+constexpr int kMaxDenseK = 4;     // forward passes: gates up to 4 qubits as dense register blocks
 constexpr int kMaxGroupSlots = 12;  // gradient-carrying gates per register group
 constexpr int kMaxPassOps = 80;     // op records of a pass, staged in LDS at the start of the pass
+constexpr int kMaxPassDense = 8;    // dense blocks of a forward pass (their matrices are staged too)
 
 // Structure classes of a one-qubit matrix inside a pass.
 enum OpType : int {
@@ -48,7 +50,8 @@ static_assert(sizeof(POp) == 128, "op record layout");
 
 struct PGroupDesc {
     int rpos[kMaxRegBits];  // tile-bit positions of the register bits, ascending
-    int lds;             // 1: a single OT_LDSK op applied in LDS
+    int lds;             // 1: a single OT_LDSK op applied in LDS; 2: a single dense block, a
+                         // 16 x 16 matrix on the register bits (index bit j <-> rpos[j])
     int op0, nops;
     int nslot;           // ops with a gradient in this group
 };
@@ -68,7 +71,8 @@ struct HostOp {
 struct HostGroup {
     std::vector<int> ops;   // indices into plan ops
     uint64_t rbits = 0;     // register tile-bit mask
-    bool lds = false;
+    bool lds = false;       // one k = 2, 3 gate applied in LDS (reverse passes)
+    bool dense = false;     // one k = 2..4 gate as a 16 x 16 matrix on the register bits (forward)
 };
 struct HostPass {
     std::vector<int> tile_qubits;   // ascending
@@ -103,6 +107,8 @@ struct Program {
     std::vector<int> pass_nops;
     std::vector<double> pass_flops; // algorithmic flops per element of the state, per pass
     std::vector<int> pass_mat;      // standalone passes: offset in doubles of their matrices in mats
+    std::vector<int> pass_dmat0;    // first double of the pass's dense block matrices in mats
+    std::vector<int> pass_dmat_words;  // their size in 16-byte words (0: none)
     std::vector<int> slot_of_gate;  // gradient slot per gate (-1)
     int nslots = 0;
 };

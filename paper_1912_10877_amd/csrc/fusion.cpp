@@ -2,10 +2,11 @@
 // a fused block has no per-parameter gradient).
 //
 // Gates are taken in order. Open blocks act on disjoint qubit sets, so they commute with each
-// other; a gate whose qubits (targets and controls) meet exactly one open block and fit with
-// it in `width` qubits is multiplied into that block (a chain is the matrix product in reverse
-// order, Sec. "Representing Quantum Circuits"); a gate that meets no block opens one; any
-// other gate first closes (emits) every block it meets. Products are formed in FP64.
+// other; a gate whose qubits (targets and controls) fit in `width` qubits together with every
+// open block it meets is multiplied into the union of those blocks (a chain is the matrix
+// product in reverse order, Sec. "Representing Quantum Circuits"); a gate that meets no block
+// opens one; any other gate first closes (emits) every block it meets. Products are formed in
+// FP64.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -156,17 +157,28 @@ std::vector<GateRec> fuse_gates(const yao_circuit* c, const double* params, int 
         const std::vector<int> q = qubits_of(g);
         HostMat U;
         gate_matrix(g, gate_theta(g, params), U);
-        int hit = -1, nhit = 0;
+        std::vector<int> hits;
+        std::vector<int> qs = merged({}, q);
         for (size_t b = 0; b < open.size(); ++b)
             if (meets(open[b].qubits, q)) {
-                hit = (int)b;
-                ++nhit;
+                hits.push_back((int)b);
+                qs = merged(qs, open[b].qubits);
             }
-        if (nhit == 1 && (int)merged(open[hit].qubits, q).size() <= width) {
-            Block& b = open[hit];
-            const std::vector<int> qs = merged(b.qubits, q);
-            if (qs.size() != b.qubits.size()) widen(b, qs);
-            b.M = matmul(embed(g, U, b.qubits), b.M);
+        if (!hits.empty() && (int)qs.size() <= width) {
+            // The blocks it meets act on disjoint qubits, so they commute: their product on the
+            // union is the product of the widened blocks, in any order.
+            Block nb;
+            nb.qubits = qs;
+            nb.M.resize((int)qs.size());
+            for (int d = 0; d < nb.M.dim(); ++d) nb.M.re[(size_t)d * nb.M.dim() + d] = 1.0;
+            for (int h : hits) {
+                Block w = open[h];
+                widen(w, qs);
+                nb.M = matmul(w.M, nb.M);
+            }
+            nb.M = matmul(embed(g, U, nb.qubits), nb.M);
+            for (int i = (int)hits.size() - 1; i >= 0; --i) open.erase(open.begin() + hits[i]);
+            open.push_back(nb);
             continue;
         }
         close_meeting(q);

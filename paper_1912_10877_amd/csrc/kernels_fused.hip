@@ -34,6 +34,8 @@ struct PassArgs {
     int tile_qubits[kMaxTileBits];
     int nontile_qubits[40];
     uint64_t rofs[1 << kMaxRegBits];  // element offset (x B) of load register r from the thread's first
+    const uint4* dmats;     // the pass's dense block matrices (forward), staged in LDS
+    int ndm;                // their size in 16-byte words
 };
 
 __device__ __forceinline__ uint32_t swz(uint32_t e)
@@ -314,35 +316,47 @@ __device__ __forceinline__ void group_index(const int (&rpos)[kMaxRegBits], int 
 // The pass's op records and group descriptors are copied to LDS in 16-byte words. The first
 // kProgRegs words of every thread are loaded together with the tile (one wait for both);
 // indices are clamped so that every load is in bounds.
-constexpr int kProgRegs = 4;
 static_assert(sizeof(POp) % 16 == 0 && sizeof(PGroupDesc) % 16 == 0, "16-byte program words");
 
-__device__ __forceinline__ const uint4* prog_src(const PassArgs& a, int i, int nwo)
+// Word i of the staged program: op records, then group descriptors, then dense matrices.
+struct ProgSeg {
+    int nwo, nwg, tot;
+};
+__device__ __forceinline__ ProgSeg prog_seg(const PassArgs& a)
 {
-    return i < nwo ? (const uint4*)a.ops + i : (const uint4*)a.groups + (i - nwo);
+    ProgSeg g;
+    g.nwo = a.nops * (int)(sizeof(POp) / 16);
+    g.nwg = a.ngroups * (int)(sizeof(PGroupDesc) / 16);
+    g.tot = g.nwo + g.nwg + a.ndm;
+    return g;
 }
-__device__ __forceinline__ uint4* prog_dst(POp* lops, PGroupDesc* lgrp, int i, int nwo)
+__device__ __forceinline__ const uint4* prog_src(const PassArgs& a, int i, const ProgSeg& g)
 {
-    return i < nwo ? (uint4*)lops + i : (uint4*)lgrp + (i - nwo);
+    return i < g.nwo ? (const uint4*)a.ops + i
+                     : (i < g.nwo + g.nwg ? (const uint4*)a.groups + (i - g.nwo) : a.dmats + (i - g.nwo - g.nwg));
+}
+__device__ __forceinline__ uint4* prog_dst(POp* lops, PGroupDesc* lgrp, uint4* ldm, int i, const ProgSeg& g)
+{
+    return i < g.nwo ? (uint4*)lops + i : (i < g.nwo + g.nwg ? (uint4*)lgrp + (i - g.nwo) : ldm + (i - g.nwo - g.nwg));
 }
 
+template <int kProgRegs>
 __device__ __forceinline__ void prog_load(const PassArgs& a, int th, int nthr, uint4 (&w)[kProgRegs])
 {
-    const int nwo = a.nops * (int)(sizeof(POp) / 16);
-    const int tot = nwo + a.ngroups * (int)(sizeof(PGroupDesc) / 16);
+    const ProgSeg g = prog_seg(a);
 #pragma unroll
-    for (int k = 0; k < kProgRegs; ++k) w[k] = *prog_src(a, min(th + k * nthr, tot - 1), nwo);
+    for (int k = 0; k < kProgRegs; ++k) w[k] = *prog_src(a, min(th + k * nthr, g.tot - 1), g);
 }
 
-__device__ __forceinline__ void prog_store(const PassArgs& a, POp* lops, PGroupDesc* lgrp, int th, int nthr,
-                                           const uint4 (&w)[kProgRegs])
+template <int kProgRegs>
+__device__ __forceinline__ void prog_store(const PassArgs& a, POp* lops, PGroupDesc* lgrp, uint4* ldm, int th,
+                                           int nthr, const uint4 (&w)[kProgRegs])
 {
-    const int nwo = a.nops * (int)(sizeof(POp) / 16);
-    const int tot = nwo + a.ngroups * (int)(sizeof(PGroupDesc) / 16);
+    const ProgSeg g = prog_seg(a);
     // Unconditional: a clamped index writes the word it loaded, so duplicates are identical.
 #pragma unroll
-    for (int k = 0; k < kProgRegs; ++k) *prog_dst(lops, lgrp, min(th + k * nthr, tot - 1), nwo) = w[k];
-    for (int i = th + kProgRegs * nthr; i < tot; i += nthr) *prog_dst(lops, lgrp, i, nwo) = *prog_src(a, i, nwo);
+    for (int k = 0; k < kProgRegs; ++k) *prog_dst(lops, lgrp, ldm, min(th + k * nthr, g.tot - 1), g) = w[k];
+    for (int i = th + kProgRegs * nthr; i < g.tot; i += nthr) *prog_dst(lops, lgrp, ldm, i, g) = *prog_src(a, i, g);
 }
 
 struct GroupCtl {
@@ -511,9 +525,99 @@ __device__ __noinline__ double lds_op_bwd(double2* lp, vec2_t<RL>* ll, const POp
     return acc;
 }
 
+// y = M x for the 16 register elements of a thread. M sits in LDS column-major: column c is
+// re[16] then im[16] in the precision RR; every lane reads the same address (broadcast).
+template <typename RR, typename V>
+__device__ __forceinline__ void dense16_apply(V (&x)[16], const RR* M)
+{
+    RR yr[16], yi[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) yr[r] = yi[r] = (RR)0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const RR* col = M + c * 32;
+        const RR xr = x[c].x, xi = x[c].y;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const RR mr = col[r], mi = col[16 + r];
+            yr[r] = fma(mr, xr, yr[r]);
+            yi[r] = fma(mr, xi, yi[r]);
+            yr[r] = fma(-mi, xi, yr[r]);
+            yi[r] = fma(mi, xr, yi[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = mkv<V, RR>(yr[r], yi[r]);
+}
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// A dense block on the FP32 matrix cores, for complex64 tiles of >= 64 columns (one column per
+// thread of the group). The block's 4 bits p[0..3] (ascending) index the 16 amplitudes of a
+// column; the other t - 4 tile bits number the columns. Taking 16 columns as the B operand
+// [Re x; Im x] (32 x 16), the update is the real GEMM [[Re M, -Im M], [Im M, Re M]] x B with
+// v_mfma_f32_16x16x4f32 (A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k,
+// D[4 (l / 16) + v][l % 16] in accumulator v of lane l). Each wave takes 64 columns; the
+// amplitudes are read from and written back to the LDS tile in that layout, so no barrier
+// is needed inside the block. Mf holds the 16 A fragments of 64 lanes each.
+__device__ __forceinline__ uint32_t insert_zeros4(uint32_t c, const int (&p)[kMaxRegBits])
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c = ((c >> p[j]) << (p[j] + 1)) | (c & ((1u << p[j]) - 1));
+    return c;
+}
+__device__ __forceinline__ uint32_t deposit4(uint32_t b, const int (&p)[kMaxRegBits])
+{
+    uint32_t e = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) e |= ((b >> j) & 1u) << p[j];
+    return e;
+}
+__device__ __forceinline__ void dense16_mfma(float2* lp, const float2* M, const int (&p)[kMaxRegBits], int th,
+                                             uint32_t cmask, uint32_t cval)
+{
+    const int lane = th & 63, wave = th >> 6;
+    const int q = lane >> 4, cl = lane & 15;
+    // A fragments of the real form: row 16 rt + cl, column 4 kc + q, from the complex matrix
+    // M (row-major, 16 x 16): Re, -Im in the upper half, Im, Re in the lower one.
+    float a[16];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+        const float2 m = M[cl * 16 + 4 * kc + q];
+        a[kc] = m.x;
+        a[4 + kc] = -m.y;
+        a[8 + kc] = m.y;
+        a[12 + kc] = m.x;
+    }
+    uint32_t bin[4], bout[4];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+        bin[s2] = deposit4((uint32_t)(q + 4 * s2), p);
+        bout[s2] = deposit4((uint32_t)(4 * q + s2), p);
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const uint32_t ec = insert_zeros4((uint32_t)(wave * 64 + ct * 16 + cl), p);
+        float2 xv[4];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) xv[s2] = lp[swz(ec | bin[s2])];
+        v4f acc0 = v4f{0.f, 0.f, 0.f, 0.f}, acc1 = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < 8; ++kc) {
+            const float bv = kc < 4 ? xv[kc].x : xv[kc - 4].y;
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kc], bv, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[8 + kc], bv, acc1, 0, 0, 0);
+        }
+        if ((ec & cmask) == cval) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) lp[swz(ec | bout[v])] = make_float2(acc0[v], acc1[v]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------ forward kernel
 template <typename RP>
-__global__ __launch_bounds__(512) void k_pass_fwd(PassArgs a)
+__global__ __launch_bounds__(512, sizeof(RP) == 4 ? 3 : 1) void k_pass_fwd(PassArgs a)
 {
     constexpr int RB = kRegBitsFwd, N = 1 << RB;
     using VP = vec2_t<RP>;
@@ -522,19 +626,22 @@ __global__ __launch_bounds__(512) void k_pass_fwd(PassArgs a)
     const int nthr = 1 << (t - RB);
     const int th = threadIdx.x;
     VP* lp = (VP*)smem;
+    // LDS: tile | op records | group descriptors | dense block matrices (2 * 256 RP each),
+    // each area sized for this pass.
     POp* lops = (POp*)(smem + (sizeof(VP) << t));
-    PGroupDesc* lgrp = (PGroupDesc*)(lops + kMaxPassOps);
+    PGroupDesc* lgrp = (PGroupDesc*)(lops + a.nops);
+    uint4* ldm = (uint4*)(lgrp + a.ngroups);
     const TileCtx tc = tile_ctx<RB>(a, th);
     VP* gp = (VP*)a.psi;
     // Every load is in bounds (slots past B read the last slot and are never stored), so all
     // of them are issued before the first wait.
     {
-        uint4 w[kProgRegs];
+        uint4 w[4];
         prog_load(a, th, nthr, w);
         VP v[N];
 #pragma unroll
         for (int r = 0; r < N; ++r) v[r] = gp[tile_off<RB>(a, tc, r)];
-        prog_store(a, lops, lgrp, th, nthr, w);
+        prog_store(a, lops, lgrp, ldm, th, nthr, w);
 #pragma unroll
         for (int r = 0; r < N; ++r) lp[swz((uint32_t)th + (uint32_t)r * nthr)] = v[r];
     }
@@ -542,6 +649,27 @@ __global__ __launch_bounds__(512) void k_pass_fwd(PassArgs a)
 
     for (int gi = 0; gi < a.ngroups; ++gi) {
         const GroupCtl G = group_ctl(lgrp[gi]);
+        if (G.lds == 2) {
+            // One dense block on the register bits; its remaining controls are on tile bits
+            // outside them (the same for all 16 elements of a thread) or outside the tile.
+            OpCtl op = op_ctl(lops[G.op0]);
+            fold_outer_controls(op, tc.base);
+            if constexpr (sizeof(RP) == 4) {
+                // Complex64 plans hold dense blocks only for tiles of >= 64 columns.
+                dense16_mfma(lp, (const float2*)ldm + op.mat * 256, G.rpos, th, op.cmask, op.cval);
+            } else {
+                uint32_t ethr, er[N];
+                group_index<RB>(G.rpos, t, th, ethr, er);
+                VP x[N];
+#pragma unroll
+                for (int r = 0; r < N; ++r) x[r] = lp[swz(ethr | er[r])];
+                if ((ethr & op.cmask) == op.cval) dense16_apply<RP>(x, (const RP*)ldm + op.mat * 512);
+#pragma unroll
+                for (int r = 0; r < N; ++r) lp[swz(ethr | er[r])] = x[r];
+            }
+            __syncthreads();
+            continue;
+        }
         if (G.lds) {
             const POp* rec = lops + G.op0;
             const uint64_t omask = sc64(rec->omask), oval = sc64(rec->oval);
@@ -602,12 +730,12 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
     double* red = (double*)(smem + ((size_t)(16 + sizeof(VL)) << t));
     int* sl = (int*)(red + kMaxGroupSlots * nthr);
     POp* lops = (POp*)(sl + 16);
-    PGroupDesc* lgrp = (PGroupDesc*)(lops + kMaxPassOps);
+    PGroupDesc* lgrp = (PGroupDesc*)(lops + a.nops);
     const TileCtx tc = tile_ctx<RB>(a, th);
     double2* gp = (double2*)a.psi;
     VL* gl = (VL*)a.lam;
     {
-        uint4 pw[kProgRegs];
+        uint4 pw[4];
         prog_load(a, th, nthr, pw);
         double2 v[N];
         VL w[N];
@@ -617,7 +745,7 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
             v[r] = gp[off];
             w[r] = gl[off];
         }
-        prog_store(a, lops, lgrp, th, nthr, pw);
+        prog_store(a, lops, lgrp, nullptr, th, nthr, pw);
 #pragma unroll
         for (int r = 0; r < N; ++r) {
             const uint32_t e = swz((uint32_t)th + (uint32_t)r * nthr);
@@ -736,20 +864,24 @@ int prepare_pass_kernels()
     return 0;
 }
 
-size_t pass_lds_bytes(bool bwd, int t, int psi_bytes, int lam_bytes)
+size_t pass_lds_bytes(bool bwd, int t, int psi_bytes, int lam_bytes, int nops, int ngroups, int dm_words)
 {
-    const size_t prog = (sizeof(POp) + sizeof(PGroupDesc)) * kMaxPassOps;
-    if (!bwd) return ((size_t)psi_bytes << t) + prog;
+    const size_t prog = sizeof(POp) * (size_t)nops + sizeof(PGroupDesc) * (size_t)ngroups;
+    if (!bwd) return ((size_t)psi_bytes << t) + prog + 16 * (size_t)dm_words;
     const size_t nthr = size_t(1) << (t - kRegBitsBwd);
     return ((size_t)(16 + lam_bytes) << t) + sizeof(double) * kMaxGroupSlots * nthr + sizeof(int) * 16 + prog;
 }
 
 int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, const POp* ops, const PGroupDesc* groups,
                 const double* mats, double* gpartial, int pstride, int n, int B, int c, int t, int group0,
-                int ngroups, const std::vector<int>& tile_qubits, double flops, int op_first, int nops)
+                int ngroups, const std::vector<int>& tile_qubits, double flops, int op_first, int nops,
+                const double* dmats, int dm_words)
 {
     if (nops > kMaxPassOps || ngroups > kMaxPassOps)
         return set_error(YAO_EINVAL, "pass of %d ops exceeds the staged program size", nops);
+    const int dm_max = bwd ? 0 : kMaxPassDense * 256;  // 4 KiB per block in every layout
+    if (dm_words < 0 || dm_words > dm_max)
+        return set_error(YAO_EINVAL, "pass carries %d words of dense matrices (at most %d)", dm_words, dm_max);
     PassArgs a;
     memset(&a, 0, sizeof(a));
     a.psi = psi;
@@ -758,6 +890,8 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
     a.groups = groups + group0;
     a.mats = mats;
     a.gpartial = gpartial;
+    a.dmats = (const uint4*)dmats;
+    a.ndm = dm_words;
     a.n = n;
     a.B = B;
     a.c = c;
@@ -790,7 +924,7 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
     dim3 block(1 << (t - (bwd ? kRegBitsBwd : kRegBitsFwd)));
     const int pb = bwd ? 16 : (psi_dtype == YAO_C64 ? 8 : 16);
     const int lb = bwd ? (lam_dtype == YAO_C64 ? 8 : 16) : 0;
-    const size_t lds = pass_lds_bytes(bwd, t, pb, lb);
+    const size_t lds = pass_lds_bytes(bwd, t, pb, lb, nops, ngroups, bwd ? 0 : dm_words);
     if (lds > 160 * 1024) return set_error(YAO_EINVAL, "tile of 2^%d needs %zu bytes of LDS", t, lds);
     hipStream_t st = stream();
     const int pi = prof_begin(bwd ? YAO_KF_PASS_BWD : YAO_KF_PASS_FWD);

@@ -71,6 +71,10 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
     }
     const int tq = t - cbits;
     const uint64_t low = low_fixed > 0 ? ((uint64_t(1) << low_fixed) - 1) : 0;
+    // Widest gate a pass takes: forward passes over tiles of >= 64 register-group columns apply
+    // k <= 4 gates as dense blocks on a register group; other passes apply k <= 3 gates in LDS.
+    const bool dense_ok = !reverse && t - reg_bits >= 6;
+    const int maxk = dense_ok ? kMaxDenseK : kMaxFusedK;
     std::vector<int> remaining(P.ops.size());
     for (size_t e = 0; e < remaining.size(); ++e) remaining[e] = (int)e;
 
@@ -78,7 +82,7 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
         HostPass pass;
         // A gate too wide for a tile runs alone when it is next.
         const GateRec& first = circ->gates[P.ops[remaining[0]].gate];
-        if (first.k > kMaxFusedK) {
+        if (first.k > maxk) {
             pass.standalone = remaining[0];
             remaining.erase(remaining.begin());
             P.passes.push_back(pass);
@@ -88,10 +92,13 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
         uint64_t T = popc(low | P.ops[remaining[0]].tmask) <= tq ? low : 0;
         uint64_t blocked = 0;
         std::vector<int> sel, rest;
+        int ndense = 0;
         for (int oi : remaining) {
             const HostOp& op = P.ops[oi];
             const int k = circ->gates[op.gate].k;
-            if ((op.qmask & blocked) || k > kMaxFusedK || (int)sel.size() >= kMaxPassOps) {
+            const bool dense = dense_ok && k > 1;
+            if ((op.qmask & blocked) || k > maxk || (int)sel.size() >= kMaxPassOps ||
+                (dense && ndense >= kMaxPassDense)) {
                 blocked |= op.qmask;
                 rest.push_back(oi);
                 continue;
@@ -99,6 +106,7 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
             if (popc(T | op.tmask) <= tq) {
                 T |= op.tmask;
                 sel.push_back(oi);
+                ndense += dense ? 1 : 0;
             } else {
                 blocked |= op.qmask;
                 rest.push_back(oi);
@@ -120,6 +128,25 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
             uint64_t R = 0, gblocked = 0;
             std::vector<int> gsel, grest;
             bool lds_first = circ->gates[P.ops[prem[0]].gate].k > 1;
+            if (lds_first && dense_ok) {
+                // Dense block on a register group: its targets, its controls inside the tile
+                // while they fit (they are folded into the matrix), then padding bits.
+                const HostOp& op = P.ops[prem[0]];
+                const GateRec& gr = circ->gates[op.gate];
+                grp.dense = true;
+                grp.ops.push_back(prem[0]);
+                for (int j = 0; j < gr.k; ++j) R |= uint64_t(1) << tile_bit(gr.locs[j]);
+                for (int m = 0; m < gr.nctrl; ++m) {
+                    const int q = gr.ctrls[m];
+                    if (((T >> q) & 1) && popc(R | (uint64_t(1) << tile_bit(q))) <= reg_bits)
+                        R |= uint64_t(1) << tile_bit(q);
+                }
+                for (int b = t - 1; b >= cbits && popc(R) < reg_bits; --b) R |= uint64_t(1) << b;
+                grp.rbits = R;
+                prem.erase(prem.begin());
+                pass.groups.push_back(grp);
+                continue;
+            }
             if (lds_first) {
                 grp.lds = true;
                 grp.ops.push_back(prem[0]);
