@@ -115,6 +115,7 @@ struct yao_circuit {
     int nparams;
     std::vector<yao::GateRec> gates;
     uint64_t version;  // bumped on every push; plans cache against it
+    bool transient = false;  // matrices rewritten on every call (a fused circuit for given angles)
 };
 
 struct yao_pauli_sum {

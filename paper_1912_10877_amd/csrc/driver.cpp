@@ -16,10 +16,12 @@ int forward(yao_state* s, const yao_circuit* c, const double* params)
     // or at the width the autotuner found fastest for this circuit and state shape.
     const bool fused = use_fused(s);
     int width = options().fuse_width;
-    if (fused) YAO_TRY(pick_forward_width(c, params, s->data, s->dtype, s->n, s->batch, &width));
+    if (fused) {
+        YAO_TRY(pick_forward_width(c, params, s->data, s->dtype, s->n, s->batch, &width));
+        return forward_sweep(s->data, s->dtype, s->n, s->batch, c, params, width, options().tile_qubits, nullptr);
+    }
     const double* fp = params;
     c = forward_circuit(c, params, width, &fp);
-    if (fused) return forward_fused(s->data, s->dtype, s->n, s->batch, c, fp);
     return forward_plain(s->data, s->dtype, s->n, s->batch, c, fp);
 }
 

@@ -18,8 +18,16 @@ void drop_batch(const void* obj);
 void drop_plans(const yao_circuit* c);
 
 // Dense-block fusion for forward sweeps (fusion.cpp).
+struct FusedPart {
+    std::vector<int> qubits;  // ascending: the fused gate's locs
+    std::vector<int> gates;   // member gates of the circuit, in application order
+    bool single = false;      // one gate kept as it is (wider than the width)
+};
 std::vector<GateRec> fuse_gates(const yao_circuit* c, const double* params, int width);
 const yao_circuit* fused_circuit(const yao_circuit* c, const double* params, int width);
+// The fused circuit's structure (cached): one gate per part, multi-gate parts as placeholders
+// whose matrices are bound later, single gates as in c (with their parameters).
+const yao_circuit* fused_shape(const yao_circuit* c, int width, const std::vector<FusedPart>** parts);
 void drop_fused(const yao_circuit* c);
 
 // Per-gate form.

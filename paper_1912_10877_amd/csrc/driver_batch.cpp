@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <set>
 #include <tuple>
 
 #include "driver.h"
@@ -46,6 +47,9 @@ struct Item {
     const Plan* bwd = nullptr;
     Program pf, pb;
     DevProgram df{}, db{};
+    const BoundProgram* bf = nullptr;  // programs bound on the device (null: built on the host)
+    const BoundProgram* bb = nullptr;
+    size_t poff = 0;                   // the circuit's parameters in the device parameter block
     size_t off_f = 0, off_b = 0, bytes_f = 0, bytes_b = 0;  // program blobs
     int bank = 0;
     int nslots = 0;
@@ -66,6 +70,9 @@ struct Cache {
     double* d_out = nullptr;
     double* h_out = nullptr;
     size_t nout = 0;
+    double* d_params = nullptr;
+    double* h_params = nullptr;
+    size_t nparams = 0;
     double* psi64[kBanks] = {};
     void* lam[kBanks] = {};
     double* gpart[kBanks] = {};
@@ -89,6 +96,8 @@ void free_cache(Cache* c)
     if (c->h_prog) (void)hipHostFree(c->h_prog);
     if (c->d_out) (void)hipFree(c->d_out);
     if (c->h_out) (void)hipHostFree(c->h_out);
+    if (c->d_params) (void)hipFree(c->d_params);
+    if (c->h_params) (void)hipHostFree(c->h_params);
     for (int b = 0; b < kBanks; ++b) {
         if (c->psi64[b]) (void)hipFree(c->psi64[b]);
         if (c->lam[b]) (void)hipFree(c->lam[b]);
@@ -234,22 +243,43 @@ int autotune(const yao_circuit* c, const double* params, yao_state* s, yao_pauli
 // if a program no longer has the size the graph was recorded with.
 int build_programs(Cache& C, const double* const* params, bool first)
 {
+    // A bound program holds one circuit's matrices at a time: a circuit listed twice binds
+    // only in its first item and takes host-built programs in the others.
+    std::set<const BoundProgram*> used;
     for (Item& it : C.items) {
         const double* p = params[it.idx];
-        const double* fp = nullptr;
-        const yao_circuit* fc = forward_circuit(it.c, p, it.tune.width, &fp);
-        if (!first && (fc != it.fc || fc->version != it.fc_version)) return 1;
-        it.fc = fc;
-        it.fc_version = fc->version;
+        const int dt = it.s->dtype;
         if (first) {
-            it.fwd = &plan_for(fc, it.s->n, it.s->dtype, false, it.tune.tq_f);
-            it.bwd = &plan_for(it.c, it.s->n, it.s->dtype, true, it.tune.tq_b);
+            // Programs bound on the device when possible: built once, nothing per call.
+            const std::vector<FusedPart>* parts = nullptr;
+            const yao_circuit* sc = it.tune.width > 0 ? fused_shape(it.c, it.tune.width, &parts) : it.c;
+            const Plan& pf = plan_for(sc, it.s->n, dt, false, it.tune.tq_f);
+            it.bf = bound_program(pf, sc, false, dt, parts, it.tune.width > 0 ? it.c : nullptr);
+            if (it.bf && !used.insert(it.bf).second) it.bf = nullptr;
+            if (it.bf) {
+                it.fwd = &pf;
+                it.fc = sc;
+                it.fc_version = sc->version;
+            }
+            it.bwd = &plan_for(it.c, it.s->n, dt, true, it.tune.tq_b);
+            if (it.nslots) it.bb = bound_program(*it.bwd, it.c, true, dt, nullptr, nullptr);
+            if (it.bb && !used.insert(it.bb).second) it.bb = nullptr;
         }
-        it.pf = Program();
-        it.pb = Program();
-        YAO_TRY(build_program(*it.fwd, fc, fp, false, it.s->dtype, it.pf));
-        if (it.nslots) YAO_TRY(build_program(*it.bwd, it.c, p, true, it.s->dtype, it.pb));
-        const size_t bf = program_blob_bytes(it.pf), bb = it.nslots ? program_blob_bytes(it.pb) : 0;
+        if (!it.bf) {
+            const double* fp = nullptr;
+            const yao_circuit* fc = forward_circuit(it.c, p, it.tune.width, &fp);
+            if (!first && (fc != it.fc || fc->version != it.fc_version)) return 1;
+            it.fc = fc;
+            it.fc_version = fc->version;
+            if (first) it.fwd = &plan_for(fc, it.s->n, dt, false, it.tune.tq_f);
+            it.pf = Program();
+            YAO_TRY(build_program(*it.fwd, fc, fp, false, dt, it.pf));
+        }
+        if (it.nslots && !it.bb) {
+            it.pb = Program();
+            YAO_TRY(build_program(*it.bwd, it.c, p, true, dt, it.pb));
+        }
+        const size_t bf = it.bf ? 0 : program_blob_bytes(it.pf), bb = (it.nslots && !it.bb) ? program_blob_bytes(it.pb) : 0;
         if (!first && (bf != it.bytes_f || bb != it.bytes_b)) return 1;
         it.bytes_f = bf;
         it.bytes_b = bb;
@@ -257,12 +287,29 @@ int build_programs(Cache& C, const double* const* params, bool first)
     return 0;
 }
 
+const Program& fwd_prog(const Item& it)
+{
+    return it.bf ? it.bf->prog : it.pf;
+}
+const Program& bwd_prog(const Item& it)
+{
+    return it.bb ? it.bb->prog : it.pb;
+}
+
 void pack_all(Cache& C)
 {
     for (Item& it : C.items) {
-        pack_program(it.pf, C.h_prog + it.off_f, C.d_prog + it.off_f, it.df);
-        if (it.nslots) pack_program(it.pb, C.h_prog + it.off_b, C.d_prog + it.off_b, it.db);
+        if (!it.bf) pack_program(it.pf, C.h_prog + it.off_f, C.d_prog + it.off_f, it.df);
+        if (it.nslots && !it.bb) pack_program(it.pb, C.h_prog + it.off_b, C.d_prog + it.off_b, it.db);
+        if (it.bf) it.df = it.bf->d;
+        if (it.bb) it.db = it.bb->d;
     }
+}
+
+void pack_params(Cache& C, const double* const* params)
+{
+    for (const Item& it : C.items)
+        if (it.c->nparams > 0) memcpy(C.h_params + it.poff, params[it.idx], sizeof(double) * (size_t)it.c->nparams);
 }
 
 int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit* const* circs,
@@ -334,11 +381,16 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
     for (Item& it : C.items) {
         it.out_g = nout;
         nout += it.nslots;
+        it.poff = C.nparams;
+        C.nparams += (size_t)it.c->nparams;
     }
     C.nout = nout;
     C.prog_bytes = off;
     YAO_TRY(dev_alloc((void**)&C.d_prog, C.prog_bytes));
     YAO_TRY(host_alloc((void**)&C.h_prog, C.prog_bytes));
+    YAO_TRY(dev_alloc((void**)&C.d_params, sizeof(double) * std::max<size_t>(1, C.nparams)));
+    YAO_TRY(host_alloc((void**)&C.h_params, sizeof(double) * std::max<size_t>(1, C.nparams)));
+    pack_params(C, params);
     YAO_TRY(dev_alloc((void**)&C.d_out, sizeof(double) * C.nout));
     YAO_TRY(host_alloc((void**)&C.h_out, sizeof(double) * C.nout));
     for (int b = 0; b < kBanks; ++b) {
@@ -354,13 +406,13 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
         const double s = (double)it.s->elem_bytes();
         for (size_t p = 0; p < it.fwd->passes.size(); ++p) {
             C.algo_bytes += 2.0 * s * N;
-            C.algo_flops += it.pf.pass_flops[p] * N;
+            C.algo_flops += fwd_prog(it).pass_flops[p] * N;
         }
         C.algo_bytes += 2.0 * s * N + 16.0 * N;  // H psi reads psi, writes lambda; FP64 copy
         if (!it.nslots) continue;
         for (size_t p = 0; p < it.bwd->passes.size(); ++p) {
             C.algo_bytes += 2.0 * (16.0 + s) * N;
-            C.algo_flops += it.pb.pass_flops[p] * N;
+            C.algo_flops += bwd_prog(it).pass_flops[p] * N;
         }
     }
     return 0;
@@ -386,13 +438,15 @@ int record(Cache& C)
             const int n = it.s->n, dt = it.s->dtype, bk = it.bank;
             set_stream(g_bank[bk]);
             if ((rc = launch_fill_basis(it.s->data, dt, n, 1))) break;
-            if ((rc = launch_forward_passes(*it.fwd, it.pf, it.df, it.s->data, dt, n, 1, it.fc, nullptr))) break;
+            if (it.bf && (rc = bind_program(it.bf, C.d_params + it.poff))) break;
+            if ((rc = launch_forward_passes(*it.fwd, fwd_prog(it), it.df, it.s->data, dt, n, 1, it.fc, nullptr))) break;
             if ((rc = launch_hpsi_dev(it.s->data, dt, C.lam[bk], dt, n, 1, it.h, C.hpart[bk], C.d_out + it.out_e)))
                 break;
             if (it.nslots == 0) continue;
             if ((rc = launch_convert(it.s->data, dt, C.psi64[bk], YAO_C128, size_t(1) << n))) break;
             if ((rc = launch_fill(C.gpart[bk], (size_t)it.nslots * it.W, 0.0))) break;
-            if ((rc = launch_backward_passes(*it.bwd, it.pb, it.db, it.c, nullptr, C.psi64[bk], C.lam[bk], dt, n, 1,
+            if (it.bb && (rc = bind_program(it.bb, C.d_params + it.poff))) break;
+            if ((rc = launch_backward_passes(*it.bwd, bwd_prog(it), it.db, it.c, nullptr, C.psi64[bk], C.lam[bk], dt, n, 1,
                                              C.gpart[bk], it.W)))
                 break;
             if ((rc = launch_row_sums(C.gpart[bk], it.nslots, it.W, C.d_out + it.out_g))) break;
@@ -437,7 +491,10 @@ int batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* cir
         const int r = build_programs(*g_cache, params, false);
         if (r < 0) return r;
         if (r == 1) fresh = true;
-        else pack_all(*g_cache);
+        else {
+            pack_all(*g_cache);
+            pack_params(*g_cache, params);
+        }
     }
     if (fresh) {
         YAO_HIP(hipStreamSynchronize(origin));
@@ -455,7 +512,9 @@ int batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* cir
     }
     Cache& C = *g_cache;
     const int pi = prof_begin(YAO_KF_BATCH);
-    YAO_HIP(hipMemcpyAsync(C.d_prog, C.h_prog, C.prog_bytes, hipMemcpyHostToDevice, origin));
+    if (C.prog_bytes) YAO_HIP(hipMemcpyAsync(C.d_prog, C.h_prog, C.prog_bytes, hipMemcpyHostToDevice, origin));
+    if (C.nparams)
+        YAO_HIP(hipMemcpyAsync(C.d_params, C.h_params, sizeof(double) * C.nparams, hipMemcpyHostToDevice, origin));
     YAO_HIP(hipGraphLaunch(C.exec, origin));
     prof_end(pi, C.algo_bytes, C.algo_flops);
     YAO_HIP(hipMemcpyAsync(C.h_out, C.d_out, sizeof(double) * C.nout, hipMemcpyDeviceToHost, origin));
@@ -467,7 +526,7 @@ int batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* cir
         for (int p = 0; p < P; ++p) g[p] = 0.0;
         if (!it.nslots) continue;
         for (int gi = (int)it.c->gates.size() - 1; gi >= 0; --gi) {
-            const int slot = it.pb.slot_of_gate[gi];
+            const int slot = bwd_prog(it).slot_of_gate[gi];
             if (slot >= 0) g[it.c->gates[gi].param] += C.h_out[it.out_g + slot];
         }
     }

@@ -78,9 +78,44 @@ static void append(std::vector<double>& v, const std::vector<double>& a)
     v.insert(v.end(), a.begin(), a.end());
 }
 
-int build_program(const Plan& P, const yao_circuit* c, const double* params, bool bwd, int dtype, Program& prog)
+// One-qubit gate kinds k_bind evaluates from an angle (fixed kinds take none).
+static bool bindable_kind(int kind)
+{
+    return kind == YAO_X || kind == YAO_Y || kind == YAO_Z || kind == YAO_H || kind == YAO_S || kind == YAO_SDAG ||
+           kind == YAO_T || kind == YAO_TDAG || kind == YAO_RX || kind == YAO_RY || kind == YAO_RZ ||
+           kind == YAO_SHIFT;
+}
+
+int build_program(const Plan& P, const yao_circuit* c, const double* params, bool bwd, int dtype, Program& prog,
+                  const std::vector<FusedPart>* parts, const yao_circuit* orig)
 {
     const int G = (int)c->gates.size();
+    const bool bind = params == nullptr;
+    // Factors of gate gi of c: the member gates of a fused placeholder, else the gate itself.
+    auto placeholder = [&](int gi) { return parts && !(*parts)[gi].single; };
+    auto param_dependent = [&](int gi) {
+        if (placeholder(gi)) {
+            for (int og : (*parts)[gi].gates)
+                if (orig->gates[og].param >= 0 && is_param_kind(orig->gates[og].kind)) return true;
+            return false;
+        }
+        return c->gates[gi].param >= 0 && is_param_kind(c->gates[gi].kind);
+    };
+    // Matrix of gate gi for the host when nothing in it depends on parameters.
+    auto fixed_matrix = [&](int gi, HostMat& U) {
+        if (!placeholder(gi)) return gate_matrix(c->gates[gi], c->gates[gi].theta, U);
+        const FusedPart& fp = (*parts)[gi];
+        U.resize((int)fp.qubits.size());
+        for (int d = 0; d < U.dim(); ++d) U.re[(size_t)d * U.dim() + d] = 1.0;
+        static thread_local HostMat F;
+        for (int og : fp.gates) {
+            const GateRec& h = orig->gates[og];
+            if (!gate_matrix(h, h.theta, F) || h.k != 1 || h.nctrl) return false;
+            HostMat T = matmul(F, U);
+            U = T;
+        }
+        return true;
+    };
     prog.slot_of_gate.assign(G, -1);
     if (bwd) {
         for (int g = 0; g < G; ++g)
@@ -101,9 +136,13 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
             // launch reads.
             const int gi = P.ops[pass.standalone].gate;
             const GateRec& g = c->gates[gi];
-            const double th = gate_theta(g, params);
+            if (bind && param_dependent(gi)) {
+                prog.bindable = false;  // a wide parameterised gate: matrices from the host only
+                continue;
+            }
+            const double th = bind ? g.theta : gate_theta(g, params);
             HostMat U;
-            if (!gate_matrix(g, th, U)) return set_error(YAO_EINVAL, "bad gate %d", gi);
+            if (!(bind ? fixed_matrix(gi, U) : gate_matrix(g, th, U))) return set_error(YAO_EINVAL, "bad gate %d", gi);
             if (!bwd) {
                 prog.pass_mat.back() = (int)encode_gate_matrix(dtype, P.n, P.B, U, prog.mats);
             } else {
@@ -142,9 +181,21 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
             for (int oi : hg.ops) {
                 const HostOp& hop = P.ops[oi];
                 const GateRec& g = c->gates[hop.gate];
-                const double th = gate_theta(g, params);
-                HostMat U;
-                if (!gate_matrix(g, th, U)) return set_error(YAO_EINVAL, "bad gate %d", hop.gate);
+                static thread_local HostMat U, Ud, M;  // reused across ops and calls
+                const bool pdep = bind && param_dependent(hop.gate);
+                double th = 0;
+                if (!bind) {
+                    th = gate_theta(g, params);
+                    if (!gate_matrix(g, th, U)) return set_error(YAO_EINVAL, "bad gate %d", hop.gate);
+                } else if (!pdep) {
+                    th = g.theta;
+                    if (!fixed_matrix(hop.gate, U)) return set_error(YAO_EINVAL, "bad gate %d", hop.gate);
+                } else {
+                    // Placeholder values: the matrix is written on the device by k_bind.
+                    if (g.k != 1 || hg.dense) prog.bindable = false;
+                    U.resize(g.k);
+                    for (int d = 0; d < U.dim(); ++d) U.re[(size_t)d * U.dim() + d] = 1.0;
+                }
                 POp op;
                 memset(&op, 0, sizeof(op));
                 op.k = g.k;
@@ -156,11 +207,10 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     append(prog.mats, U.re);
                     append(prog.mats, U.im);
                 } else {
-                    HostMat Ud = dagger(U);
+                    dagger_into(U, Ud);
                     op.type = op_type_of(Ud);
                     append(prog.mats, Ud.re);
                     append(prog.mats, Ud.im);
-                    HostMat M;
                     if (op.slot >= 0) {
                         gate_grad_matrix(g, th, M);
                         op.gen = gen_type_of(g);
@@ -233,6 +283,27 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                         }
                     }
                 }
+                if (pdep && g.k == 1) {
+                    // Factors for k_bind, and the structure class the bound matrix will have.
+                    BindRec br;
+                    br.op = (int)prog.ops.size();
+                    br.f0 = (int)prog.facs.size();
+                    br.mode = bwd ? 2 : (dtype == YAO_C64 ? 0 : 1);
+                    if (placeholder(hop.gate)) {
+                        for (int og : (*parts)[hop.gate].gates) {
+                            const GateRec& h = orig->gates[og];
+                            prog.facs.push_back(BindFac{h.kind, is_param_kind(h.kind) ? h.param : -1, h.theta});
+                        }
+                    } else {
+                        prog.facs.push_back(BindFac{g.kind, g.param, g.theta});
+                    }
+                    br.nf = (int)prog.facs.size() - br.f0;
+                    for (int f = br.f0; f < br.f0 + br.nf; ++f) prog.bindable &= bindable_kind(prog.facs[f].kind);
+                    prog.binds.push_back(br);
+                    const int k1 = prog.facs[br.f0].kind;
+                    op.type = br.nf > 1 ? OT_DENSE
+                                        : (k1 == YAO_RX ? OT_RX : (k1 == YAO_RY ? OT_REAL : (k1 == YAO_RZ || k1 == YAO_SHIFT ? OT_DIAG : OT_DENSE)));
+                }
                 if (g.k == 1) {
                     // The forward kernel of complex64 states reads the 2x2 matrix as float[8].
                     if (!bwd && dtype == YAO_C64) {
@@ -304,13 +375,24 @@ void pack_program(const Program& prog, char* host, char* dev, DevProgram& d)
     d.mats = (double*)(dev + al256(so) + al256(sg));
 }
 
-static int upload_program(const Program& prog, DevProgram& d)
+// Pack a program into the slot's pinned buffer and queue its copy to the slot's device
+// buffer; the host returns at once. The caller synchronises the stream before the slot is
+// packed again.
+static hipEvent_t g_copied[WS_COUNT] = {};
+
+static int upload_program(const Program& prog, DevProgram& d, int slot = WS_MAT)
 {
-    std::vector<char> blob(program_blob_bytes(prog));
-    char* dev = (char*)workspace(WS_MAT, blob.size());
+    // The previous copy out of this slot's pinned buffer has to be done before it is reused.
+    if (!g_copied[slot]) YAO_HIP(hipEventCreateWithFlags(&g_copied[slot], hipEventDisableTiming));
+    else YAO_HIP(hipEventSynchronize(g_copied[slot]));
+    const size_t bytes = program_blob_bytes(prog);
+    char* dev = (char*)workspace(slot, bytes);
     if (!dev) return YAO_ENOMEM;
-    pack_program(prog, blob.data(), dev, d);
-    if (!upload_to(WS_MAT, blob.data(), blob.size())) return YAO_ENOMEM;
+    char* host = (char*)pinned(slot, bytes);
+    if (!host) return YAO_ENOMEM;
+    pack_program(prog, host, dev, d);
+    YAO_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, stream()));
+    YAO_HIP(hipEventRecord(g_copied[slot], stream()));
     return 0;
 }
 
@@ -362,6 +444,96 @@ int launch_backward_passes(const Plan& P, const Program& prog, const DevProgram&
     return 0;
 }
 
+// ---------------------------------------------------------------------- device-bound programs
+// A plan's program built once without parameters and kept in device memory; each call only
+// copies the parameters and runs k_bind over the parameter-dependent matrices.
+static std::map<std::tuple<const Plan*, bool, int>, BoundProgram*> g_bound;
+static std::mutex g_bound_mu;
+
+static void free_bound(BoundProgram* b)
+{
+    if (b->dev) (void)hipFree(b->dev);
+    if (b->dbinds) (void)hipFree(b->dbinds);
+    if (b->dfacs) (void)hipFree(b->dfacs);
+    delete b;
+}
+
+void drop_bound(const yao_circuit* c)
+{
+    std::lock_guard<std::mutex> lk(g_bound_mu);
+    for (auto it = g_bound.begin(); it != g_bound.end();) {
+        if (it->second->circ == c) {
+            (void)hipDeviceSynchronize();
+            free_bound(it->second);
+            it = g_bound.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+// The bound program of plan P over circuit c (with parts/orig for a fused structure), or
+// nullptr when it cannot be bound on the device. Built and copied on first use.
+const BoundProgram* bound_program(const Plan& P, const yao_circuit* c, bool bwd, int dtype,
+                                  const std::vector<FusedPart>* parts, const yao_circuit* orig)
+{
+    std::lock_guard<std::mutex> lk(g_bound_mu);
+    const auto key = std::make_tuple(&P, bwd, dtype);
+    auto it = g_bound.find(key);
+    if (it != g_bound.end()) return it->second->ok ? it->second : nullptr;
+    BoundProgram* b = new BoundProgram;
+    b->circ = orig ? orig : c;
+    g_bound[key] = b;
+    if (build_program(P, c, nullptr, bwd, dtype, b->prog, parts, orig) != 0 || !b->prog.bindable) return nullptr;
+    const size_t bytes = program_blob_bytes(b->prog);
+    std::vector<char> host(bytes);
+    const size_t nb = std::max<size_t>(1, b->prog.binds.size()), nf = std::max<size_t>(1, b->prog.facs.size());
+    if (hipMalloc((void**)&b->dev, bytes) != hipSuccess || hipMalloc((void**)&b->dbinds, nb * sizeof(BindRec)) != hipSuccess ||
+        hipMalloc((void**)&b->dfacs, nf * sizeof(BindFac)) != hipSuccess) {
+        set_error(YAO_ENOMEM, "bound program of %zu bytes", bytes);
+        return nullptr;
+    }
+    pack_program(b->prog, host.data(), b->dev, b->d);
+    if (hipMemcpy(b->dev, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        (!b->prog.binds.empty() && hipMemcpy(b->dbinds, b->prog.binds.data(), b->prog.binds.size() * sizeof(BindRec),
+                                             hipMemcpyHostToDevice) != hipSuccess) ||
+        (!b->prog.facs.empty() && hipMemcpy(b->dfacs, b->prog.facs.data(), b->prog.facs.size() * sizeof(BindFac),
+                                            hipMemcpyHostToDevice) != hipSuccess)) {
+        set_error(YAO_EHIP, "copying a bound program");
+        return nullptr;
+    }
+    b->ok = true;
+    return b;
+}
+
+// Copy the parameters to the device (queued; the pinned buffer is reused only after the copy
+// is done). Returns the device array, or nullptr on failure.
+const double* upload_params(const double* params, int nparams)
+{
+    static hipEvent_t done = nullptr;
+    if (!done) {
+        if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) return nullptr;
+    } else if (hipEventSynchronize(done) != hipSuccess) {
+        return nullptr;
+    }
+    const size_t bytes = sizeof(double) * (size_t)std::max(1, nparams);
+    double* dev = (double*)workspace(WS_PARAMS, bytes);
+    double* host = (double*)pinned(WS_PARAMS, bytes);
+    if (!dev || !host) return nullptr;
+    if (nparams > 0) {
+        memcpy(host, params, sizeof(double) * (size_t)nparams);
+        if (hipMemcpyAsync(dev, host, sizeof(double) * (size_t)nparams, hipMemcpyHostToDevice, stream()) != hipSuccess)
+            return nullptr;
+    }
+    if (hipEventRecord(done, stream()) != hipSuccess) return nullptr;
+    return dev;
+}
+
+int bind_program(const BoundProgram* b, const double* dparams)
+{
+    return launch_bind(b->d.ops, b->dbinds, (int)b->prog.binds.size(), b->dfacs, dparams);
+}
+
 namespace {
 
 int run_forward_plan(const Plan& P, void* data, int dtype, int n, int B, const yao_circuit* c, const double* params)
@@ -399,12 +571,127 @@ int forward_fused_range(void* data, int dtype, int n, int B, const yao_circuit* 
     if (g1 <= g0) return 0;
     int t, cb, L;
     tile_geometry(n, B, dtype, false, &t, &cb, &L);
-    return run_forward_plan(get_plan(c, g0, g1, B, t, cb, L, false), data, dtype, n, B, c, params);
+    const Plan& P = get_plan(c, g0, g1, B, t, cb, L, false);
+    const BoundProgram* bp = c->transient ? nullptr : bound_program(P, c, false, dtype, nullptr, nullptr);
+    if (!bp) return run_forward_plan(P, data, dtype, n, B, c, params);
+    const double* dp = c->nparams > 0 ? upload_params(params, c->nparams) : nullptr;
+    if (c->nparams > 0 && !dp) return YAO_ENOMEM;
+    YAO_TRY(bind_program(bp, dp));
+    return launch_forward_passes(P, bp->prog, bp->d, data, dtype, n, B, c, params);
 }
 
 int forward_fused(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params)
 {
-    return forward_fused_range(data, dtype, n, B, c, params, 0, (int)c->gates.size());
+    return forward_sweep(data, dtype, n, B, c, params, 0, options().tile_qubits, nullptr);
+}
+
+int forward_sweep(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params, int width, int tq,
+                  const double* dparams)
+{
+    if (c->gates.empty()) return 0;
+    int t, cb, L;
+    tile_geometry_tq(n, B, dtype, false, tq, &t, &cb, &L);
+    if (!c->transient) {
+        // Bound on the device: the circuit itself (width 0) or the structure of its fused form.
+        const std::vector<FusedPart>* parts = nullptr;
+        const yao_circuit* sc = width > 0 ? fused_shape(c, width, &parts) : c;
+        const Plan& P = get_plan(sc, 0, (int)sc->gates.size(), B, t, cb, L, false);
+        const BoundProgram* bp = bound_program(P, sc, false, dtype, parts, width > 0 ? c : nullptr);
+        if (bp) {
+            if (!dparams && c->nparams > 0) {
+                dparams = upload_params(params, c->nparams);
+                if (!dparams) return YAO_ENOMEM;
+            }
+            YAO_TRY(bind_program(bp, dparams));
+            return launch_forward_passes(P, bp->prog, bp->d, data, dtype, n, B, sc, nullptr);
+        }
+    }
+    // Host-built program for these parameters (dense fused blocks, or gates the device cannot bind).
+    const yao_circuit* hc = width > 0 && !c->transient ? fused_circuit(c, params, width) : c;
+    const double* hp = hc == c ? params : nullptr;
+    const Plan& P = get_plan(hc, 0, (int)hc->gates.size(), B, t, cb, L, false);
+    return run_forward_plan(P, data, dtype, n, B, hc, hp);
+}
+
+// Sum the per-tile gradient partials of each gate slot into the caller's layout.
+static void gather_gradients(const yao_circuit* c, const std::vector<int>& slot_of_gate, const double* sums, int B,
+                             bool reduce_batch, double* grad)
+{
+    const int P_ = c->nparams;
+    const size_t glen = reduce_batch ? (size_t)P_ : (size_t)P_ * B;
+    for (size_t e = 0; e < glen; ++e) grad[e] = 0.0;
+    for (int gi = (int)c->gates.size() - 1; gi >= 0; --gi) {
+        const int slot = slot_of_gate.empty() ? -1 : slot_of_gate[gi];
+        if (slot < 0) continue;
+        const int p = c->gates[gi].param;
+        for (int b = 0; b < B; ++b) {
+            const double v = sums[(size_t)slot * B + b];
+            if (reduce_batch) grad[p] += v;
+            else grad[(size_t)b * P_ + p] += v;
+        }
+    }
+}
+
+// The reversible sweep as one plan. The forward sweep only has to produce the final state, so
+// it may fold gates into dense blocks; the reverse program is built on the host while the
+// device runs the forward sweep, and nothing waits for the device until the results are read.
+static int backward_reversible(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h,
+                               bool reduce_batch, double* energy, double* grad, double* drift, const void* psi0)
+{
+    const int n = s->n, B = s->batch;
+    const size_t elems = s->elems();
+    const int G = (int)c->gates.size();
+    hipStream_t st = stream();
+    int t, cb, L;
+    tile_geometry(n, B, s->dtype, true, &t, &cb, &L);
+    const int ntiles = 1 << (n - (t - cb));
+    const int W = std::max(ntiles, adjoint_nblk(n, 1, B));
+    const int nslots = count_slots(c);
+    double* psi = (double*)workspace(WS_PSI64, elems * 16);
+    void* lam = workspace(WS_LAM, s->bytes());
+    double* gpartial = (double*)workspace(WS_PARTIAL, sizeof(double) * (size_t)std::max(1, nslots) * B * W);
+    const size_t hp = hpsi_partial_doubles(n, B);
+    double* misc = (double*)workspace(WS_MISC, sizeof(double) * (hp + (size_t)B + (size_t)std::max(1, nslots) * B));
+    if (!psi || !lam || !gpartial || !misc) return YAO_ENOMEM;
+    double* edev = misc + hp;
+    double* sums = edev + B;
+
+    YAO_TRY(pauli_upload(h));
+    int width = 0;
+    YAO_TRY(pick_forward_width(c, params, s->data, s->dtype, n, B, &width));
+    const double* dp = nullptr;
+    if (c->nparams > 0) {
+        dp = upload_params(params, c->nparams);
+        if (!dp) return YAO_ENOMEM;
+    }
+    YAO_TRY(forward_sweep(s->data, s->dtype, n, B, c, params, width, options().tile_qubits, dp));
+
+    const Plan& P = get_plan(c, 0, G, B, t, cb, L, true);
+    const BoundProgram* bp = bound_program(P, c, true, s->dtype, nullptr, nullptr);
+    Program hprog;
+    if (!bp) YAO_TRY(build_program(P, c, params, true, s->dtype, hprog));
+    YAO_TRY(launch_convert(s->data, s->dtype, psi, YAO_C128, elems));
+    YAO_TRY(launch_hpsi_dev(s->data, s->dtype, lam, s->dtype, n, B, h, misc, edev));
+    if (nslots) YAO_TRY(launch_fill(gpartial, (size_t)nslots * B * W, 0.0));
+    DevProgram hd;
+    if (bp) YAO_TRY(bind_program(bp, dp));
+    else YAO_TRY(upload_program(hprog, hd, WS_MAT2));
+    const Program& prog = bp ? bp->prog : hprog;
+    YAO_TRY(launch_backward_passes(P, prog, bp ? bp->d : hd, c, params, psi, lam, s->dtype, n, B, gpartial, W));
+    if (nslots) YAO_TRY(launch_row_sums(gpartial, nslots * B, W, sums));
+    const size_t nres = (size_t)B + (size_t)nslots * B;
+    double* hres = (double*)pinned(WS_PARTIAL, sizeof(double) * nres);
+    if (!hres) return YAO_ENOMEM;
+    YAO_HIP(hipMemcpyAsync(hres, edev, sizeof(double) * nres, hipMemcpyDeviceToHost, st));
+    double dend = 0;
+    YAO_TRY(launch_maxdiff(psi, YAO_C128, psi0, s->dtype, elems, &dend));  // synchronises the stream
+    for (int b = 0; b < B; ++b) energy[b] = hres[b];
+    gather_gradients(c, prog.slot_of_gate, hres + B, B, reduce_batch, grad);
+    if (drift) *drift = dend;
+    if (options().drift_tol > 0 && dend > options().drift_tol)
+        return set_error(YAO_EDRIFT, "uncomputed input differs from the input by %.3g > %.3g", dend,
+                         options().drift_tol);
+    return 0;
 }
 
 int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h, int mode,
@@ -435,16 +722,8 @@ int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao
         ckpt = (char*)workspace(WS_CKPT, s->bytes() * (size_t)(nseg - 1));
         if (!ckpt) return YAO_ENOMEM;
     }
-    if (nseg == 1) {
-        // One segment: the forward sweep only has to produce the final state, so it may run
-        // with gates folded into dense blocks; the reverse sweep still takes them one by one.
-        int width = 0;
-        YAO_TRY(pick_forward_width(c, params, s->data, s->dtype, n, B, &width));
-        const double* fp = params;
-        const yao_circuit* fc = forward_circuit(c, params, width, &fp);
-        YAO_TRY(forward_fused(s->data, s->dtype, n, B, fc, fp));
-    }
-    for (int sg = 0; sg < nseg && nseg > 1; ++sg) {
+    if (nseg == 1) return backward_reversible(s, c, params, h, reduce_batch, energy, grad, drift, psi0);
+    for (int sg = 0; sg < nseg; ++sg) {
         YAO_TRY(forward_fused_range(s->data, s->dtype, n, B, c, params, cuts[sg], cuts[sg + 1]));
         if (sg + 1 < nseg)
             YAO_HIP(hipMemcpyAsync(ckpt + s->bytes() * sg, s->data, s->bytes(), hipMemcpyDeviceToDevice, st));
@@ -514,6 +793,7 @@ int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao
 
 void drop_plans(const yao_circuit* c)
 {
+    drop_bound(c);
     std::lock_guard<std::mutex> lk(g_plan_mu);
     for (auto it = g_plans.begin(); it != g_plans.end();) {
         if (std::get<0>(it->first) == c) it = g_plans.erase(it);

@@ -97,6 +97,19 @@ void tile_geometry(int n, int B, int dtype, bool backward, int* t, int* cbits, i
 // The same for an explicit number of tile qubits (<= 0: default).
 void tile_geometry_tq(int n, int B, int dtype, bool backward, int tq, int* t, int* cbits, int* low_fixed);
 
+// Parameter binding on the device: op record `op` (index in the program's records) takes the
+// one-qubit matrix U = U_{nf-1} ... U_0 of factors f0 .. f0 + nf - 1, each a gate kind with
+// its angle from params[param] (param >= 0) or theta. mode 0: U as float[8] (forward,
+// complex64), 1: U as double[8] (forward, complex128), 2: U^dagger as double[8] (reverse).
+struct BindRec {
+    int op, f0, nf, mode;
+};
+struct BindFac {
+    int kind, param;
+    double theta;
+};
+static_assert(sizeof(BindRec) == 16 && sizeof(BindFac) == 16, "bind table layout");
+
 // Device program of one plan for given parameters (built on the host, copied in one block).
 struct Program {
     std::vector<POp> ops;
@@ -111,6 +124,10 @@ struct Program {
     std::vector<int> pass_dmat_words;  // their size in 16-byte words (0: none)
     std::vector<int> slot_of_gate;  // gradient slot per gate (-1)
     int nslots = 0;
+    // Built without parameters: the matrices that depend on them are left to k_bind.
+    std::vector<BindRec> binds;
+    std::vector<BindFac> facs;
+    bool bindable = true;  // false: some parameter-dependent matrix cannot be bound on the device
 };
 struct DevProgram {
     POp* ops;
@@ -118,8 +135,14 @@ struct DevProgram {
     double* mats;
 };
 const Plan& get_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse);
-// dtype: the state's (forward) or the adjoint state's (backward) precision.
-int build_program(const Plan& P, const yao_circuit* c, const double* params, bool bwd, int dtype, Program& prog);
+// dtype: the state's (forward) or the adjoint state's (backward) precision. With params null
+// the program is built for binding on the device (Program::binds); when c is the structure of a
+// fused circuit (fused_shape), parts and orig describe its multi-gate placeholders.
+struct FusedPart;
+int build_program(const Plan& P, const yao_circuit* c, const double* params, bool bwd, int dtype, Program& prog,
+                  const std::vector<FusedPart>* parts = nullptr, const yao_circuit* orig = nullptr);
+// Fill the bound matrices of a device program (see BindRec) for the device array params.
+int launch_bind(POp* ops, const BindRec* binds, int nbinds, const BindFac* facs, const double* params);
 size_t program_blob_bytes(const Program& prog);
 void pack_program(const Program& prog, char* host, char* dev, DevProgram& d);
 // Launch the passes of a plan whose program is already in device memory (no host sync, no
@@ -132,6 +155,25 @@ int launch_backward_passes(const Plan& P, const Program& prog, const DevProgram&
 
 // Drivers.
 int forward_fused(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params);
+// Forward sweep at fusion width `width` (0: none) over tiles of tq qubits (<= 0: default);
+// dparams: c's parameters already on the device, or null.
+int forward_sweep(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params, int width, int tq,
+                  const double* dparams);
+// Device-bound programs (built once per plan; see BindRec).
+struct BoundProgram {
+    const yao_circuit* circ = nullptr;
+    Program prog;
+    char* dev = nullptr;
+    DevProgram d{};
+    BindRec* dbinds = nullptr;
+    BindFac* dfacs = nullptr;
+    bool ok = false;  // false: the program needs the host for some matrix
+};
+const BoundProgram* bound_program(const Plan& P, const yao_circuit* c, bool bwd, int dtype,
+                                  const std::vector<FusedPart>* parts, const yao_circuit* orig);
+const double* upload_params(const double* params, int nparams);
+int bind_program(const BoundProgram* b, const double* dparams);
+void drop_bound(const yao_circuit* c);
 // Gates [g0, g1) only.
 int forward_fused_range(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params, int g0,
                         int g1);

@@ -3,10 +3,13 @@
 //
 // Gates are taken in order. Open blocks act on disjoint qubit sets, so they commute with each
 // other; a gate whose qubits (targets and controls) fit in `width` qubits together with every
-// open block it meets is multiplied into the union of those blocks (a chain is the matrix
-// product in reverse order, Sec. "Representing Quantum Circuits"); a gate that meets no block
-// opens one; any other gate first closes (emits) every block it meets. Products are formed in
-// FP64.
+// open block it meets joins the union of those blocks; a gate that meets no block opens one;
+// any other gate first closes (emits) every block it meets. A block's matrix is the product of
+// its gates in order (a chain is the matrix product in reverse order, Sec. "Representing
+// Quantum Circuits"), formed in FP64 by applying each gate to the columns of the block matrix.
+//
+// The partition depends only on the circuit's structure and is kept per circuit and width;
+// each call only recomputes the block matrices for its parameters.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -18,11 +21,6 @@ namespace yao {
 
 namespace {
 
-struct Block {
-    std::vector<int> qubits;  // ascending; bit j of the matrix index <-> qubits[j]
-    HostMat M;
-};
-
 int position(const std::vector<int>& qs, int q)
 {
     for (size_t j = 0; j < qs.size(); ++j)
@@ -30,88 +28,20 @@ int position(const std::vector<int>& qs, int q)
     return -1;
 }
 
-// Widen a block to the qubit set `qs` (a superset), as M (x) identity on the new qubits.
-void widen(Block& b, const std::vector<int>& qs)
-{
-    const int k = (int)qs.size();
-    HostMat W;
-    W.resize(k);
-    std::vector<int> map(b.qubits.size());
-    for (size_t j = 0; j < b.qubits.size(); ++j) map[j] = position(qs, b.qubits[j]);
-    uint64_t oldmask = 0;
-    for (int p : map) oldmask |= uint64_t(1) << p;
-    const int dn = 1 << k, dold = b.M.dim();
-    for (int r = 0; r < dn; ++r)
-        for (int c = 0; c < dn; ++c) {
-            if ((r & ~oldmask) != (c & ~oldmask)) continue;
-            int ro = 0, co = 0;
-            for (size_t j = 0; j < map.size(); ++j) {
-                ro |= ((r >> map[j]) & 1) << j;
-                co |= ((c >> map[j]) & 1) << j;
-            }
-            W.re[(size_t)r * dn + c] = b.M.re[(size_t)ro * dold + co];
-            W.im[(size_t)r * dn + c] = b.M.im[(size_t)ro * dold + co];
-        }
-    b.qubits = qs;
-    b.M = W;
-}
-
-// Full operator of gate g (matrix U on its targets, identity where its controls fail) on
-// the block's qubit set.
-HostMat embed(const GateRec& g, const HostMat& U, const std::vector<int>& qs)
-{
-    const int k = (int)qs.size(), dn = 1 << k;
-    HostMat F;
-    F.resize(k);
-    int tp[8], cp[8];
-    for (int j = 0; j < g.k; ++j) tp[j] = position(qs, g.locs[j]);
-    for (int m = 0; m < g.nctrl; ++m) cp[m] = position(qs, g.ctrls[m]);
-    const int du = U.dim();
-    for (int c = 0; c < dn; ++c) {
-        bool pass = true;
-        for (int m = 0; m < g.nctrl; ++m) pass &= ((c >> cp[m]) & 1) == g.cvals[m];
-        if (!pass) {
-            F.re[(size_t)c * dn + c] = 1.0;
-            continue;
-        }
-        int sin = 0, clear = c;
-        for (int j = 0; j < g.k; ++j) {
-            sin |= ((c >> tp[j]) & 1) << j;
-            clear &= ~(1 << tp[j]);
-        }
-        for (int sout = 0; sout < du; ++sout) {
-            int r = clear;
-            for (int j = 0; j < g.k; ++j) r |= ((sout >> j) & 1) << tp[j];
-            F.re[(size_t)r * dn + c] += U.re[(size_t)sout * du + sin];
-            F.im[(size_t)r * dn + c] += U.im[(size_t)sout * du + sin];
-        }
-    }
-    return F;
-}
-
-GateRec dense_rec(const Block& b)
-{
-    GateRec r;
-    r.kind = YAO_DENSE;
-    r.param = -1;
-    r.theta = 0;
-    r.k = (int)b.qubits.size();
-    for (int j = 0; j < r.k; ++j) r.locs[j] = b.qubits[j];
-    r.nctrl = 0;
-    r.G.resize(size_t(2) << (2 * r.k));
-    for (size_t t = 0; t < b.M.re.size(); ++t) {
-        r.G[2 * t] = b.M.re[t];
-        r.G[2 * t + 1] = b.M.im[t];
-    }
-    return r;
-}
-
 std::vector<int> qubits_of(const GateRec& g)
 {
     std::vector<int> q;
     for (int j = 0; j < g.k; ++j) q.push_back(g.locs[j]);
     for (int m = 0; m < g.nctrl; ++m) q.push_back(g.ctrls[m]);
+    std::sort(q.begin(), q.end());
     return q;
+}
+
+bool meets(const std::vector<int>& a, const std::vector<int>& b)
+{
+    for (int q : b)
+        if (position(a, q) >= 0) return true;
+    return false;
 }
 
 std::vector<int> merged(const std::vector<int>& a, const std::vector<int>& b)
@@ -123,120 +53,209 @@ std::vector<int> merged(const std::vector<int>& a, const std::vector<int>& b)
     return m;
 }
 
-bool meets(const std::vector<int>& a, const std::vector<int>& b)
+std::vector<FusedPart> partition(const yao_circuit* c, int width)
 {
-    for (int q : b)
-        if (position(a, q) >= 0) return true;
-    return false;
-}
-
-struct Shadow {
-    yao_circuit circ;
-};
-
-std::map<std::tuple<const yao_circuit*, uint64_t, int>, Shadow*> g_shadows;
-std::mutex g_shadow_mu;
-
-}  // namespace
-
-std::vector<GateRec> fuse_gates(const yao_circuit* c, const double* params, int width)
-{
-    std::vector<GateRec> out;
-    std::vector<Block> open;
+    std::vector<FusedPart> out, open;
     auto close_meeting = [&](const std::vector<int>& q) {
         for (size_t b = 0; b < open.size();) {
             if (meets(open[b].qubits, q)) {
-                out.push_back(dense_rec(open[b]));
+                out.push_back(open[b]);
                 open.erase(open.begin() + b);
             } else {
                 ++b;
             }
         }
     };
-    for (const GateRec& g : c->gates) {
-        const std::vector<int> q = qubits_of(g);
-        HostMat U;
-        gate_matrix(g, gate_theta(g, params), U);
-        std::vector<int> hits;
-        std::vector<int> qs = merged({}, q);
+    for (int gi = 0; gi < (int)c->gates.size(); ++gi) {
+        const std::vector<int> q = qubits_of(c->gates[gi]);
+        if ((int)q.size() > width) {
+            close_meeting(q);
+            FusedPart p;
+            p.qubits = q;
+            p.gates = {gi};
+            p.single = true;
+            out.push_back(p);
+            continue;
+        }
+        std::vector<int> hits, qs = q;
         for (size_t b = 0; b < open.size(); ++b)
             if (meets(open[b].qubits, q)) {
                 hits.push_back((int)b);
                 qs = merged(qs, open[b].qubits);
             }
-        if (!hits.empty() && (int)qs.size() <= width) {
-            // The blocks it meets act on disjoint qubits, so they commute: their product on the
-            // union is the product of the widened blocks, in any order.
-            Block nb;
+        if ((int)qs.size() <= width) {
+            // The blocks it meets act on disjoint qubits and commute: their gates can follow
+            // each other in any order.
+            FusedPart nb;
             nb.qubits = qs;
-            nb.M.resize((int)qs.size());
-            for (int d = 0; d < nb.M.dim(); ++d) nb.M.re[(size_t)d * nb.M.dim() + d] = 1.0;
-            for (int h : hits) {
-                Block w = open[h];
-                widen(w, qs);
-                nb.M = matmul(w.M, nb.M);
-            }
-            nb.M = matmul(embed(g, U, nb.qubits), nb.M);
+            for (int h : hits) nb.gates.insert(nb.gates.end(), open[h].gates.begin(), open[h].gates.end());
+            nb.gates.push_back(gi);
             for (int i = (int)hits.size() - 1; i >= 0; --i) open.erase(open.begin() + hits[i]);
             open.push_back(nb);
-            continue;
-        }
-        close_meeting(q);
-        if ((int)q.size() <= width) {
-            Block b;
-            b.qubits = merged({}, q);
-            b.M = embed(g, U, b.qubits);
-            open.push_back(b);
         } else {
-            // Kept as it is, with its angle fixed: the fused circuit takes no parameters.
-            GateRec fixed = g;
-            fixed.theta = gate_theta(g, params);
-            fixed.param = -1;
-            out.push_back(fixed);
+            close_meeting(q);
+            FusedPart nb;
+            nb.qubits = q;
+            nb.gates = {gi};
+            open.push_back(nb);
         }
     }
-    for (const Block& b : open) out.push_back(dense_rec(b));
+    for (const FusedPart& b : open) out.push_back(b);
     return out;
 }
 
-// A circuit holding the fused gates of c; its structure (and so its cached pass plans) is
-// reused while c is unchanged, its matrices are refreshed on every call.
+// M <- (gate g with matrix U, identity where its controls fail) M, on the qubit set qs
+// (index bit j <-> qs[j]): every column of M is updated as a state of |qs| qubits.
+void apply_left(HostMat& M, const GateRec& g, const HostMat& U, const std::vector<int>& qs)
+{
+    const int D = M.dim(), du = U.dim();
+    int tp[8], cp[8];
+    uint32_t tmask = 0, cmask = 0, cval = 0;
+    for (int j = 0; j < g.k; ++j) {
+        tp[j] = position(qs, g.locs[j]);
+        tmask |= 1u << tp[j];
+    }
+    for (int m = 0; m < g.nctrl; ++m) {
+        cp[m] = position(qs, g.ctrls[m]);
+        cmask |= 1u << cp[m];
+        if (g.cvals[m]) cval |= 1u << cp[m];
+    }
+    double inr[32], ini[32];
+    int idx[32];
+    for (int base = 0; base < D; ++base) {
+        if (((uint32_t)base & tmask) || ((uint32_t)base & cmask) != cval) continue;
+        for (int s = 0; s < du; ++s) {
+            int e = base;
+            for (int j = 0; j < g.k; ++j) e |= ((s >> j) & 1) << tp[j];
+            idx[s] = e;
+        }
+        for (int col = 0; col < D; ++col) {
+            for (int s = 0; s < du; ++s) {
+                inr[s] = M.re[(size_t)idx[s] * D + col];
+                ini[s] = M.im[(size_t)idx[s] * D + col];
+            }
+            for (int r = 0; r < du; ++r) {
+                double xr = 0, xi = 0;
+                for (int s = 0; s < du; ++s) {
+                    const double ur = U.re[(size_t)r * du + s], ui = U.im[(size_t)r * du + s];
+                    xr += ur * inr[s] - ui * ini[s];
+                    xi += ur * ini[s] + ui * inr[s];
+                }
+                M.re[(size_t)idx[r] * D + col] = xr;
+                M.im[(size_t)idx[r] * D + col] = xi;
+            }
+        }
+    }
+}
+
+void part_matrix(const yao_circuit* c, const FusedPart& p, const double* params, HostMat& M)
+{
+    M.resize((int)p.qubits.size());
+    for (int d = 0; d < M.dim(); ++d) M.re[(size_t)d * M.dim() + d] = 1.0;
+    static thread_local HostMat U;
+    for (int gi : p.gates) {
+        const GateRec& g = c->gates[gi];
+        gate_matrix(g, gate_theta(g, params), U);
+        apply_left(M, g, U, p.qubits);
+    }
+}
+
+GateRec dense_rec(const FusedPart& p)
+{
+    GateRec r;
+    r.kind = YAO_DENSE;
+    r.param = -1;
+    r.theta = 0;
+    r.k = (int)p.qubits.size();
+    for (int j = 0; j < r.k; ++j) r.locs[j] = p.qubits[j];
+    r.nctrl = 0;
+    r.G.assign(size_t(2) << (2 * r.k), 0.0);
+    for (int d = 0; d < (1 << r.k); ++d) r.G[2 * ((size_t)d * (1 << r.k) + d)] = 1.0;  // identity until bound
+    return r;
+}
+
+struct Fused {
+    std::vector<FusedPart> parts;
+    yao_circuit host;   // gates with their matrices for the last parameters
+    yao_circuit shape;  // structure only: multi-gate blocks as identity placeholders, single
+                        // gates as they are (parameters kept)
+};
+
+std::map<std::tuple<const yao_circuit*, uint64_t, int>, Fused*> g_fused;
+std::mutex g_fused_mu;
+
+Fused* get_fused(const yao_circuit* c, int width)
+{
+    std::lock_guard<std::mutex> lk(g_fused_mu);
+    auto key = std::make_tuple(c, c->version, width);
+    auto it = g_fused.find(key);
+    if (it != g_fused.end()) return it->second;
+    Fused* f = new Fused;
+    f->parts = partition(c, width);
+    for (yao_circuit* x : {&f->host, &f->shape}) {
+        x->n = c->n;
+        x->version = 1;
+    }
+    f->host.nparams = 0;
+    f->host.transient = true;
+    f->shape.nparams = c->nparams;
+    for (const FusedPart& p : f->parts) {
+        const GateRec r = p.single ? c->gates[p.gates[0]] : dense_rec(p);
+        f->shape.gates.push_back(r);
+        f->host.gates.push_back(r);
+    }
+    g_fused[key] = f;
+    return f;
+}
+
+}  // namespace
+
+std::vector<GateRec> fuse_gates(const yao_circuit* c, const double* params, int width)
+{
+    return fused_circuit(c, params, width)->gates;
+}
+
+// A circuit holding the fused gates of c with matrices for these parameters; its structure (and
+// so its cached pass plans) is reused while c is unchanged.
 const yao_circuit* fused_circuit(const yao_circuit* c, const double* params, int width)
 {
-    std::vector<GateRec> gates = fuse_gates(c, params, width);
-    std::lock_guard<std::mutex> lk(g_shadow_mu);
-    auto key = std::make_tuple(c, c->version, width);
-    auto it = g_shadows.find(key);
-    Shadow* sh;
-    if (it == g_shadows.end()) {
-        sh = new Shadow;
-        sh->circ.n = c->n;
-        sh->circ.nparams = 0;
-        sh->circ.version = 1;
-        g_shadows[key] = sh;
-    } else {
-        sh = it->second;
+    Fused* f = get_fused(c, width);
+    for (size_t i = 0; i < f->parts.size(); ++i) {
+        const FusedPart& p = f->parts[i];
+        GateRec& r = f->host.gates[i];
+        if (p.single) {
+            // Kept as it is, with its angle fixed: the fused circuit takes no parameters.
+            r = c->gates[p.gates[0]];
+            r.theta = gate_theta(r, params);
+            r.param = -1;
+            continue;
+        }
+        static thread_local HostMat M;
+        part_matrix(c, p, params, M);
+        for (size_t t = 0; t < M.re.size(); ++t) {
+            r.G[2 * t] = M.re[t];
+            r.G[2 * t + 1] = M.im[t];
+        }
     }
-    bool same = sh->circ.gates.size() == gates.size();
-    for (size_t t = 0; same && t < gates.size(); ++t) {
-        const GateRec &a = sh->circ.gates[t], &b = gates[t];
-        same = a.kind == b.kind && a.k == b.k && a.nctrl == b.nctrl &&
-               std::equal(a.locs, a.locs + a.k, b.locs) && std::equal(a.ctrls, a.ctrls + a.nctrl, b.ctrls) &&
-               std::equal(a.cvals, a.cvals + a.nctrl, b.cvals);
-    }
-    if (!same) sh->circ.version++;
-    sh->circ.gates = std::move(gates);
-    return &sh->circ;
+    return &f->host;
+}
+
+const yao_circuit* fused_shape(const yao_circuit* c, int width, const std::vector<FusedPart>** parts)
+{
+    Fused* f = get_fused(c, width);
+    if (parts) *parts = &f->parts;
+    return &f->shape;
 }
 
 void drop_fused(const yao_circuit* c)
 {
-    std::lock_guard<std::mutex> lk(g_shadow_mu);
-    for (auto it = g_shadows.begin(); it != g_shadows.end();) {
+    std::lock_guard<std::mutex> lk(g_fused_mu);
+    for (auto it = g_fused.begin(); it != g_fused.end();) {
         if (std::get<0>(it->first) == c) {
-            drop_plans(&it->second->circ);
+            drop_plans(&it->second->host);
+            drop_plans(&it->second->shape);
             delete it->second;
-            it = g_shadows.erase(it);
+            it = g_fused.erase(it);
         } else {
             ++it;
         }

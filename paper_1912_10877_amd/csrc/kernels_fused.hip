@@ -852,7 +852,92 @@ template <typename K> int set_lds_limit(K kernel)
     return 0;
 }
 
+// One-qubit matrix of a gate kind at angle th: rotations exp(-i th S / 2), shift(th) =
+// diag(1, e^{i th}), and the fixed Pauli, Hadamard, S and T gates (the same definitions as the
+// host's gate matrices).
+__device__ void gate2(int kind, double th, double (&r)[4], double (&i)[4])
+{
+    const double h = 0.70710678118654752440;
+    for (int e = 0; e < 4; ++e) r[e] = i[e] = 0.0;
+    double sn, cs;
+    switch (kind) {
+    case YAO_X: r[1] = r[2] = 1.0; break;
+    case YAO_Y: i[1] = -1.0; i[2] = 1.0; break;
+    case YAO_Z: r[0] = 1.0; r[3] = -1.0; break;
+    case YAO_H: r[0] = r[1] = r[2] = h; r[3] = -h; break;
+    case YAO_S: r[0] = 1.0; i[3] = 1.0; break;
+    case YAO_SDAG: r[0] = 1.0; i[3] = -1.0; break;
+    case YAO_T: r[0] = 1.0; r[3] = h; i[3] = h; break;
+    case YAO_TDAG: r[0] = 1.0; r[3] = h; i[3] = -h; break;
+    case YAO_SHIFT: sincos(th, &sn, &cs); r[0] = 1.0; r[3] = cs; i[3] = sn; break;
+    case YAO_RX: sincos(0.5 * th, &sn, &cs); r[0] = r[3] = cs; i[1] = i[2] = -sn; break;
+    case YAO_RY: sincos(0.5 * th, &sn, &cs); r[0] = r[3] = cs; r[1] = -sn; r[2] = sn; break;
+    case YAO_RZ: sincos(0.5 * th, &sn, &cs); r[0] = r[3] = cs; i[0] = -sn; i[3] = sn; break;
+    default: r[0] = r[3] = 1.0; break;
+    }
+}
+
+// Parameter binding: one thread per bound record multiplies its factors (in application
+// order) and writes the matrix into the record (see BindRec).
+__global__ void k_bind(POp* __restrict__ ops, const BindRec* __restrict__ binds, int nb,
+                       const BindFac* __restrict__ facs, const double* __restrict__ params)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const BindRec br = binds[b];
+    double ar[4] = {1.0, 0.0, 0.0, 1.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int f = 0; f < br.nf; ++f) {
+        const BindFac x = facs[br.f0 + f];
+        double gr[4], gi[4];
+        gate2(x.kind, x.param >= 0 ? params[x.param] : x.theta, gr, gi);
+        double nr[4], ni[4];
+        for (int row = 0; row < 2; ++row)
+            for (int col = 0; col < 2; ++col) {
+                const int o = 2 * row + col;
+                nr[o] = gr[2 * row] * ar[col] - gi[2 * row] * ai[col] + gr[2 * row + 1] * ar[2 + col] -
+                        gi[2 * row + 1] * ai[2 + col];
+                ni[o] = gr[2 * row] * ai[col] + gi[2 * row] * ar[col] + gr[2 * row + 1] * ai[2 + col] +
+                        gi[2 * row + 1] * ar[2 + col];
+            }
+        for (int e = 0; e < 4; ++e) {
+            ar[e] = nr[e];
+            ai[e] = ni[e];
+        }
+    }
+    if (br.mode == 2) {  // U^dagger
+        double t = ar[1];
+        ar[1] = ar[2];
+        ar[2] = t;
+        t = ai[1];
+        ai[1] = -ai[2];
+        ai[2] = -t;
+        ai[0] = -ai[0];
+        ai[3] = -ai[3];
+    }
+    POp& op = ops[br.op];
+    if (br.mode == 0) {
+        float* u = (float*)op.u;
+        for (int e = 0; e < 4; ++e) {
+            u[e] = (float)ar[e];
+            u[4 + e] = (float)ai[e];
+        }
+    } else {
+        for (int e = 0; e < 4; ++e) {
+            op.u[e] = ar[e];
+            op.u[4 + e] = ai[e];
+        }
+    }
+}
+
 }  // namespace
+
+int launch_bind(POp* ops, const BindRec* binds, int nbinds, const BindFac* facs, const double* params)
+{
+    if (nbinds <= 0) return 0;
+    k_bind<<<(nbinds + 255) / 256, 256, 0, stream()>>>(ops, binds, nbinds, facs, params);
+    YAO_HIP(hipGetLastError());
+    return 0;
+}
 
 // Raise the dynamic LDS limit of every pass kernel ahead of a graph capture.
 int prepare_pass_kernels()

@@ -126,6 +126,28 @@ void* host_staging(size_t bytes)
     return g_stage;
 }
 
+static void* g_pin[WS_COUNT] = {};
+static size_t g_pin_size[WS_COUNT] = {};
+
+void* pinned(int slot, size_t bytes)
+{
+    if (g_pin_size[slot] >= bytes) return g_pin[slot];
+    if (g_pin[slot]) {
+        (void)hipStreamSynchronize(g_stream);
+        (void)hipHostFree(g_pin[slot]);
+        g_pin[slot] = nullptr;
+        g_pin_size[slot] = 0;
+    }
+    const size_t want = (bytes < 65536 ? 65536 : bytes) + bytes / 4;
+    if (hipHostMalloc(&g_pin[slot], want, hipHostMallocDefault) != hipSuccess) {
+        g_pin[slot] = nullptr;
+        set_error(YAO_ENOMEM, "pinned slot %d: %zu bytes", slot, want);
+        return nullptr;
+    }
+    g_pin_size[slot] = want;
+    return g_pin[slot];
+}
+
 static constexpr size_t kRingSlot = 64 * 1024;
 static constexpr int kRingSlots = 256;
 static char* g_ring = nullptr;
@@ -211,7 +233,7 @@ bool gate_matrix(const GateRec& g, double theta, HostMat& U)
     case YAO_SHIFT: set_entry(U, 0, 0, 1, 0); set_entry(U, 1, 1, std::cos(theta), std::sin(theta)); return true;
     case YAO_RX: case YAO_RY: case YAO_RZ: case YAO_ROT: {
         // cos(theta/2) 1 - i sin(theta/2) S
-        HostMat S;
+        static thread_local HostMat S;  // reused: programs are rebuilt for every call
         generator(g, S);
         const double c = std::cos(theta / 2), s = std::sin(theta / 2);
         for (int r = 0; r < U.dim(); ++r)
@@ -243,7 +265,7 @@ bool gate_grad_matrix(const GateRec& g, double theta, HostMat& M)
     }
     if (g.kind == YAO_RX || g.kind == YAO_RY || g.kind == YAO_RZ || g.kind == YAO_ROT) {
         // d/dtheta exp(-i theta S/2) = (-i/2) S exp(-i theta S/2), so M = -(i/2) S
-        HostMat S;
+        static thread_local HostMat S;  // reused: programs are rebuilt for every call
         generator(g, S);
         M.resize(S.k);
         for (size_t t = 0; t < S.re.size(); ++t) {
@@ -253,6 +275,17 @@ bool gate_grad_matrix(const GateRec& g, double theta, HostMat& M)
         return true;
     }
     return false;
+}
+
+void dagger_into(const HostMat& U, HostMat& D)
+{
+    D.resize(U.k);
+    const int d = U.dim();
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            D.re[c * d + r] = U.re[r * d + c];
+            D.im[c * d + r] = -U.im[r * d + c];
+        }
 }
 
 HostMat dagger(const HostMat& U)

@@ -32,16 +32,21 @@ enum WsSlot {
     WS_LAM,         // adjoint state
     WS_PARTIAL,     // per-block partial sums
     WS_PARTIAL2,    // second-level sums
-    WS_MAT,         // gate matrices and pass programs
+    WS_MAT,         // gate matrices and pass programs (forward sweeps)
+    WS_MAT2,        // pass programs of reverse sweeps
     WS_CKPT,        // checkpoints
     WS_SEG,         // segment states of the checkpointed backward
     WS_TUNE,        // copy of a state while schedules are timed on it
+    WS_PARAMS,      // circuit parameters for the device-side binding of programs
     WS_MISC,
     WS_COUNT
 };
 void* workspace(int slot, size_t bytes);
 // Pinned host staging buffer for results (grows on demand).
 void* host_staging(size_t bytes);
+// Pinned host buffer per workspace slot, for uploads that must not block the host (grows on
+// demand; growing first waits for the stream, so no queued copy still reads the old one).
+void* pinned(int slot, size_t bytes);
 // Copy a small host block (<= 64 KiB) into the next slot of a device ring and return the slot.
 // The copy is queued on the current stream, so kernels queued after it see the data; slots
 // are reused round-robin after 256 uploads.
@@ -69,6 +74,7 @@ bool gate_matrix(const GateRec& g, double theta, HostMat& U);
 // controlled subspace.
 bool gate_grad_matrix(const GateRec& g, double theta, HostMat& M);
 HostMat dagger(const HostMat& U);
+void dagger_into(const HostMat& U, HostMat& D);
 HostMat matmul(const HostMat& A, const HostMat& B);
 
 // Matrix classes that pick a kernel specialisation (App. "sparse matrices": diagonal,

@@ -2,6 +2,7 @@
 #include "tuner.h"
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -67,18 +68,21 @@ const yao_circuit* forward_circuit(const yao_circuit* c, const double* params, i
 int time_forward(const yao_circuit* c, const double* params, void* data, int dtype, int n, int B, int width, int tq,
                  double* ms)
 {
-    const double* fp = nullptr;
-    const yao_circuit* fc = forward_circuit(c, params, width, &fp);
-    int t, cb, L;
-    tile_geometry_tq(n, B, dtype, false, tq, &t, &cb, &L);
-    const Plan& P = get_plan(fc, 0, (int)fc->gates.size(), B, t, cb, L, false);
-    Program prog;
-    YAO_TRY(build_program(P, fc, fp, false, dtype, prog));
-    TrialProgram tp;
-    YAO_TRY(tp.load(prog));
-    // One timed run for large states, the median of three otherwise.
+    // Wall time of the whole sweep (host work for the program included), median of three runs
+    // for small states and one for large ones, after one untimed run.
     const int reps = (uint64_t(1) << n) * (uint64_t)B >= (uint64_t(1) << 24) ? 1 : 3;
-    return time_ms(reps, [&] { return launch_forward_passes(P, prog, tp.dp, data, dtype, n, B, fc, fp); }, ms);
+    YAO_TRY(forward_sweep(data, dtype, n, B, c, params, width, tq, nullptr));
+    YAO_HIP(hipStreamSynchronize(stream()));
+    std::vector<double> v;
+    for (int r = 0; r < reps; ++r) {
+        const auto t0 = std::chrono::steady_clock::now();
+        YAO_TRY(forward_sweep(data, dtype, n, B, c, params, width, tq, nullptr));
+        YAO_HIP(hipStreamSynchronize(stream()));
+        v.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    }
+    std::sort(v.begin(), v.end());
+    *ms = v[v.size() / 2];
+    return 0;
 }
 
 namespace {
