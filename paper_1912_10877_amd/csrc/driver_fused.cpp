@@ -313,7 +313,7 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                         for (int e = 0; e < 8; ++e) op.u[e] = prog.mats[op.mat + e];
                     }
                 }
-                for (int j = 0; j < g.k; ++j) op.tpos[j] = tile_bit(g.locs[j]);
+                for (int j = 0; j < g.k && j < 3; ++j) op.tpos[j] = tile_bit(g.locs[j]);
                 op.rpos = 0;
                 if (!hg.lds) {
                     for (int j = 0; j < P.reg_bits; ++j)
@@ -332,6 +332,24 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                         op.omask |= uint64_t(1) << q;
                         if (g.cvals[m]) op.oval |= uint64_t(1) << q;
                     }
+                }
+                {
+                    const bool plain = op.cmask == 0 && op.omask == 0;
+                    const bool cswap = op.type == OT_SWAP && op.cmask != 0 && op.omask == 0;
+                    int cls;
+                    if (!bwd) {
+                        cls = (plain && op.type == OT_RX)     ? 0
+                              : (plain && op.type == OT_DIAG)  ? 1
+                              : (plain && op.type == OT_DENSE) ? 2
+                              : cswap                          ? 3
+                                                               : kFwdGenericClass;
+                    } else {
+                        cls = (plain && op.slot >= 0 && op.type == OT_RX && op.gen == GEN_X)     ? 0
+                              : (plain && op.slot >= 0 && op.type == OT_DIAG && op.gen == GEN_Z) ? 1
+                              : (cswap && op.slot < 0)                                           ? 2
+                                                                                                 : kBwdGenericClass;
+                    }
+                    op.var = g.k == 1 ? cls * P.reg_bits + op.rpos : 0;
                 }
                 prog.ops.push_back(op);
                 prog.pass_flops.back() += op_flops(op, bwd) / double(uint64_t(1) << g.nctrl);

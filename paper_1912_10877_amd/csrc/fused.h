@@ -31,6 +31,14 @@ enum OpType : int {
 // Gradient generators: M = (dU/dtheta) U^dagger restricted to the op's subspace.
 enum GenType : int { GEN_NONE = 0, GEN_X = 1, GEN_Y = 2, GEN_Z = 3, GEN_P1 = 4, GEN_DENSE = 5 };
 
+// Code paths of one-qubit ops, chosen on the host: var = class * R + register position (R =
+// register bits). Forward classes: 0 Rx-like, 1 diagonal, 2 dense (all without controls),
+// 3 swap with controls inside the tile, 4 anything else. Reverse classes: 0 Rx-like with an
+// X generator, 1 diagonal with a Z generator (both without controls, with a gradient),
+// 2 swap with controls inside the tile and no gradient, 3 anything else.
+constexpr int kFwdGenericClass = 4;
+constexpr int kBwdGenericClass = 3;
+
 // Device op record (one gate inside a pass), 128 bytes: everything a one-qubit op needs comes
 // in one scalar fetch, so the next op's record can be fetched while the current one computes.
 struct POp {
@@ -44,7 +52,8 @@ struct POp {
     uint64_t omask, oval;  // controls on qubits outside the tile
     double u[8];    // one-qubit matrix (forward U, backward U^dagger): re[4] then im[4]; in
                     // forward programs of complex64 states the same entries as float[8]
-    int tpos[4];    // tile-bit positions of the targets, in locs order
+    int tpos[3];    // tile-bit positions of the targets of a k = 2, 3 op, in locs order
+    int var;        // code path of a one-qubit op (see op_variant)
 };
 static_assert(sizeof(POp) == 128, "op record layout");
 

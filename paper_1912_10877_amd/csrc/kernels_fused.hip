@@ -64,7 +64,7 @@ __device__ __forceinline__ uint64_t sc64(uint64_t v)
 
 // Control fields of an op record, made wave-uniform (scalar registers).
 struct OpCtl {
-    int type, gen, rpos, slot, mat;
+    int type, gen, rpos, slot, mat, var;
     uint32_t cmask, cval;
     uint64_t omask, oval;
 };
@@ -76,6 +76,7 @@ __device__ __forceinline__ OpCtl op_ctl(const POp& r)
     o.rpos = sc(r.rpos);
     o.slot = sc(r.slot);
     o.mat = sc(r.mat);
+    o.var = sc(r.var);
     o.cmask = (uint32_t)sc((int)r.cmask);
     o.cval = (uint32_t)sc((int)r.cval);
     o.omask = sc64(r.omask);
@@ -700,7 +701,20 @@ __global__ __launch_bounds__(512, sizeof(RP) == 4 ? 3 : 1) void k_pass_fwd(PassA
         if (op.cmask) op_apply<J, true, RP>(x, op.type, mr, mi, ethr, er, op.cmask, op.cval); \
         else op_apply<J, false, RP>(x, op.type, mr, mi, ethr, er, 0u, 0u);                    \
         break;
-            switch (op.rpos) { YAO_FWD_CASE(0) YAO_FWD_CASE(1) YAO_FWD_CASE(2) default: YAO_FWD_CASE(3) }
+            // Ops of the common classes (see op_variant) have code of their own, picked by one
+            // switch on the variant the host chose.
+#define YAO_FWD_FAST(J)                                                                             \
+    case 0 * kRegBitsFwd + J: pairs_apply<J, false, OT_RX, RP>(x, mr, mi, ethr, er, 0u, 0u); break;    \
+    case 1 * kRegBitsFwd + J: pairs_apply<J, false, OT_DIAG, RP>(x, mr, mi, ethr, er, 0u, 0u); break;  \
+    case 2 * kRegBitsFwd + J: pairs_apply<J, false, OT_DENSE, RP>(x, mr, mi, ethr, er, 0u, 0u); break; \
+    case 3 * kRegBitsFwd + J: pairs_apply<J, true, OT_SWAP, RP>(x, mr, mi, ethr, er, op.cmask, op.cval); break;
+            switch (op.var) {
+                YAO_FWD_FAST(0) YAO_FWD_FAST(1) YAO_FWD_FAST(2) YAO_FWD_FAST(3)
+            default:
+                switch (op.rpos) { YAO_FWD_CASE(0) YAO_FWD_CASE(1) YAO_FWD_CASE(2) default: YAO_FWD_CASE(3) }
+                break;
+            }
+#undef YAO_FWD_FAST
 #undef YAO_FWD_CASE
             cur = load_op<RP>(nxt);
         }
@@ -809,7 +823,30 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
             op_apply<J, false, double>(y, op.type, m, m + 4, ethr, er, 0u, 0u);                               \
         }                                                                                                     \
         break;
-            switch (op.rpos) { YAO_BWD_CASE(0) YAO_BWD_CASE(1) default: YAO_BWD_CASE(2) }
+            // Ops of the common classes (see op_variant) have code of their own, picked by one
+            // switch on the variant the host chose.
+#define YAO_BWD_FAST(J)                                                                             \
+    case 0 * kRegBitsBwd + J:                                                                       \
+        g = pairs_grad<J, false, GEN_X>(x, y, m, m + 4, ethr, er, 0u, 0u);                            \
+        pairs_apply<J, false, OT_RX, double>(x, m, m + 4, ethr, er, 0u, 0u);                          \
+        pairs_apply<J, false, OT_RX, double>(y, m, m + 4, ethr, er, 0u, 0u);                          \
+        break;                                                                                      \
+    case 1 * kRegBitsBwd + J:                                                                       \
+        g = pairs_grad<J, false, GEN_Z>(x, y, m, m + 4, ethr, er, 0u, 0u);                            \
+        pairs_apply<J, false, OT_DIAG, double>(x, m, m + 4, ethr, er, 0u, 0u);                        \
+        pairs_apply<J, false, OT_DIAG, double>(y, m, m + 4, ethr, er, 0u, 0u);                        \
+        break;                                                                                      \
+    case 2 * kRegBitsBwd + J:                                                                       \
+        pairs_apply<J, true, OT_SWAP, double>(x, m, m + 4, ethr, er, op.cmask, op.cval);              \
+        pairs_apply<J, true, OT_SWAP, double>(y, m, m + 4, ethr, er, op.cmask, op.cval);              \
+        break;
+            switch (op.var) {
+                YAO_BWD_FAST(0) YAO_BWD_FAST(1) YAO_BWD_FAST(2)
+            default:
+                switch (op.rpos) { YAO_BWD_CASE(0) YAO_BWD_CASE(1) default: YAO_BWD_CASE(2) }
+                break;
+            }
+#undef YAO_BWD_FAST
 #undef YAO_BWD_CASE
             if (op.slot >= 0) {
                 red[nslot * nthr + th] = g;
