@@ -13,9 +13,12 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libyao.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# Packed FP32 instructions are disabled on purpose for every device compile.
+# Packed FP32 instructions are disabled on purpose for every device compile. Branches on
+# wave-uniform values (the pass kernels' dispatch on op variants) are left unstructured, so each
+# variant's in-place register updates reach the loop latch without phi copies.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-structurizecfg-skip-uniform-regions=true",
          "-munsafe-fp-atomics", "-ffp-contract=fast"]
 
 

@@ -214,7 +214,9 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     if (op.slot >= 0) {
                         gate_grad_matrix(g, th, M);
                         op.gen = gen_type_of(g);
-                        gd.nslot++;
+                        if (gd.nslot >= kMaxGroupSlots)
+                            return set_error(YAO_EINVAL, "register group carries more than %d gradients", kMaxGroupSlots);
+                        gd.slots[gd.nslot++] = op.slot;
                     } else {
                         M.resize(g.k);
                         op.gen = GEN_NONE;

@@ -63,6 +63,7 @@ struct PGroupDesc {
                          // 16 x 16 matrix on the register bits (index bit j <-> rpos[j])
     int op0, nops;
     int nslot;           // ops with a gradient in this group
+    int slots[kMaxGroupSlots];  // their gradient slots, in op order
 };
 
 struct PassDesc {

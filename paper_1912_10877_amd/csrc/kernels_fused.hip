@@ -13,6 +13,9 @@
 //
 // The pass's op records are copied to LDS together with the tile; LDS reads complete in
 // order, so the record of the next op is fetched while the current op computes.
+#include <mutex>
+#include <vector>
+
 #include "fused.h"
 
 namespace yao {
@@ -68,22 +71,6 @@ struct OpCtl {
     uint32_t cmask, cval;
     uint64_t omask, oval;
 };
-__device__ __forceinline__ OpCtl op_ctl(const POp& r)
-{
-    OpCtl o;
-    o.type = sc(r.type);
-    o.gen = sc(r.gen);
-    o.rpos = sc(r.rpos);
-    o.slot = sc(r.slot);
-    o.mat = sc(r.mat);
-    o.var = sc(r.var);
-    o.cmask = (uint32_t)sc((int)r.cmask);
-    o.cval = (uint32_t)sc((int)r.cval);
-    o.omask = sc64(r.omask);
-    o.oval = sc64(r.oval);
-    return o;
-}
-
 // Control fields and the one-qubit matrix of an op, wave-uniform. The matrix is read in the
 // precision MR: the host stores float entries (u viewed as float[8]) in programs for complex64
 // forward sweeps, double entries otherwise.
@@ -91,31 +78,45 @@ template <typename MR> struct OpS {
     OpCtl c;
     MR m[8];  // re[4], im[4]
 };
-__device__ __forceinline__ double sc_f64(double v)
+// Op records and group descriptors are read in place through the scalar cache: a pointer in
+// the constant address space tells the compiler that the kernel never writes them, so
+// wave-uniform reads become scalar loads straight into SGPRs (the records are written by the
+// host or by the bind kernel before the pass is launched).
+#define YAO_CONST __attribute__((address_space(4)))
+template <typename T> __device__ __forceinline__ const YAO_CONST T* cptr(const T* p)
 {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    return __builtin_bit_cast(double, sc64(b));
+    return (const YAO_CONST T*)p;
 }
-__device__ __forceinline__ float sc_f32(float v)
+__device__ __forceinline__ OpCtl op_ctl_c(const YAO_CONST POp* r)
 {
-    return __builtin_bit_cast(float, sc(__builtin_bit_cast(int, v)));
-}
-template <typename MR> __device__ __forceinline__ OpS<MR> load_op(const POp& r)
-{
-    OpS<MR> o;
-    o.c = op_ctl(r);
-    if constexpr (sizeof(MR) == 4) {
-        const float* f = (const float*)r.u;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) o.m[q] = sc_f32(f[q]);
-    } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) o.m[q] = sc_f64(r.u[q]);
-    }
-    // A tile that fails the op's controls on qubits outside the tile skips every pair: the
-    // pair predicate then asks for bit 31 of a tile index, which is never set.
+    OpCtl o;
+    o.type = r->type;
+    o.gen = r->gen;
+    o.rpos = r->rpos;
+    o.slot = r->slot;
+    o.mat = r->mat;
+    o.var = r->var;
+    o.cmask = r->cmask;
+    o.cval = r->cval;
+    o.omask = r->omask;
+    o.oval = r->oval;
     return o;
 }
+template <typename MR> __device__ __forceinline__ OpS<MR> load_op_c(const YAO_CONST POp* r)
+{
+    OpS<MR> o;
+    o.c = op_ctl_c(r);
+    if constexpr (sizeof(MR) == 4) {
+        const YAO_CONST float* f = (const YAO_CONST float*)r->u;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o.m[q] = f[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o.m[q] = r->u[q];
+    }
+    return o;
+}
+
 __device__ __forceinline__ void fold_outer_controls(OpCtl& c, uint64_t base)
 {
     if ((base & c.omask) != c.oval) {
@@ -124,46 +125,232 @@ __device__ __forceinline__ void fold_outer_controls(OpCtl& c, uint64_t base)
     }
 }
 
-// ------------------------------------------------------------------------------ pair updates
-// Apply a one-qubit matrix of structure TYPE to the pair (a, b); m = {re[4], im[4]}.
-template <int TYPE, typename RR, typename V>
-__device__ __forceinline__ void apply_pair(const RR* mr, const RR* mi, V& a, V& b)
+// ------------------------------------------------------------------------------ in-place updates
+// The common one-qubit updates are written as inline assembly whose results are tied to the
+// registers of their inputs. A register group's amplitudes stay in fixed registers from op to
+// op; computed as plain expressions, each op variant would leave its results in fresh
+// registers and every op would end with a copy of all of them. Scalar operands are the op's
+// matrix entries (SGPRs); each VALU instruction reads at most one of them.
+#define YAO_IP_FNS(T, V, SFX, MOV)                                                                       \
+    /* (a, b) <- (c a + i s b, i s a + c b) */                                                          \
+    __device__ __forceinline__ void rx_ip(V& a, V& b, T cc, T ss)                                      \
+    {                                                                                                   \
+        T t0, t1;                                                                                       \
+        asm("v_mul_" SFX " %[t0], %[s], %[by]\n\t"                                                    \
+            "v_mul_" SFX " %[t1], %[s], %[ax]\n\t"                                                    \
+            "v_fma_" SFX " %[ax], %[c], %[ax], -%[t0]\n\t"                                            \
+            "v_fma_" SFX " %[by], %[c], %[by], %[t1]\n\t"                                             \
+            "v_mul_" SFX " %[t0], %[s], %[bx]\n\t"                                                    \
+            "v_mul_" SFX " %[t1], %[s], %[ay]\n\t"                                                    \
+            "v_fma_" SFX " %[ay], %[c], %[ay], %[t0]\n\t"                                             \
+            "v_fma_" SFX " %[bx], %[c], %[bx], -%[t1]"                                                  \
+            : [ax] "+v"(a.x), [ay] "+v"(a.y), [bx] "+v"(b.x), [by] "+v"(b.y), [t0] "=&v"(t0),            \
+              [t1] "=&v"(t1)                                                                            \
+            : [c] "s"(cc), [s] "s"(ss));                                                                \
+    }                                                                                                   \
+    /* a <- (r + i m) a */                                                                              \
+    __device__ __forceinline__ void diag_ip(V& a, T r, T m)                                            \
+    {                                                                                                   \
+        T t0, t1;                                                                                       \
+        asm("v_mul_" SFX " %[t0], %[m], %[ay]\n\t"                                                    \
+            "v_mul_" SFX " %[t1], %[m], %[ax]\n\t"                                                    \
+            "v_fma_" SFX " %[ax], %[r], %[ax], -%[t0]\n\t"                                            \
+            "v_fma_" SFX " %[ay], %[r], %[ay], %[t1]"                                                   \
+            : [ax] "+v"(a.x), [ay] "+v"(a.y), [t0] "=&v"(t0), [t1] "=&v"(t1)                             \
+            : [r] "s"(r), [m] "s"(m));                                                                  \
+    }                                                                                                   \
+    /* (a, b) <- U (a, b) for U = mr + i mi, row-major; four interleaved FMA chains, the last */  \
+    /* of which ends in b.y itself */                                                                 \
+    __device__ __forceinline__ void dense_ip(V& a, V& b, const T* mr, const T* mi)                     \
+    {                                                                                                   \
+        T t0, t1, t2, t3;                                                                               \
+        asm("v_mul_" SFX " %[t0], %[r0], %[ax]\n\t"                                                   \
+            "v_mul_" SFX " %[t1], %[r0], %[ay]\n\t"                                                   \
+            "v_mul_" SFX " %[t2], %[r2], %[ax]\n\t"                                                   \
+            "v_mul_" SFX " %[t3], %[r2], %[ay]\n\t"                                                   \
+            "v_fma_" SFX " %[t0], -%[i0], %[ay], %[t0]\n\t"                                           \
+            "v_fma_" SFX " %[t1], %[i0], %[ax], %[t1]\n\t"                                            \
+            "v_fma_" SFX " %[t2], -%[i2], %[ay], %[t2]\n\t"                                           \
+            "v_fma_" SFX " %[t3], %[i2], %[ax], %[t3]\n\t"                                            \
+            "v_fma_" SFX " %[t0], %[r1], %[bx], %[t0]\n\t"                                            \
+            "v_fma_" SFX " %[t1], %[i1], %[bx], %[t1]\n\t"                                            \
+            "v_fma_" SFX " %[t2], %[r3], %[bx], %[t2]\n\t"                                            \
+            "v_fma_" SFX " %[t3], %[i3], %[bx], %[t3]\n\t"                                            \
+            "v_fma_" SFX " %[t0], -%[i1], %[by], %[t0]\n\t"                                           \
+            "v_fma_" SFX " %[t1], %[r1], %[by], %[t1]\n\t"                                            \
+            "v_fma_" SFX " %[t2], -%[i3], %[by], %[t2]\n\t"                                           \
+            "v_fma_" SFX " %[by], %[r3], %[by], %[t3]\n\t"                                            \
+            MOV " %[ax], %[t0]\n\t"                                                                   \
+            MOV " %[ay], %[t1]\n\t"                                                                   \
+            MOV " %[bx], %[t2]"                                                                         \
+            : [ax] "+v"(a.x), [ay] "+v"(a.y), [bx] "+v"(b.x), [by] "+v"(b.y), [t0] "=&v"(t0),            \
+              [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3)                                            \
+            : [r0] "s"(mr[0]), [r1] "s"(mr[1]), [r2] "s"(mr[2]), [r3] "s"(mr[3]), [i0] "s"(mi[0]),       \
+              [i1] "s"(mi[1]), [i2] "s"(mi[2]), [i3] "s"(mi[3]));                                        \
+    }
+#define YAO_IP_CTL_FNS(T, V, SFX, MOV)                                                                   \
+    /* (a, b) <- U (a, b) in the lanes of the mask m (a ballot), unchanged elsewhere */                \
+    __device__ __forceinline__ void dense_ctl_ip(V& a, V& b, const T* mr, const T* mi, uint64_t m)     \
+    {                                                                                                   \
+        T t0, t1, t2, t3;                                                                               \
+        uint64_t sv;                                                                                    \
+        asm volatile("v_mul_" SFX " %[t0], %[r0], %[ax]\n\t"                                          \
+                     "v_mul_" SFX " %[t1], %[r0], %[ay]\n\t"                                          \
+                     "v_mul_" SFX " %[t2], %[r2], %[ax]\n\t"                                          \
+                     "v_mul_" SFX " %[t3], %[r2], %[ay]\n\t"                                          \
+                     "v_fma_" SFX " %[t0], -%[i0], %[ay], %[t0]\n\t"                                  \
+                     "v_fma_" SFX " %[t1], %[i0], %[ax], %[t1]\n\t"                                   \
+                     "v_fma_" SFX " %[t2], -%[i2], %[ay], %[t2]\n\t"                                  \
+                     "v_fma_" SFX " %[t3], %[i2], %[ax], %[t3]\n\t"                                   \
+                     "v_fma_" SFX " %[t0], %[r1], %[bx], %[t0]\n\t"                                   \
+                     "v_fma_" SFX " %[t1], %[i1], %[bx], %[t1]\n\t"                                   \
+                     "v_fma_" SFX " %[t2], %[r3], %[bx], %[t2]\n\t"                                   \
+                     "v_fma_" SFX " %[t3], %[i3], %[bx], %[t3]\n\t"                                   \
+                     "v_fma_" SFX " %[t0], -%[i1], %[by], %[t0]\n\t"                                  \
+                     "v_fma_" SFX " %[t1], %[r1], %[by], %[t1]\n\t"                                   \
+                     "v_fma_" SFX " %[t2], -%[i3], %[by], %[t2]\n\t"                                  \
+                     "v_fma_" SFX " %[t3], %[r3], %[by], %[t3]\n\t"                                   \
+                     "s_mov_b64 %[sv], exec\n\t"                                                      \
+                     "s_mov_b64 exec, %[m]\n\t"                                                       \
+                     MOV " %[ax], %[t0]\n\t"                                                          \
+                     MOV " %[ay], %[t1]\n\t"                                                          \
+                     MOV " %[bx], %[t2]\n\t"                                                          \
+                     MOV " %[by], %[t3]\n\t"                                                          \
+                     "s_mov_b64 exec, %[sv]"                                                            \
+                     : [ax] "+v"(a.x), [ay] "+v"(a.y), [bx] "+v"(b.x), [by] "+v"(b.y), [t0] "=&v"(t0),   \
+                       [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3), [sv] "=&s"(sv)                   \
+                     : [r0] "s"(mr[0]), [r1] "s"(mr[1]), [r2] "s"(mr[2]), [r3] "s"(mr[3]),              \
+                       [i0] "s"(mi[0]), [i1] "s"(mi[1]), [i2] "s"(mi[2]), [i3] "s"(mi[3]), [m] "s"(m));  \
+    }
+YAO_IP_CTL_FNS(float, float2, "f32", "v_mov_b32")
+YAO_IP_CTL_FNS(double, double2, "f64", "v_mov_b64")
+#undef YAO_IP_CTL_FNS
+YAO_IP_FNS(float, float2, "f32", "v_mov_b32")
+YAO_IP_FNS(double, double2, "f64", "v_mov_b64")
+#undef YAO_IP_FNS
+
+// Swap a and b in the lanes of the mask m (a ballot, so a subset of the active lanes): exec is
+// narrowed to m for the moves and restored.
+__device__ __forceinline__ void cswap_ip(float2& a, float2& b, uint64_t m)
 {
-    if constexpr (TYPE == OT_SWAP) {
-        V t = a;
-        a = b;
-        b = t;
-    } else if constexpr (TYPE == OT_DIAG) {
-        a = mkv<V, RR>(fma(mr[0], a.x, -mi[0] * a.y), fma(mr[0], a.y, mi[0] * a.x));
-        b = mkv<V, RR>(fma(mr[3], b.x, -mi[3] * b.y), fma(mr[3], b.y, mi[3] * b.x));
-    } else if constexpr (TYPE == OT_REAL) {
-        V na = mkv<V, RR>(fma(mr[0], a.x, mr[1] * b.x), fma(mr[0], a.y, mr[1] * b.y));
-        V nb = mkv<V, RR>(fma(mr[2], a.x, mr[3] * b.x), fma(mr[2], a.y, mr[3] * b.y));
-        a = na;
-        b = nb;
-    } else if constexpr (TYPE == OT_RX) {
-        // [[c, i s], [i s, c]] with c = mr[0], s = mi[1] = mi[2]
-        const RR cc = mr[0], ss = mi[1];
-        V na = mkv<V, RR>(fma(cc, a.x, -ss * b.y), fma(cc, a.y, ss * b.x));
-        V nb = mkv<V, RR>(fma(cc, b.x, -ss * a.y), fma(cc, b.y, ss * a.x));
-        a = na;
-        b = nb;
-    } else {
-        RR x0 = mr[0] * a.x, y0 = mr[0] * a.y, x1 = mr[2] * a.x, y1 = mr[2] * a.y;
-        x0 = fma(-mi[0], a.y, x0);
-        y0 = fma(mi[0], a.x, y0);
-        x0 = fma(mr[1], b.x, x0);
-        y0 = fma(mr[1], b.y, y0);
-        x0 = fma(-mi[1], b.y, x0);
-        y0 = fma(mi[1], b.x, y0);
-        x1 = fma(-mi[2], a.y, x1);
-        y1 = fma(mi[2], a.x, y1);
-        x1 = fma(mr[3], b.x, x1);
-        y1 = fma(mr[3], b.y, y1);
-        x1 = fma(-mi[3], b.y, x1);
-        y1 = fma(mi[3], b.x, y1);
-        a = mkv<V, RR>(x0, y0);
-        b = mkv<V, RR>(x1, y1);
+    uint64_t sv;
+    asm volatile("s_mov_b64 %[sv], exec\n\t"
+                 "s_mov_b64 exec, %[m]\n\t"
+                 "v_swap_b32 %[ax], %[bx]\n\t"
+                 "v_swap_b32 %[ay], %[by]\n\t"
+                 "s_mov_b64 exec, %[sv]"
+                 : [ax] "+v"(a.x), [ay] "+v"(a.y), [bx] "+v"(b.x), [by] "+v"(b.y), [sv] "=&s"(sv)
+                 : [m] "s"(m));
+}
+__device__ __forceinline__ void cswap_ip(double2& a, double2& b, uint64_t m)
+{
+    uint64_t sv;
+    double t;
+    asm volatile("s_mov_b64 %[sv], exec\n\t"
+                 "s_mov_b64 exec, %[m]\n\t"
+                 "v_mov_b64 %[t], %[ax]\n\t"
+                 "v_mov_b64 %[ax], %[bx]\n\t"
+                 "v_mov_b64 %[bx], %[t]\n\t"
+                 "v_mov_b64 %[t], %[ay]\n\t"
+                 "v_mov_b64 %[ay], %[by]\n\t"
+                 "v_mov_b64 %[by], %[t]\n\t"
+                 "s_mov_b64 exec, %[sv]"
+                 : [ax] "+v"(a.x), [ay] "+v"(a.y), [bx] "+v"(b.x), [by] "+v"(b.y), [t] "=&v"(t), [sv] "=&s"(sv)
+                 : [m] "s"(m));
+}
+__device__ __forceinline__ void cswap_ip(double2& a, double2& b, double2& c, double2& d, uint64_t m)
+{
+    uint64_t sv;
+    double t;
+    asm volatile("s_mov_b64 %[sv], exec\n\t"
+                 "s_mov_b64 exec, %[m]\n\t"
+                 "v_mov_b64 %[t], %[ax]\n\t"
+                 "v_mov_b64 %[ax], %[bx]\n\t"
+                 "v_mov_b64 %[bx], %[t]\n\t"
+                 "v_mov_b64 %[t], %[ay]\n\t"
+                 "v_mov_b64 %[ay], %[by]\n\t"
+                 "v_mov_b64 %[by], %[t]\n\t"
+                 "v_mov_b64 %[t], %[cx]\n\t"
+                 "v_mov_b64 %[cx], %[dx]\n\t"
+                 "v_mov_b64 %[dx], %[t]\n\t"
+                 "v_mov_b64 %[t], %[cy]\n\t"
+                 "v_mov_b64 %[cy], %[dy]\n\t"
+                 "v_mov_b64 %[dy], %[t]\n\t"
+                 "s_mov_b64 exec, %[sv]"
+                 : [ax] "+v"(a.x), [ay] "+v"(a.y), [bx] "+v"(b.x), [by] "+v"(b.y), [cx] "+v"(c.x),
+                   [cy] "+v"(c.y), [dx] "+v"(d.x), [dy] "+v"(d.y), [t] "=&v"(t), [sv] "=&s"(sv)
+                 : [m] "s"(m));
+}
+
+// An uncontrolled one-qubit op of structure TYPE (OT_RX, OT_DIAG or OT_DENSE) on register bit J.
+template <int J, int TYPE, typename RR, typename V, int N>
+__device__ __forceinline__ void pairs_ip(V (&x)[N], const RR* mr, const RR* mi)
+{
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        if (a & (1 << J)) continue;
+        V& p = x[a];
+        V& q = x[a + (1 << J)];
+        if constexpr (TYPE == OT_RX) {
+            rx_ip(p, q, mr[0], mi[1]);
+        } else if constexpr (TYPE == OT_DIAG) {
+            diag_ip(p, mr[0], mi[0]);
+            diag_ip(q, mr[3], mi[3]);
+        } else {
+            dense_ip(p, q, mr, mi);
+        }
+    }
+}
+
+// Any one-qubit op on register bit J (as a dense 2 x 2 matrix) where the pair's tile index
+// matches the tile-bit controls (every pair when cmask is 0); the backward form updates psi
+// and lambda with the same matrix.
+template <int J, typename RR, typename V, int N>
+__device__ __forceinline__ void pairs_dense_ctl_ip(V (&x)[N], const RR* mr, const RR* mi, uint32_t ethr,
+                                                   const uint32_t (&er)[N], uint32_t cmask, uint32_t cval)
+{
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        if (a & (1 << J)) continue;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(((ethr | er[a]) & cmask) == cval);
+        dense_ctl_ip(x[a], x[a + (1 << J)], mr, mi, m);
+    }
+}
+template <int J, int N>
+__device__ __forceinline__ void pairs_dense_ctl_ip(double2 (&x)[N], double2 (&y)[N], const double* mr,
+                                                   const double* mi, uint32_t ethr, const uint32_t (&er)[N],
+                                                   uint32_t cmask, uint32_t cval)
+{
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        if (a & (1 << J)) continue;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(((ethr | er[a]) & cmask) == cval);
+        dense_ctl_ip(x[a], x[a + (1 << J)], mr, mi, m);
+        dense_ctl_ip(y[a], y[a + (1 << J)], mr, mi, m);
+    }
+}
+
+// A SWAP of the pair on register bit J where the pair's tile index matches the tile-bit controls.
+template <int J, typename V, int N>
+__device__ __forceinline__ void pairs_cswap_ip(V (&x)[N], uint32_t ethr, const uint32_t (&er)[N], uint32_t cmask,
+                                               uint32_t cval)
+{
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        if (a & (1 << J)) continue;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(((ethr | er[a]) & cmask) == cval);
+        cswap_ip(x[a], x[a + (1 << J)], m);
+    }
+}
+template <int J, int N>
+__device__ __forceinline__ void pairs_cswap_ip(double2 (&x)[N], double2 (&y)[N], uint32_t ethr,
+                                               const uint32_t (&er)[N], uint32_t cmask, uint32_t cval)
+{
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        if (a & (1 << J)) continue;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(((ethr | er[a]) & cmask) == cval);
+        cswap_ip(x[a], x[a + (1 << J)], y[a], y[a + (1 << J)], m);
     }
 }
 
@@ -189,44 +376,20 @@ __device__ __forceinline__ double grad_pair(const double* mr, const double* mi, 
     }
 }
 
-// One op of structure TYPE on register bit J of the thread's N elements; with CTRL the pair
-// is skipped unless its tile index matches the tile-bit controls.
-template <int J, bool CTRL, int TYPE, typename RR, typename V, int N>
-__device__ __forceinline__ void pairs_apply(V (&x)[N], const RR* mr, const RR* mi, uint32_t ethr,
-                                            const uint32_t (&er)[N], uint32_t cmask, uint32_t cval)
-{
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-        if (a & (1 << J)) continue;
-        if (CTRL && (((ethr | er[a]) & cmask) != cval)) continue;
-        apply_pair<TYPE, RR>(mr, mi, x[a], x[a + (1 << J)]);
-    }
-}
-
-template <int J, bool CTRL, typename RR, typename V, int N>
-__device__ __forceinline__ void op_apply(V (&x)[N], int type, const RR* mr, const RR* mi, uint32_t ethr,
-                                         const uint32_t (&er)[N], uint32_t cmask, uint32_t cval)
-{
-    switch (type) {
-    case OT_SWAP: pairs_apply<J, CTRL, OT_SWAP, RR>(x, mr, mi, ethr, er, cmask, cval); break;
-    case OT_DIAG: pairs_apply<J, CTRL, OT_DIAG, RR>(x, mr, mi, ethr, er, cmask, cval); break;
-    case OT_REAL: pairs_apply<J, CTRL, OT_REAL, RR>(x, mr, mi, ethr, er, cmask, cval); break;
-    case OT_RX: pairs_apply<J, CTRL, OT_RX, RR>(x, mr, mi, ethr, er, cmask, cval); break;
-    default: pairs_apply<J, CTRL, OT_DENSE, RR>(x, mr, mi, ethr, er, cmask, cval); break;
-    }
-}
-
 template <int J, bool CTRL, int GEN, int N>
 __device__ __forceinline__ double pairs_grad(const double2 (&x)[N], const double2 (&y)[N], const double* mr,
                                              const double* mi, uint32_t ethr, const uint32_t (&er)[N], uint32_t cmask,
                                              uint32_t cval)
 {
     double g = 0;
+    bool first = true;  // resolved at compile time when CTRL is false
 #pragma unroll
     for (int a = 0; a < N; ++a) {
         if (a & (1 << J)) continue;
-        if (CTRL && (((ethr | er[a]) & cmask) != cval)) continue;
-        g += grad_pair<GEN>(mr, mi, x[a], x[a + (1 << J)], y[a], y[a + (1 << J)]);
+        const double v = grad_pair<GEN>(mr, mi, x[a], x[a + (1 << J)], y[a], y[a + (1 << J)]);
+        if (CTRL) g += (((ethr | er[a]) & cmask) == cval) ? v : 0.0;  // a select
+        else g = first ? v : g + v;
+        first = false;
     }
     return g;
 }
@@ -314,71 +477,70 @@ __device__ __forceinline__ void group_index(const int (&rpos)[kMaxRegBits], int 
     }
 }
 
-// The pass's op records and group descriptors are copied to LDS in 16-byte words. The first
-// kProgRegs words of every thread are loaded together with the tile (one wait for both);
-// indices are clamped so that every load is in bounds.
-static_assert(sizeof(POp) % 16 == 0 && sizeof(PGroupDesc) % 16 == 0, "16-byte program words");
-
-// Word i of the staged program: op records, then group descriptors, then dense matrices.
-struct ProgSeg {
-    int nwo, nwg, tot;
-};
-__device__ __forceinline__ ProgSeg prog_seg(const PassArgs& a)
+// The dense block matrices of a forward pass are copied to LDS in 16-byte words; the first
+// kDmRegs words of every thread are loaded together with the tile (one wait for both), with
+// indices clamped so that every load is in bounds.
+static_assert(sizeof(POp) % 16 == 0 && sizeof(PGroupDesc) % 16 == 0, "16-byte records");
+constexpr int kDmRegs = 4;
+// With no dense matrices the words are read from the first op record (every forward pass has
+// one) and dropped, so the registers are always defined.
+__device__ __forceinline__ void dm_load(const PassArgs& a, int th, int nthr, uint4 (&w)[kDmRegs])
 {
-    ProgSeg g;
-    g.nwo = a.nops * (int)(sizeof(POp) / 16);
-    g.nwg = a.ngroups * (int)(sizeof(PGroupDesc) / 16);
-    g.tot = g.nwo + g.nwg + a.ndm;
-    return g;
-}
-__device__ __forceinline__ const uint4* prog_src(const PassArgs& a, int i, const ProgSeg& g)
-{
-    return i < g.nwo ? (const uint4*)a.ops + i
-                     : (i < g.nwo + g.nwg ? (const uint4*)a.groups + (i - g.nwo) : a.dmats + (i - g.nwo - g.nwg));
-}
-__device__ __forceinline__ uint4* prog_dst(POp* lops, PGroupDesc* lgrp, uint4* ldm, int i, const ProgSeg& g)
-{
-    return i < g.nwo ? (uint4*)lops + i : (i < g.nwo + g.nwg ? (uint4*)lgrp + (i - g.nwo) : ldm + (i - g.nwo - g.nwg));
-}
-
-template <int kProgRegs>
-__device__ __forceinline__ void prog_load(const PassArgs& a, int th, int nthr, uint4 (&w)[kProgRegs])
-{
-    const ProgSeg g = prog_seg(a);
+    const uint4* src = a.ndm > 0 ? a.dmats : (const uint4*)a.ops;
+    const int last = a.ndm > 0 ? a.ndm - 1 : 0;
 #pragma unroll
-    for (int k = 0; k < kProgRegs; ++k) w[k] = *prog_src(a, min(th + k * nthr, g.tot - 1), g);
+    for (int k = 0; k < kDmRegs; ++k) w[k] = src[min(th + k * nthr, last)];
 }
-
-template <int kProgRegs>
-__device__ __forceinline__ void prog_store(const PassArgs& a, POp* lops, PGroupDesc* lgrp, uint4* ldm, int th,
-                                           int nthr, const uint4 (&w)[kProgRegs])
+__device__ __forceinline__ void dm_store(const PassArgs& a, uint4* ldm, int th, int nthr, const uint4 (&w)[kDmRegs])
 {
-    const ProgSeg g = prog_seg(a);
     // Unconditional: a clamped index writes the word it loaded, so duplicates are identical.
 #pragma unroll
-    for (int k = 0; k < kProgRegs; ++k) *prog_dst(lops, lgrp, ldm, min(th + k * nthr, g.tot - 1), g) = w[k];
-    for (int i = th + kProgRegs * nthr; i < g.tot; i += nthr) *prog_dst(lops, lgrp, ldm, i, g) = *prog_src(a, i, g);
+    for (int k = 0; k < kDmRegs; ++k) ldm[min(th + k * nthr, a.ndm - 1)] = w[k];
+    for (int i = th + kDmRegs * nthr; i < a.ndm; i += nthr) ldm[i] = a.dmats[i];
 }
 
 struct GroupCtl {
     int lds, op0, nops;
     int rpos[kMaxRegBits];
 };
-__device__ __forceinline__ GroupCtl group_ctl(const PGroupDesc& g)
+__device__ __forceinline__ GroupCtl group_ctl_c(const YAO_CONST PGroupDesc* g)
 {
     GroupCtl o;
-    o.lds = sc(g.lds);
-    o.op0 = sc(g.op0);
-    o.nops = sc(g.nops);
+    o.lds = g->lds;
+    o.op0 = g->op0;
+    o.nops = g->nops;
 #pragma unroll
-    for (int j = 0; j < kMaxRegBits; ++j) o.rpos[j] = sc(g.rpos[j]);
+    for (int j = 0; j < kMaxRegBits; ++j) o.rpos[j] = g->rpos[j];
     return o;
 }
 
-// Reduce the per-thread partials red[s * nthr + th] (s < S) to one value per (slot, batch
-// slot of the tile) and store them in gpartial; slot ids are in sl[s]. Order is fixed.
+// ------------------------------------------------------------------------------ gradient sums
+// v from lane (lane op CTRL) of the same DPP row, both 32-bit halves.
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum of v over the lanes of a 16-lane row that share this lane's low c bits (its batch slot
+// of the tile); lanes 0 .. 2^c - 1 of the row end with the sums of slots 0 .. 2^c - 1. Every
+// lane of the row must be active.
+__device__ __forceinline__ double row_sum(double v, int c)
+{
+    if (c < 1) v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]: lane ^ 1
+    if (c < 2) v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]: lane ^ 2
+    if (c < 3) v += dpp_f64<0x124>(v);  // row_ror 4
+    v += dpp_f64<0x128>(v);             // row_ror 8
+    return v;
+}
+
+// Reduce the partials of a register group, red[s * E + e] for gradient s < S (entry e holds
+// batch slot e mod 2^c), to one value per (slot, batch slot of the tile) and store them in
+// gpartial. slots[s] are the group's gradient slots. The order of the sums is fixed.
 __device__ __forceinline__ void group_reduce(double* __restrict__ gpartial, int B, int pstride, int c,
-                                             const double* red, const int* sl, int S, int nthr, int th)
+                                             const double* red, const int* slots, int S, int E, int nthr, int th)
 {
     const int Bc = 1 << c;
     const int b0 = blockIdx.y << c;
@@ -386,16 +548,16 @@ __device__ __forceinline__ void group_reduce(double* __restrict__ gpartial, int 
         for (int task = th; task < S * 16; task += nthr) {
             const int s = task >> 4, j = task & 15;
             double v = 0;
-            for (int th2 = j; th2 < nthr; th2 += 16) v += red[s * nthr + th2];
+            for (int e = j; e < E; e += 16) v += red[s * E + e];
             for (int off = 8; off >= Bc; off >>= 1) v += __shfl_xor(v, off, 16);
-            if (j < Bc && b0 + j < B) gpartial[((uint64_t)sl[s] * B + b0 + j) * pstride + blockIdx.x] = v;
+            if (j < Bc && b0 + j < B) gpartial[((uint64_t)slots[s] * B + b0 + j) * pstride + blockIdx.x] = v;
         }
     } else {
         for (int task = th; task < S * Bc; task += nthr) {
             const int s = task / Bc, bb = task % Bc;
             double v = 0;
-            for (int th2 = bb; th2 < nthr; th2 += Bc) v += red[s * nthr + th2];
-            if (b0 + bb < B) gpartial[((uint64_t)sl[s] * B + b0 + bb) * pstride + blockIdx.x] = v;
+            for (int e = bb; e < E; e += Bc) v += red[s * E + e];
+            if (b0 + bb < B) gpartial[((uint64_t)slots[s] * B + b0 + bb) * pstride + blockIdx.x] = v;
         }
     }
 }
@@ -442,7 +604,8 @@ template <int K> __device__ __forceinline__ uint32_t lds_base(uint32_t gidx, con
 }
 
 template <typename RP, int K>
-__device__ __noinline__ void lds_op_fwd(vec2_t<RP>* lp, const POp* rec, const double* m, int t, int th, int nthr)
+__device__ __noinline__ void lds_op_fwd(vec2_t<RP>* lp, const YAO_CONST POp* rec, const double* m, int t, int th,
+                                        int nthr)
 {
     using VP = vec2_t<RP>;
     constexpr int D = 1 << K, DD = D * D;
@@ -472,7 +635,7 @@ __device__ __noinline__ void lds_op_fwd(vec2_t<RP>* lp, const POp* rec, const do
 }
 
 template <typename RL, int K>
-__device__ __noinline__ double lds_op_bwd(double2* lp, vec2_t<RL>* ll, const POp* rec, const double* m, int t, int th,
+__device__ __noinline__ double lds_op_bwd(double2* lp, vec2_t<RL>* ll, const YAO_CONST POp* rec, const double* m, int t, int th,
                                           int nthr)
 {
     using VL = vec2_t<RL>;
@@ -626,34 +789,33 @@ __global__ __launch_bounds__(512, sizeof(RP) == 4 ? 3 : 1) void k_pass_fwd(PassA
     const int t = a.t;
     const int nthr = 1 << (t - RB);
     const int th = threadIdx.x;
+    // LDS: tile | dense block matrices (2 * 256 RP each), sized for this pass.
     VP* lp = (VP*)smem;
-    // LDS: tile | op records | group descriptors | dense block matrices (2 * 256 RP each),
-    // each area sized for this pass.
-    POp* lops = (POp*)(smem + (sizeof(VP) << t));
-    PGroupDesc* lgrp = (PGroupDesc*)(lops + a.nops);
-    uint4* ldm = (uint4*)(lgrp + a.ngroups);
+    uint4* ldm = (uint4*)(smem + (sizeof(VP) << t));
+    const YAO_CONST POp* gops = cptr(a.ops);
+    const YAO_CONST PGroupDesc* ggrp = cptr(a.groups);
     const TileCtx tc = tile_ctx<RB>(a, th);
     VP* gp = (VP*)a.psi;
     // Every load is in bounds (slots past B read the last slot and are never stored), so all
     // of them are issued before the first wait.
     {
-        uint4 w[4];
-        prog_load(a, th, nthr, w);
+        uint4 w[kDmRegs];
+        dm_load(a, th, nthr, w);
         VP v[N];
 #pragma unroll
         for (int r = 0; r < N; ++r) v[r] = gp[tile_off<RB>(a, tc, r)];
-        prog_store(a, lops, lgrp, ldm, th, nthr, w);
+        if (a.ndm) dm_store(a, ldm, th, nthr, w);
 #pragma unroll
         for (int r = 0; r < N; ++r) lp[swz((uint32_t)th + (uint32_t)r * nthr)] = v[r];
     }
     __syncthreads();
 
     for (int gi = 0; gi < a.ngroups; ++gi) {
-        const GroupCtl G = group_ctl(lgrp[gi]);
+        const GroupCtl G = group_ctl_c(ggrp + gi);
         if (G.lds == 2) {
             // One dense block on the register bits; its remaining controls are on tile bits
             // outside them (the same for all 16 elements of a thread) or outside the tile.
-            OpCtl op = op_ctl(lops[G.op0]);
+            OpCtl op = op_ctl_c(gops + G.op0);
             fold_outer_controls(op, tc.base);
             if constexpr (sizeof(RP) == 4) {
                 // Complex64 plans hold dense blocks only for tiles of >= 64 columns.
@@ -672,11 +834,11 @@ __global__ __launch_bounds__(512, sizeof(RP) == 4 ? 3 : 1) void k_pass_fwd(PassA
             continue;
         }
         if (G.lds) {
-            const POp* rec = lops + G.op0;
-            const uint64_t omask = sc64(rec->omask), oval = sc64(rec->oval);
+            const YAO_CONST POp* rec = gops + G.op0;
+            const uint64_t omask = rec->omask, oval = rec->oval;
             if ((tc.base & omask) == oval) {
-                const double* m = a.mats + sc(rec->mat);
-                if (sc(rec->k) == 2) lds_op_fwd<RP, 2>(lp, rec, m, t, th, nthr);
+                const double* m = a.mats + rec->mat;
+                if (rec->k == 2) lds_op_fwd<RP, 2>(lp, rec, m, t, th, nthr);
                 else lds_op_fwd<RP, 3>(lp, rec, m, t, th, nthr);
             }
             __syncthreads();
@@ -687,27 +849,27 @@ __global__ __launch_bounds__(512, sizeof(RP) == 4 ? 3 : 1) void k_pass_fwd(PassA
         VP x[N];
 #pragma unroll
         for (int r = 0; r < N; ++r) x[r] = lp[swz(ethr | er[r])];
-        // The record of op oi + 1 is read from LDS while op oi computes and is moved to scalar
-        // registers at the end of op oi.
-        OpS<RP> cur = load_op<RP>(lops[G.op0]);
+        // The record of op oi + 1 is loaded (scalar loads) while op oi computes.
+        const YAO_CONST POp* rec = gops + G.op0;
+        OpS<RP> cur = load_op_c<RP>(rec);
+        // Wait here for the first record (and the LDS reads): scalar loads return out of order,
+        // so a wait inside the loop would also wait for the prefetch of the next record.
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
         for (int oi = 0; oi < G.nops; ++oi) {
-            const POp nxt = lops[G.op0 + min(oi + 1, G.nops - 1)];
+            const OpS<RP> nxt = load_op_c<RP>(rec + min(oi + 1, G.nops - 1));
             OpCtl op = cur.c;
             fold_outer_controls(op, tc.base);
             const RP* mr = cur.m;
             const RP* mi = cur.m + 4;
-#define YAO_FWD_CASE(J)                                                                       \
-    case J:                                                                                   \
-        if (op.cmask) op_apply<J, true, RP>(x, op.type, mr, mi, ethr, er, op.cmask, op.cval); \
-        else op_apply<J, false, RP>(x, op.type, mr, mi, ethr, er, 0u, 0u);                    \
-        break;
-            // Ops of the common classes (see op_variant) have code of their own, picked by one
-            // switch on the variant the host chose.
-#define YAO_FWD_FAST(J)                                                                             \
-    case 0 * kRegBitsFwd + J: pairs_apply<J, false, OT_RX, RP>(x, mr, mi, ethr, er, 0u, 0u); break;    \
-    case 1 * kRegBitsFwd + J: pairs_apply<J, false, OT_DIAG, RP>(x, mr, mi, ethr, er, 0u, 0u); break;  \
-    case 2 * kRegBitsFwd + J: pairs_apply<J, false, OT_DENSE, RP>(x, mr, mi, ethr, er, 0u, 0u); break; \
-    case 3 * kRegBitsFwd + J: pairs_apply<J, true, OT_SWAP, RP>(x, mr, mi, ethr, er, op.cmask, op.cval); break;
+#define YAO_FWD_CASE(J) \
+    case J: pairs_dense_ctl_ip<J>(x, mr, mi, ethr, er, op.cmask, op.cval); break;
+            // Ops of the common classes (see op_variant) have in-place code of their own, picked
+            // by one switch on the variant the host chose.
+#define YAO_FWD_FAST(J)                                                                              \
+    case 0 * kRegBitsFwd + J: pairs_ip<J, OT_RX>(x, mr, mi); break;                                   \
+    case 1 * kRegBitsFwd + J: pairs_ip<J, OT_DIAG>(x, mr, mi); break;                                 \
+    case 2 * kRegBitsFwd + J: pairs_ip<J, OT_DENSE>(x, mr, mi); break;                                \
+    case 3 * kRegBitsFwd + J: pairs_cswap_ip<J>(x, ethr, er, op.cmask, op.cval); break;
             switch (op.var) {
                 YAO_FWD_FAST(0) YAO_FWD_FAST(1) YAO_FWD_FAST(2) YAO_FWD_FAST(3)
             default:
@@ -716,7 +878,7 @@ __global__ __launch_bounds__(512, sizeof(RP) == 4 ? 3 : 1) void k_pass_fwd(PassA
             }
 #undef YAO_FWD_FAST
 #undef YAO_FWD_CASE
-            cur = load_op<RP>(nxt);
+            cur = nxt;
         }
 #pragma unroll
         for (int r = 0; r < N; ++r) lp[swz(ethr | er[r])] = x[r];
@@ -730,7 +892,15 @@ __global__ __launch_bounds__(512, sizeof(RP) == 4 ? 3 : 1) void k_pass_fwd(PassA
 }
 
 // ------------------------------------------------------------------------------ backward kernel
-template <typename RL>
+// Entries of gradient partials per register group: one per 16-lane row and batch slot of the
+// tile (row sums), or one per thread in tiles of fewer than 16 threads.
+__host__ __device__ __forceinline__ int grad_entries(int nthr, int c)
+{
+    return nthr >= 16 ? (nthr >> 4) << c : nthr;
+}
+
+// C0: tiles of one batch slot (c = 0), where every row-sum step applies.
+template <typename RL, bool C0>
 __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
 {
     constexpr int RB = kRegBitsBwd, N = 1 << RB;
@@ -739,18 +909,23 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
     const int t = a.t;
     const int nthr = 1 << (t - RB);
     const int th = threadIdx.x;
+    const int c = C0 ? 0 : a.c;
+    const bool rows = nthr >= 16;
+    const int E = grad_entries(nthr, c);
+    // LDS: psi | lambda | gradient partials, two buffers of kMaxGroupSlots * E (a group's
+    // partials are reduced after the barrier that ends it, while the next group fills the other
+    // buffer).
     double2* lp = (double2*)smem;
     VL* ll = (VL*)(smem + ((size_t)16 << t));
-    double* red = (double*)(smem + ((size_t)(16 + sizeof(VL)) << t));
-    int* sl = (int*)(red + kMaxGroupSlots * nthr);
-    POp* lops = (POp*)(sl + 16);
-    PGroupDesc* lgrp = (PGroupDesc*)(lops + a.nops);
+    double* red0 = (double*)(smem + ((size_t)(16 + sizeof(VL)) << t));
+    const int ent = rows ? (th >> 4) * (1 << c) + (th & 15) : th;
+    const bool stores = rows ? (th & 15) < (1 << c) : true;
+    const YAO_CONST POp* gops = cptr(a.ops);
+    const YAO_CONST PGroupDesc* ggrp = cptr(a.groups);
     const TileCtx tc = tile_ctx<RB>(a, th);
     double2* gp = (double2*)a.psi;
     VL* gl = (VL*)a.lam;
     {
-        uint4 pw[4];
-        prog_load(a, th, nthr, pw);
         double2 v[N];
         VL w[N];
 #pragma unroll
@@ -759,7 +934,6 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
             v[r] = gp[off];
             w[r] = gl[off];
         }
-        prog_store(a, lops, lgrp, nullptr, th, nthr, pw);
 #pragma unroll
         for (int r = 0; r < N; ++r) {
             const uint32_t e = swz((uint32_t)th + (uint32_t)r * nthr);
@@ -769,102 +943,96 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
     }
     __syncthreads();
 
+    int buf = 0;
     for (int gi = 0; gi < a.ngroups; ++gi) {
-        const GroupCtl G = group_ctl(lgrp[gi]);
+        const GroupCtl G = group_ctl_c(ggrp + gi);
+        double* red = red0 + buf * (kMaxGroupSlots * E);
+        int nslot = 0;
         if (G.lds) {
-            const POp* rec = lops + G.op0;
-            const uint64_t omask = sc64(rec->omask), oval = sc64(rec->oval);
-            const int slot = sc(rec->slot);
+            const YAO_CONST POp* rec = gops + G.op0;
+            const uint64_t omask = rec->omask, oval = rec->oval;
             double g = 0;
             if ((tc.base & omask) == oval) {
-                const double* m = a.mats + sc(rec->mat);
-                if (sc(rec->k) == 2) g = lds_op_bwd<RL, 2>(lp, ll, rec, m, t, th, nthr);
+                const double* m = a.mats + rec->mat;
+                if (rec->k == 2) g = lds_op_bwd<RL, 2>(lp, ll, rec, m, t, th, nthr);
                 else g = lds_op_bwd<RL, 3>(lp, ll, rec, m, t, th, nthr);
             }
-            if (slot >= 0) {
-                red[th] = g;
-                if (th == 0) sl[0] = slot;
+            if (rec->slot >= 0) {
+                if (rows) g = row_sum(g, c);
+                if (stores) red[ent] = g;
+                nslot = 1;
             }
-            __syncthreads();
-            if (slot >= 0) {
-                group_reduce(a.gpartial, a.B, a.pstride, a.c, red, sl, 1, nthr, th);
-                __syncthreads();
-            }
-            continue;
-        }
-        uint32_t ethr, er[N];
-        group_index<RB>(G.rpos, t, th, ethr, er);
-        double2 x[N], y[N];
+        } else {
+            uint32_t ethr, er[N];
+            group_index<RB>(G.rpos, t, th, ethr, er);
+            double2 x[N], y[N];
 #pragma unroll
-        for (int r = 0; r < N; ++r) {
-            const uint32_t p = swz(ethr | er[r]);
-            x[r] = lp[p];
-            const VL w = ll[p];
-            y[r] = make_double2((double)w.x, (double)w.y);
-        }
-        int nslot = 0;
-        OpS<double> cur = load_op<double>(lops[G.op0]);
-        for (int oi = 0; oi < G.nops; ++oi) {
-            const POp nxt = lops[G.op0 + min(oi + 1, G.nops - 1)];
-            OpCtl op = cur.c;
-            fold_outer_controls(op, tc.base);
-            const double* m = cur.m;
-            double g = 0;
-            const double* gm = a.mats + op.mat + 8;  // M of a dense generator
+            for (int r = 0; r < N; ++r) {
+                const uint32_t p = swz(ethr | er[r]);
+                x[r] = lp[p];
+                const VL w = ll[p];
+                y[r] = make_double2((double)w.x, (double)w.y);
+            }
+            const YAO_CONST POp* rec = gops + G.op0;
+            OpS<double> cur = load_op_c<double>(rec);
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), as in the forward kernel
+            for (int oi = 0; oi < G.nops; ++oi) {
+                const OpS<double> nxt = load_op_c<double>(rec + min(oi + 1, G.nops - 1));
+                OpCtl op = cur.c;
+                fold_outer_controls(op, tc.base);
+                const double* m = cur.m;
+                double g = 0;
+                const double* gm = a.mats + op.mat + 8;  // M of a dense generator
 #define YAO_BWD_CASE(J)                                                                                       \
     case J:                                                                                                   \
-        if (op.cmask) {                                                                                       \
-            if (op.slot >= 0) g = op_grad<J, true>(x, y, op.gen, gm, gm + 4, ethr, er, op.cmask, op.cval);    \
-            op_apply<J, true, double>(x, op.type, m, m + 4, ethr, er, op.cmask, op.cval);                     \
-            op_apply<J, true, double>(y, op.type, m, m + 4, ethr, er, op.cmask, op.cval);                     \
-        } else {                                                                                              \
-            if (op.slot >= 0) g = op_grad<J, false>(x, y, op.gen, gm, gm + 4, ethr, er, 0u, 0u);             \
-            op_apply<J, false, double>(x, op.type, m, m + 4, ethr, er, 0u, 0u);                               \
-            op_apply<J, false, double>(y, op.type, m, m + 4, ethr, er, 0u, 0u);                               \
+        if (op.slot >= 0) {                                                                                   \
+            if (op.cmask) g = op_grad<J, true>(x, y, op.gen, gm, gm + 4, ethr, er, op.cmask, op.cval);        \
+            else g = op_grad<J, false>(x, y, op.gen, gm, gm + 4, ethr, er, 0u, 0u);                           \
         }                                                                                                     \
+        pairs_dense_ctl_ip<J>(x, y, m, m + 4, ethr, er, op.cmask, op.cval);                                   \
         break;
-            // Ops of the common classes (see op_variant) have code of their own, picked by one
-            // switch on the variant the host chose.
-#define YAO_BWD_FAST(J)                                                                             \
-    case 0 * kRegBitsBwd + J:                                                                       \
-        g = pairs_grad<J, false, GEN_X>(x, y, m, m + 4, ethr, er, 0u, 0u);                            \
-        pairs_apply<J, false, OT_RX, double>(x, m, m + 4, ethr, er, 0u, 0u);                          \
-        pairs_apply<J, false, OT_RX, double>(y, m, m + 4, ethr, er, 0u, 0u);                          \
-        break;                                                                                      \
-    case 1 * kRegBitsBwd + J:                                                                       \
-        g = pairs_grad<J, false, GEN_Z>(x, y, m, m + 4, ethr, er, 0u, 0u);                            \
-        pairs_apply<J, false, OT_DIAG, double>(x, m, m + 4, ethr, er, 0u, 0u);                        \
-        pairs_apply<J, false, OT_DIAG, double>(y, m, m + 4, ethr, er, 0u, 0u);                        \
-        break;                                                                                      \
-    case 2 * kRegBitsBwd + J:                                                                       \
-        pairs_apply<J, true, OT_SWAP, double>(x, m, m + 4, ethr, er, op.cmask, op.cval);              \
-        pairs_apply<J, true, OT_SWAP, double>(y, m, m + 4, ethr, er, op.cmask, op.cval);              \
+                // Ops of the common classes (see op_variant) have in-place code of their own,
+                // picked by one switch on the variant the host chose.
+#define YAO_BWD_FAST(J)                                                          \
+    case 0 * kRegBitsBwd + J:                                                    \
+        g = pairs_grad<J, false, GEN_X>(x, y, m, m + 4, ethr, er, 0u, 0u);         \
+        pairs_ip<J, OT_RX>(x, m, m + 4);                                         \
+        pairs_ip<J, OT_RX>(y, m, m + 4);                                         \
+        break;                                                                   \
+    case 1 * kRegBitsBwd + J:                                                    \
+        g = pairs_grad<J, false, GEN_Z>(x, y, m, m + 4, ethr, er, 0u, 0u);         \
+        pairs_ip<J, OT_DIAG>(x, m, m + 4);                                       \
+        pairs_ip<J, OT_DIAG>(y, m, m + 4);                                       \
+        break;                                                                   \
+    case 2 * kRegBitsBwd + J:                                                    \
+        pairs_cswap_ip<J>(x, y, ethr, er, op.cmask, op.cval);                    \
         break;
-            switch (op.var) {
-                YAO_BWD_FAST(0) YAO_BWD_FAST(1) YAO_BWD_FAST(2)
-            default:
-                switch (op.rpos) { YAO_BWD_CASE(0) YAO_BWD_CASE(1) default: YAO_BWD_CASE(2) }
-                break;
-            }
+                switch (op.var) {
+                    YAO_BWD_FAST(0) YAO_BWD_FAST(1) YAO_BWD_FAST(2)
+                default:
+                    switch (op.rpos) { YAO_BWD_CASE(0) YAO_BWD_CASE(1) default: YAO_BWD_CASE(2) }
+                    break;
+                }
 #undef YAO_BWD_FAST
 #undef YAO_BWD_CASE
-            if (op.slot >= 0) {
-                red[nslot * nthr + th] = g;
-                if (th == 0) sl[nslot] = op.slot;
-                ++nslot;
+                if (op.slot >= 0) {
+                    if (rows) g = row_sum(g, c);
+                    if (stores) red[nslot * E + ent] = g;
+                    ++nslot;
+                }
+                cur = nxt;
             }
-            cur = load_op<double>(nxt);
-        }
 #pragma unroll
-        for (int r = 0; r < N; ++r) {
-            const uint32_t p = swz(ethr | er[r]);
-            lp[p] = x[r];
-            ll[p] = mkv<VL, RL>((RL)y[r].x, (RL)y[r].y);
+            for (int r = 0; r < N; ++r) {
+                const uint32_t p = swz(ethr | er[r]);
+                lp[p] = x[r];
+                ll[p] = mkv<VL, RL>((RL)y[r].x, (RL)y[r].y);
+            }
         }
         __syncthreads();
         if (nslot > 0) {
-            group_reduce(a.gpartial, a.B, a.pstride, a.c, red, sl, nslot, nthr, th);
-            __syncthreads();
+            group_reduce(a.gpartial, a.B, a.pstride, c, red, a.groups[gi].slots, nslot, E, nthr, th);
+            buf ^= 1;
         }
     }
 
@@ -879,13 +1047,16 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
     }
 }
 
+// Raise each pass kernel's dynamic LDS limit to the CU's 160 KiB, once per kernel.
 template <typename K> int set_lds_limit(K kernel)
 {
-    static bool done = false;
-    if (!done) {
-        YAO_HIP(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        done = true;
-    }
+    static std::mutex mu;
+    static std::vector<const void*> done;
+    std::lock_guard<std::mutex> lk(mu);
+    for (const void* k : done)
+        if (k == (const void*)kernel) return 0;
+    YAO_HIP(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    done.push_back((const void*)kernel);
     return 0;
 }
 
@@ -981,17 +1152,18 @@ int prepare_pass_kernels()
 {
     YAO_TRY(set_lds_limit(k_pass_fwd<float>));
     YAO_TRY(set_lds_limit(k_pass_fwd<double>));
-    YAO_TRY(set_lds_limit(k_pass_bwd<float>));
-    YAO_TRY(set_lds_limit(k_pass_bwd<double>));
+    YAO_TRY(set_lds_limit(k_pass_bwd<float, true>));
+    YAO_TRY(set_lds_limit(k_pass_bwd<float, false>));
+    YAO_TRY(set_lds_limit(k_pass_bwd<double, true>));
+    YAO_TRY(set_lds_limit(k_pass_bwd<double, false>));
     return 0;
 }
 
-size_t pass_lds_bytes(bool bwd, int t, int psi_bytes, int lam_bytes, int nops, int ngroups, int dm_words)
+size_t pass_lds_bytes(bool bwd, int t, int c, int psi_bytes, int lam_bytes, int dm_words)
 {
-    const size_t prog = sizeof(POp) * (size_t)nops + sizeof(PGroupDesc) * (size_t)ngroups;
-    if (!bwd) return ((size_t)psi_bytes << t) + prog + 16 * (size_t)dm_words;
-    const size_t nthr = size_t(1) << (t - kRegBitsBwd);
-    return ((size_t)(16 + lam_bytes) << t) + sizeof(double) * kMaxGroupSlots * nthr + sizeof(int) * 16 + prog;
+    if (!bwd) return ((size_t)psi_bytes << t) + 16 * (size_t)dm_words;
+    const int nthr = 1 << (t - kRegBitsBwd);
+    return ((size_t)(16 + lam_bytes) << t) + sizeof(double) * 2 * kMaxGroupSlots * (size_t)grad_entries(nthr, c);
 }
 
 int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, const POp* ops, const PGroupDesc* groups,
@@ -1046,7 +1218,7 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
     dim3 block(1 << (t - (bwd ? kRegBitsBwd : kRegBitsFwd)));
     const int pb = bwd ? 16 : (psi_dtype == YAO_C64 ? 8 : 16);
     const int lb = bwd ? (lam_dtype == YAO_C64 ? 8 : 16) : 0;
-    const size_t lds = pass_lds_bytes(bwd, t, pb, lb, nops, ngroups, bwd ? 0 : dm_words);
+    const size_t lds = pass_lds_bytes(bwd, t, c, pb, lb, bwd ? 0 : dm_words);
     if (lds > 160 * 1024) return set_error(YAO_EINVAL, "tile of 2^%d needs %zu bytes of LDS", t, lds);
     hipStream_t st = stream();
     const int pi = prof_begin(bwd ? YAO_KF_PASS_BWD : YAO_KF_PASS_FWD);
@@ -1060,11 +1232,21 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
         }
     } else {
         if (lam_dtype == YAO_C64) {
-            YAO_TRY(set_lds_limit(k_pass_bwd<float>));
-            k_pass_bwd<float><<<grid, block, lds, st>>>(a);
+            if (c == 0) {
+                YAO_TRY(set_lds_limit(k_pass_bwd<float, true>));
+                k_pass_bwd<float, true><<<grid, block, lds, st>>>(a);
+            } else {
+                YAO_TRY(set_lds_limit(k_pass_bwd<float, false>));
+                k_pass_bwd<float, false><<<grid, block, lds, st>>>(a);
+            }
         } else {
-            YAO_TRY(set_lds_limit(k_pass_bwd<double>));
-            k_pass_bwd<double><<<grid, block, lds, st>>>(a);
+            if (c == 0) {
+                YAO_TRY(set_lds_limit(k_pass_bwd<double, true>));
+                k_pass_bwd<double, true><<<grid, block, lds, st>>>(a);
+            } else {
+                YAO_TRY(set_lds_limit(k_pass_bwd<double, false>));
+                k_pass_bwd<double, false><<<grid, block, lds, st>>>(a);
+            }
         }
     }
     prof_end(pi, 2.0 * (double)(uint64_t(1) << n) * B * (pb + lb), flops);
