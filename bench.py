@@ -212,7 +212,7 @@ def main():
             roofline = {"bound": "alu", "achieved": round(tfl, 3), "peak": peak_alu, "unit": "TFLOP/s",
                         "frac": round(tfl / peak_alu, 4), "traffic": None}
         if dtype == yb.C64 and fam in (2, 3):
-            roofline["traffic"] = measured_traffic("k_pass_bwd<float>" if fam == 3 else "k_pass_fwd<float>")
+            roofline["traffic"] = measured_traffic("k_pass_bwd<float, true>" if fam == 3 else "k_pass_fwd<float>")
         roofline.update({"kernel": KERNEL_NAMES[fam], "launches_per_step": nl / args.steps,
                          "avg_launch_us": round(ms * 1e3 / nl, 2), "algo_bytes_per_launch": by / nl,
                          "algo_flops_per_launch": fl / nl, "achieved_gbs": round(gbs, 1),

@@ -13,6 +13,7 @@
 //
 // The pass's op records are copied to LDS together with the tile; LDS reads complete in
 // order, so the record of the next op is fetched while the current op computes.
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -515,12 +516,13 @@ __device__ __forceinline__ GroupCtl group_ctl_c(const YAO_CONST PGroupDesc* g)
 }
 
 // ------------------------------------------------------------------------------ gradient sums
-// v from lane (lane op CTRL) of the same DPP row, both 32-bit halves.
+// v from lane (lane op CTRL) of the same DPP row, both 32-bit halves. The patterns used here
+// read inside the row only, so every source lane is valid.
 template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
 {
     const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
@@ -536,11 +538,12 @@ __device__ __forceinline__ double row_sum(double v, int c)
     return v;
 }
 
-// Reduce the partials of a register group, red[s * E + e] for gradient s < S (entry e holds
-// batch slot e mod 2^c), to one value per (slot, batch slot of the tile) and store them in
-// gpartial. slots[s] are the group's gradient slots. The order of the sums is fixed.
-__device__ __forceinline__ void group_reduce(double* __restrict__ gpartial, int B, int pstride, int c,
-                                             const double* red, const int* slots, int S, int E, int nthr, int th)
+// Reduce partials red[s * E + e] for gradient s < S (entry e holds batch slot e mod 2^c) to
+// one value per (gradient, batch slot of the tile) and store it in gpartial at the slot
+// slot_of(s). The order of the sums is fixed.
+template <typename SlotOf>
+__device__ __forceinline__ void reduce_partials(double* __restrict__ gpartial, int B, int pstride, int c,
+                                                const double* red, SlotOf slot_of, int S, int E, int nthr, int th)
 {
     const int Bc = 1 << c;
     const int b0 = blockIdx.y << c;
@@ -550,14 +553,14 @@ __device__ __forceinline__ void group_reduce(double* __restrict__ gpartial, int 
             double v = 0;
             for (int e = j; e < E; e += 16) v += red[s * E + e];
             for (int off = 8; off >= Bc; off >>= 1) v += __shfl_xor(v, off, 16);
-            if (j < Bc && b0 + j < B) gpartial[((uint64_t)slots[s] * B + b0 + j) * pstride + blockIdx.x] = v;
+            if (j < Bc && b0 + j < B) gpartial[((uint64_t)slot_of(s) * B + b0 + j) * pstride + blockIdx.x] = v;
         }
     } else {
         for (int task = th; task < S * Bc; task += nthr) {
             const int s = task / Bc, bb = task % Bc;
             double v = 0;
             for (int e = bb; e < E; e += Bc) v += red[s * E + e];
-            if (b0 + bb < B) gpartial[((uint64_t)slots[s] * B + b0 + bb) * pstride + blockIdx.x] = v;
+            if (b0 + bb < B) gpartial[((uint64_t)slot_of(s) * B + b0 + bb) * pstride + blockIdx.x] = v;
         }
     }
 }
@@ -849,36 +852,52 @@ __global__ __launch_bounds__(512, sizeof(RP) == 4 ? 3 : 1) void k_pass_fwd(PassA
         VP x[N];
 #pragma unroll
         for (int r = 0; r < N; ++r) x[r] = lp[swz(ethr | er[r])];
-        // The record of op oi + 1 is loaded (scalar loads) while op oi computes.
-        const YAO_CONST POp* rec = gops + G.op0;
-        OpS<RP> cur = load_op_c<RP>(rec);
-        // Wait here for the first record (and the LDS reads): scalar loads return out of order,
-        // so a wait inside the loop would also wait for the prefetch of the next record.
-        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-        for (int oi = 0; oi < G.nops; ++oi) {
-            const OpS<RP> nxt = load_op_c<RP>(rec + min(oi + 1, G.nops - 1));
-            OpCtl op = cur.c;
-            fold_outer_controls(op, tc.base);
-            const RP* mr = cur.m;
-            const RP* mi = cur.m + 4;
-#define YAO_FWD_CASE(J) \
-    case J: pairs_dense_ctl_ip<J>(x, mr, mi, ethr, er, op.cmask, op.cval); break;
-            // Ops of the common classes (see op_variant) have in-place code of their own, picked
-            // by one switch on the variant the host chose.
-#define YAO_FWD_FAST(J)                                                                              \
-    case 0 * kRegBitsFwd + J: pairs_ip<J, OT_RX>(x, mr, mi); break;                                   \
-    case 1 * kRegBitsFwd + J: pairs_ip<J, OT_DIAG>(x, mr, mi); break;                                 \
-    case 2 * kRegBitsFwd + J: pairs_ip<J, OT_DENSE>(x, mr, mi); break;                                \
-    case 3 * kRegBitsFwd + J: pairs_cswap_ip<J>(x, ethr, er, op.cmask, op.cval); break;
-            switch (op.var) {
+        // One op: the common classes (see op_variant: no controls outside the tile, and none
+        // at all but for the controlled SWAP) have in-place code of their own, picked by one
+        // switch on the variant the host chose; the rest take the masked dense update.
+        auto apply = [&](const OpS<RP>& o) __attribute__((always_inline)) {
+            const RP* mr = o.m;
+            const RP* mi = o.m + 4;
+#define YAO_FWD_CASE(J)                                                  \
+    case J: {                                                            \
+        OpCtl op = o.c;                                                  \
+        fold_outer_controls(op, tc.base);                                \
+        pairs_dense_ctl_ip<J>(x, mr, mi, ethr, er, op.cmask, op.cval);   \
+        break;                                                           \
+    }
+#define YAO_FWD_FAST(J)                                                                            \
+    case 0 * kRegBitsFwd + J: pairs_ip<J, OT_RX>(x, mr, mi); break;                                 \
+    case 1 * kRegBitsFwd + J: pairs_ip<J, OT_DIAG>(x, mr, mi); break;                               \
+    case 2 * kRegBitsFwd + J: pairs_ip<J, OT_DENSE>(x, mr, mi); break;                              \
+    case 3 * kRegBitsFwd + J: pairs_cswap_ip<J>(x, ethr, er, o.c.cmask, o.c.cval); break;
+            switch (o.c.var) {
                 YAO_FWD_FAST(0) YAO_FWD_FAST(1) YAO_FWD_FAST(2) YAO_FWD_FAST(3)
             default:
-                switch (op.rpos) { YAO_FWD_CASE(0) YAO_FWD_CASE(1) YAO_FWD_CASE(2) default: YAO_FWD_CASE(3) }
+                switch (o.c.rpos) { YAO_FWD_CASE(0) YAO_FWD_CASE(1) YAO_FWD_CASE(2) default: YAO_FWD_CASE(3) }
                 break;
             }
 #undef YAO_FWD_FAST
 #undef YAO_FWD_CASE
-            cur = nxt;
+        };
+        // Two record buffers in turn: the record of the next op is loaded (scalar loads) while
+        // the current one computes, and is waited for only at the end of it. The record one
+        // past a group's last op is always readable (it lies inside the program's buffer) and
+        // is never used.
+        // Scalar loads return out of order, so each buffer's wait is placed (and fenced from
+        // the scheduler) before the other buffer's loads are issued; otherwise it would also
+        // wait for the prefetch.
+        const YAO_CONST POp* rec = gops + G.op0;
+        OpS<RP> A = load_op_c<RP>(rec);
+        for (int oi = 0; oi < G.nops; oi += 2) {
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): A (and the LDS reads) arrived
+            __builtin_amdgcn_sched_barrier(0);
+            const OpS<RP> B = load_op_c<RP>(rec + oi + 1);
+            apply(A);
+            if (oi + 1 >= G.nops) break;
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // B arrived
+            __builtin_amdgcn_sched_barrier(0);
+            A = load_op_c<RP>(rec + oi + 2);
+            apply(B);
         }
 #pragma unroll
         for (int r = 0; r < N; ++r) lp[swz(ethr | er[r])] = x[r];
@@ -899,9 +918,10 @@ __host__ __device__ __forceinline__ int grad_entries(int nthr, int c)
     return nthr >= 16 ? (nthr >> 4) << c : nthr;
 }
 
-// C0: tiles of one batch slot (c = 0), where every row-sum step applies.
+// C0: tiles of one batch slot (c = 0), where every row-sum step applies. At most 168 VGPRs, so
+// that three 256-thread tiles of 2^11 elements (48 KiB of LDS each) fit on one CU.
 template <typename RL, bool C0>
-__global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
+__global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
 {
     constexpr int RB = kRegBitsBwd, N = 1 << RB;
     using VL = vec2_t<RL>;
@@ -973,26 +993,23 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
                 const VL w = ll[p];
                 y[r] = make_double2((double)w.x, (double)w.y);
             }
-            const YAO_CONST POp* rec = gops + G.op0;
-            OpS<double> cur = load_op_c<double>(rec);
-            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), as in the forward kernel
-            for (int oi = 0; oi < G.nops; ++oi) {
-                const OpS<double> nxt = load_op_c<double>(rec + min(oi + 1, G.nops - 1));
-                OpCtl op = cur.c;
-                fold_outer_controls(op, tc.base);
-                const double* m = cur.m;
+            // One op (see the forward kernel): its gradient partial first, from psi and lambda
+            // before the update, then U^dagger on both.
+            auto apply = [&](const OpS<double>& o) __attribute__((always_inline)) {
+                const double* m = o.m;
                 double g = 0;
-                const double* gm = a.mats + op.mat + 8;  // M of a dense generator
-#define YAO_BWD_CASE(J)                                                                                       \
-    case J:                                                                                                   \
-        if (op.slot >= 0) {                                                                                   \
-            if (op.cmask) g = op_grad<J, true>(x, y, op.gen, gm, gm + 4, ethr, er, op.cmask, op.cval);        \
-            else g = op_grad<J, false>(x, y, op.gen, gm, gm + 4, ethr, er, 0u, 0u);                           \
-        }                                                                                                     \
-        pairs_dense_ctl_ip<J>(x, y, m, m + 4, ethr, er, op.cmask, op.cval);                                   \
-        break;
-                // Ops of the common classes (see op_variant) have in-place code of their own,
-                // picked by one switch on the variant the host chose.
+#define YAO_BWD_CASE(J)                                                                                 \
+    case J: {                                                                                           \
+        OpCtl op = o.c;                                                                                 \
+        fold_outer_controls(op, tc.base);                                                               \
+        const double* gm = a.mats + op.mat + 8; /* M of a dense generator */                           \
+        if (op.slot >= 0) {                                                                             \
+            if (op.cmask) g = op_grad<J, true>(x, y, op.gen, gm, gm + 4, ethr, er, op.cmask, op.cval);  \
+            else g = op_grad<J, false>(x, y, op.gen, gm, gm + 4, ethr, er, 0u, 0u);                     \
+        }                                                                                               \
+        pairs_dense_ctl_ip<J>(x, y, m, m + 4, ethr, er, op.cmask, op.cval);                             \
+        break;                                                                                          \
+    }
 #define YAO_BWD_FAST(J)                                                          \
     case 0 * kRegBitsBwd + J:                                                    \
         g = pairs_grad<J, false, GEN_X>(x, y, m, m + 4, ethr, er, 0u, 0u);         \
@@ -1005,22 +1022,35 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
         pairs_ip<J, OT_DIAG>(y, m, m + 4);                                       \
         break;                                                                   \
     case 2 * kRegBitsBwd + J:                                                    \
-        pairs_cswap_ip<J>(x, y, ethr, er, op.cmask, op.cval);                    \
+        pairs_cswap_ip<J>(x, y, ethr, er, o.c.cmask, o.c.cval);                  \
         break;
-                switch (op.var) {
+                switch (o.c.var) {
                     YAO_BWD_FAST(0) YAO_BWD_FAST(1) YAO_BWD_FAST(2)
                 default:
-                    switch (op.rpos) { YAO_BWD_CASE(0) YAO_BWD_CASE(1) default: YAO_BWD_CASE(2) }
+                    switch (o.c.rpos) { YAO_BWD_CASE(0) YAO_BWD_CASE(1) default: YAO_BWD_CASE(2) }
                     break;
                 }
 #undef YAO_BWD_FAST
 #undef YAO_BWD_CASE
-                if (op.slot >= 0) {
+                if (o.c.slot >= 0) {
                     if (rows) g = row_sum(g, c);
                     if (stores) red[nslot * E + ent] = g;
                     ++nslot;
                 }
-                cur = nxt;
+            };
+            // Two record buffers in turn, as in the forward kernel.
+            const YAO_CONST POp* rec = gops + G.op0;
+            OpS<double> A = load_op_c<double>(rec);
+            for (int oi = 0; oi < G.nops; oi += 2) {
+                __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), as in the forward kernel
+                __builtin_amdgcn_sched_barrier(0);
+                const OpS<double> B = load_op_c<double>(rec + oi + 1);
+                apply(A);
+                if (oi + 1 >= G.nops) break;
+                __builtin_amdgcn_s_waitcnt(0xC07F);
+                __builtin_amdgcn_sched_barrier(0);
+                A = load_op_c<double>(rec + oi + 2);
+                apply(B);
             }
 #pragma unroll
             for (int r = 0; r < N; ++r) {
@@ -1031,7 +1061,8 @@ __global__ __launch_bounds__(512) void k_pass_bwd(PassArgs a)
         }
         __syncthreads();
         if (nslot > 0) {
-            group_reduce(a.gpartial, a.B, a.pstride, c, red, a.groups[gi].slots, nslot, E, nthr, th);
+            const int* slots = a.groups[gi].slots;
+            reduce_partials(a.gpartial, a.B, a.pstride, c, red, [&](int s) { return slots[s]; }, nslot, E, nthr, th);
             buf ^= 1;
         }
     }
@@ -1214,8 +1245,11 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
     a.ntiles = 1 << a.nnt;
     a.pstride = pstride > a.ntiles ? pstride : a.ntiles;
     const int Bc = 1 << c;
+    const int RBk = bwd ? kRegBitsBwd : kRegBitsFwd;
+    // The kernels are compiled for at most 512 threads per block (one tile, 2^(t - RB) threads).
+    if (t - RBk < 0 || t - RBk > 9) return set_error(YAO_EINVAL, "tile of 2^%d does not fit 1 .. 512 threads", t);
     dim3 grid(a.ntiles, (B + Bc - 1) / Bc);
-    dim3 block(1 << (t - (bwd ? kRegBitsBwd : kRegBitsFwd)));
+    dim3 block(1 << (t - RBk));
     const int pb = bwd ? 16 : (psi_dtype == YAO_C64 ? 8 : 16);
     const int lb = bwd ? (lam_dtype == YAO_C64 ? 8 : 16) : 0;
     const size_t lds = pass_lds_bytes(bwd, t, c, pb, lb, bwd ? 0 : dm_words);
