@@ -28,6 +28,15 @@ namespace {
 
 constexpr int kBanks = 4;  // streams of the graph
 
+// Circuits are recorded in phases by state size, each phase waiting for the previous one on
+// every stream: a pass over a tile takes about as long whatever the state size, so a small
+// circuit's one-tile passes running beside a large circuit's passes (hundreds of tiles) hold
+// CUs that the large pass waits for. Phases: >= 2^19 amplitudes, 2^16 .. 2^18, smaller.
+int batch_phase(int n)
+{
+    return n >= 19 ? 0 : (n >= 16 ? 1 : 2);
+}
+
 struct Tune {
     int width = 0;  // fusion width of the forward sweep (0: none)
     int tq_f = 0;   // tile qubits of the forward passes (0: default)
@@ -52,6 +61,7 @@ struct Item {
     size_t poff = 0;                   // the circuit's parameters in the device parameter block
     size_t off_f = 0, off_b = 0, bytes_f = 0, bytes_b = 0;  // program blobs
     int bank = 0;
+    int phase = 0;  // recording phase by state size (see record)
     int nslots = 0;
     int W = 0;                    // partial-sum row stride of the reverse passes
     size_t out_e = 0, out_g = 0;  // positions in the output block
@@ -328,6 +338,7 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
         YAO_TRY(pauli_upload(it.h));
         it.nslots = count_param_slots(it.c);
         it.cost = (double)(it.c->gates.size() + 1) * (double)(uint64_t(1) << n);
+        it.phase = batch_phase(n);
     }
     // Tuning per qubit count, on the deepest circuit of that count.
     std::map<std::pair<int, int>, int> rep;
@@ -356,12 +367,19 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
     YAO_TRY(build_programs(C, params, true));
     for (Item& it : C.items) it.W = reverse_stride(it.s->n, it.s->dtype, it.tune.tq_b);
 
-    // Largest circuits first, each on the least loaded stream.
-    std::stable_sort(C.items.begin(), C.items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    // By phase, then largest circuits first, each on the least loaded stream of its phase.
+    std::stable_sort(C.items.begin(), C.items.end(), [](const Item& a, const Item& b) {
+        return a.phase != b.phase ? a.phase < b.phase : a.cost > b.cost;
+    });
     double load[kBanks] = {};
+    int cur_phase = -1;
     size_t psi_b[kBanks] = {}, lam_b[kBanks] = {}, gp_b[kBanks] = {}, hp_b[kBanks] = {};
     size_t nout = 0, off = 0;
     for (Item& it : C.items) {
+        if (it.phase != cur_phase) {
+            cur_phase = it.phase;
+            for (double& l : load) l = 0;
+        }
         int best = 0;
         for (int b = 1; b < kBanks; ++b)
             if (load[b] < load[best]) best = b;
@@ -434,8 +452,20 @@ int record(Cache& C)
         for (int b = 0; b < kBanks && !rc; ++b)
             if (hipStreamWaitEvent(g_bank[b], g_fork, 0) != hipSuccess) rc = set_error(YAO_EHIP, "fork wait");
         if (rc) break;
+        int phase = C.items.empty() ? 0 : C.items.front().phase;
         for (Item& it : C.items) {
             const int n = it.s->n, dt = it.s->dtype, bk = it.bank;
+            if (it.phase != phase) {
+                // Every stream finishes the previous phase before any starts this one.
+                phase = it.phase;
+                for (int b = 0; b < kBanks && !rc; ++b)
+                    if (hipEventRecord(g_join[b], g_bank[b]) != hipSuccess || hipStreamWaitEvent(cs, g_join[b], 0) != hipSuccess)
+                        rc = set_error(YAO_EHIP, "phase join");
+                if (!rc && hipEventRecord(g_fork, cs) != hipSuccess) rc = set_error(YAO_EHIP, "phase fork record");
+                for (int b = 0; b < kBanks && !rc; ++b)
+                    if (hipStreamWaitEvent(g_bank[b], g_fork, 0) != hipSuccess) rc = set_error(YAO_EHIP, "phase fork wait");
+                if (rc) break;
+            }
             set_stream(g_bank[bk]);
             if ((rc = launch_fill_basis(it.s->data, dt, n, 1))) break;
             if (it.bf && (rc = bind_program(it.bf, C.d_params + it.poff))) break;
