@@ -62,6 +62,7 @@ struct Item {
     size_t off_f = 0, off_b = 0, bytes_f = 0, bytes_b = 0;  // program blobs
     int bank = 0;
     int phase = 0;  // recording phase by state size (see record)
+    bool small = false;  // run start to end by one workgroup (k_small_circuit)
     int nslots = 0;
     int W = 0;                    // partial-sum row stride of the reverse passes
     size_t out_e = 0, out_g = 0;  // positions in the output block
@@ -90,6 +91,15 @@ struct Cache {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double algo_bytes = 0, algo_flops = 0;
+    // Circuits run by k_small_circuit: their descriptors by qubit count (one launch per count)
+    // and the bind jobs of their programs (one launch for all).
+    SmallCircuit* d_small = nullptr;
+    struct SmallLaunch {
+        int n, first, count;
+    };
+    std::vector<SmallLaunch> small_launches;
+    BindJob* d_jobs = nullptr;
+    int njobs = 0, max_nb = 0;
 };
 
 Cache* g_cache = nullptr;
@@ -107,6 +117,8 @@ void free_cache(Cache* c)
     if (c->d_out) (void)hipFree(c->d_out);
     if (c->h_out) (void)hipHostFree(c->h_out);
     if (c->d_params) (void)hipFree(c->d_params);
+    if (c->d_small) (void)hipFree(c->d_small);
+    if (c->d_jobs) (void)hipFree(c->d_jobs);
     if (c->h_params) (void)hipHostFree(c->h_params);
     for (int b = 0; b < kBanks; ++b) {
         if (c->psi64[b]) (void)hipFree(c->psi64[b]);
@@ -257,6 +269,7 @@ int build_programs(Cache& C, const double* const* params, bool first)
     // only in its first item and takes host-built programs in the others.
     std::set<const BoundProgram*> used;
     for (Item& it : C.items) {
+        if (it.small) continue;  // programs bound at cache build
         const double* p = params[it.idx];
         const int dt = it.s->dtype;
         if (first) {
@@ -340,9 +353,43 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
         it.cost = (double)(it.c->gates.size() + 1) * (double)(uint64_t(1) << n);
         it.phase = batch_phase(n);
     }
+    // Circuits whose whole state fits one tile run start to end in one workgroup, from
+    // programs of one pass each (3 register bits, FP64 matrices) bound on the device; a
+    // circuit with a gate wider than an LDS op, or whose programs cannot be bound there (or are
+    // already bound for an earlier entry of the same circuit), takes the pass path.
+    {
+        std::set<const BoundProgram*> used;
+        for (Item& it : C.items) {
+            const int n = it.s->n;
+            if (n < 5 || n > kSmallMaxQubits) continue;
+            bool narrow = true;
+            for (const GateRec& g : it.c->gates) narrow &= g.k <= kMaxFusedK;
+            const int G = (int)it.c->gates.size();
+            if (!narrow || G == 0) continue;
+            const Plan& pf = get_plan_ex(it.c, 0, G, 1, n, 0, 0, false, 3, 1 << 30);
+            const Plan& pr = get_plan_ex(it.c, 0, G, 1, n, 0, 0, true, 3, 1 << 30);
+            if (pf.passes.size() != 1 || pr.passes.size() != 1 || pf.passes[0].standalone >= 0 ||
+                pr.passes[0].standalone >= 0)
+                continue;
+            const BoundProgram* bf = bound_program(pf, it.c, false, YAO_C128, nullptr, nullptr);
+            const BoundProgram* bb = bound_program(pr, it.c, true, YAO_C128, nullptr, nullptr);
+            if (!bf || !bb || used.count(bf) || used.count(bb)) continue;
+            used.insert(bf);
+            used.insert(bb);
+            it.small = true;
+            it.phase = -1;
+            it.fwd = &pf;
+            it.bwd = &pr;
+            it.bf = bf;
+            it.bb = bb;
+            it.fc = it.c;
+            it.fc_version = it.c->version;
+        }
+    }
     // Tuning per qubit count, on the deepest circuit of that count.
     std::map<std::pair<int, int>, int> rep;
     for (int i = 0; i < ncirc; ++i) {
+        if (C.items[i].small) continue;
         auto k = std::make_pair(C.items[i].s->n, C.items[i].s->dtype);
         auto r = rep.find(k);
         if (r == rep.end() || C.items[r->second].c->gates.size() < C.items[i].c->gates.size()) rep[k] = i;
@@ -362,10 +409,11 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
             }
         }
         for (Item& it : C.items)
-            if (it.s->n == kv.first.first && it.s->dtype == kv.first.second) it.tune = t;
+            if (!it.small && it.s->n == kv.first.first && it.s->dtype == kv.first.second) it.tune = t;
     }
     YAO_TRY(build_programs(C, params, true));
-    for (Item& it : C.items) it.W = reverse_stride(it.s->n, it.s->dtype, it.tune.tq_b);
+    for (Item& it : C.items)
+        if (!it.small) it.W = reverse_stride(it.s->n, it.s->dtype, it.tune.tq_b);
 
     // By phase, then largest circuits first, each on the least loaded stream of its phase.
     std::stable_sort(C.items.begin(), C.items.end(), [](const Item& a, const Item& b) {
@@ -376,6 +424,11 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
     size_t psi_b[kBanks] = {}, lam_b[kBanks] = {}, gp_b[kBanks] = {}, hp_b[kBanks] = {};
     size_t nout = 0, off = 0;
     for (Item& it : C.items) {
+        if (it.small) {
+            it.out_e = nout++;
+            it.off_f = it.off_b = off;
+            continue;
+        }
         if (it.phase != cur_phase) {
             cur_phase = it.phase;
             for (double& l : load) l = 0;
@@ -418,6 +471,54 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
         YAO_TRY(dev_alloc((void**)&C.hpart[b], hp_b[b]));
     }
     pack_all(C);
+    // Descriptors and bind jobs of the small circuits, by qubit count.
+    {
+        std::vector<const Item*> sm;
+        for (const Item& it : C.items)
+            if (it.small) sm.push_back(&it);
+        std::stable_sort(sm.begin(), sm.end(), [](const Item* a, const Item* b) { return a->s->n < b->s->n; });
+        std::vector<SmallCircuit> hs;
+        std::vector<BindJob> jobs;
+        for (const Item* it : sm) {
+            SmallCircuit x;
+            memset(&x, 0, sizeof(x));
+            x.fops = it->bf->d.ops;
+            x.fgroups = it->bf->d.groups;
+            x.fmats = it->bf->d.mats;
+            x.nfg = (int)it->fwd->passes[0].groups.size();
+            x.rops = it->bb->d.ops;
+            x.rgroups = it->bb->d.groups;
+            x.rmats = it->bb->d.mats;
+            x.nrg = (int)it->bwd->passes[0].groups.size();
+            x.hgroups = (const PGroup*)it->h->d_groups;
+            x.hterms = (const PTerm*)it->h->d_terms;
+            x.nhg = it->h->ngroups;
+            x.state = it->s->data;
+            x.energy = C.d_out + it->out_e;
+            x.grad = C.d_out + it->out_g;
+            x.n = it->s->n;
+            x.c64 = it->s->dtype == YAO_C64 ? 1 : 0;
+            if (C.small_launches.empty() || C.small_launches.back().n != x.n)
+                C.small_launches.push_back(Cache::SmallLaunch{x.n, (int)hs.size(), 0});
+            C.small_launches.back().count++;
+            hs.push_back(x);
+            for (const BoundProgram* b : {it->bf, it->bb}) {
+                const int nb = (int)b->prog.binds.size();
+                if (nb == 0) continue;
+                jobs.push_back(BindJob{b->d.ops, b->dbinds, b->dfacs, C.d_params + it->poff, nb, 0});
+                C.max_nb = std::max(C.max_nb, nb);
+            }
+        }
+        if (!hs.empty()) {
+            YAO_TRY(dev_alloc((void**)&C.d_small, sizeof(SmallCircuit) * hs.size()));
+            YAO_HIP(hipMemcpy(C.d_small, hs.data(), sizeof(SmallCircuit) * hs.size(), hipMemcpyHostToDevice));
+        }
+        if (!jobs.empty()) {
+            YAO_TRY(dev_alloc((void**)&C.d_jobs, sizeof(BindJob) * jobs.size()));
+            YAO_HIP(hipMemcpy(C.d_jobs, jobs.data(), sizeof(BindJob) * jobs.size(), hipMemcpyHostToDevice));
+        }
+        C.njobs = (int)jobs.size();
+    }
     // Algorithmic traffic and flops of one replay (every pass reads and writes its states once).
     for (const Item& it : C.items) {
         const double N = (double)(uint64_t(1) << it.s->n);
@@ -452,8 +553,15 @@ int record(Cache& C)
         for (int b = 0; b < kBanks && !rc; ++b)
             if (hipStreamWaitEvent(g_bank[b], g_fork, 0) != hipSuccess) rc = set_error(YAO_EHIP, "fork wait");
         if (rc) break;
-        int phase = C.items.empty() ? 0 : C.items.front().phase;
+        // The small circuits first, alone: one bind launch and one launch per qubit count.
+        set_stream(cs);
+        if ((rc = launch_bind_jobs(C.d_jobs, C.njobs, C.max_nb))) break;
+        for (const Cache::SmallLaunch& l : C.small_launches)
+            if ((rc = launch_small_circuits(C.d_small + l.first, l.count, l.n))) break;
+        if (rc) break;
+        int phase = -1;
         for (Item& it : C.items) {
+            if (it.small) continue;
             const int n = it.s->n, dt = it.s->dtype, bk = it.bank;
             if (it.phase != phase) {
                 // Every stream finishes the previous phase before any starts this one.

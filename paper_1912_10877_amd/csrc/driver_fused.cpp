@@ -18,18 +18,23 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
                 const double* dmats, int dm_words);
 int launch_fill(double* p, size_t count, double v);
 
-using PlanKey = std::tuple<const yao_circuit*, uint64_t, int, int, int, int, int, int, bool>;
+using PlanKey = std::tuple<const yao_circuit*, uint64_t, int, int, int, int, int, int, bool, int, int>;
 static std::map<PlanKey, Plan> g_plans;
 static std::mutex g_plan_mu;
 
-const Plan& get_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse)
+const Plan& get_plan_ex(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse, int reg_bits,
+                        int max_ops)
 {
     std::lock_guard<std::mutex> lk(g_plan_mu);
-    PlanKey key{c, c->version, g0, g1, B, t, cb, L, reverse};
+    PlanKey key{c, c->version, g0, g1, B, t, cb, L, reverse, reg_bits, max_ops};
     auto it = g_plans.find(key);
     if (it != g_plans.end()) return it->second;
-    return g_plans.emplace(key, make_plan(c, g0, g1, B, t, cb, L, reverse, reverse ? kRegBitsBwd : kRegBitsFwd))
-        .first->second;
+    return g_plans.emplace(key, make_plan(c, g0, g1, B, t, cb, L, reverse, reg_bits, max_ops)).first->second;
+}
+
+const Plan& get_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse)
+{
+    return get_plan_ex(c, g0, g1, B, t, cb, L, reverse, reverse ? kRegBitsBwd : kRegBitsFwd, kMaxPassOps);
 }
 
 int op_type_of(const HostMat& U)

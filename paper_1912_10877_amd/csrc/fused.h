@@ -100,8 +100,9 @@ struct Plan {
 
 // Build the pass structure of gates [g0, g1); taken in circuit order, or reversed for the
 // backward.
+// max_ops: at most that many ops per pass.
 Plan make_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cbits, int low_fixed, bool reverse,
-               int reg_bits);
+               int reg_bits, int max_ops = kMaxPassOps);
 // Choose tile geometry for a state (tile qubits from the options, 0 = default).
 void tile_geometry(int n, int B, int dtype, bool backward, int* t, int* cbits, int* low_fixed);
 // The same for an explicit number of tile qubits (<= 0: default).
@@ -145,6 +146,9 @@ struct DevProgram {
     double* mats;
 };
 const Plan& get_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse);
+// A plan with the given register bits and pass size (cached like get_plan's).
+const Plan& get_plan_ex(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse, int reg_bits,
+                        int max_ops);
 // dtype: the state's (forward) or the adjoint state's (backward) precision. With params null
 // the program is built for binding on the device (Program::binds); when c is the structure of a
 // fused circuit (fused_shape), parts and orig describe its multi-gate placeholders.
@@ -170,6 +174,39 @@ int forward_fused(void* data, int dtype, int n, int B, const yao_circuit* c, con
 int forward_sweep(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params, int width, int tq,
                   const double* dparams);
 // Device-bound programs (built once per plan; see BindRec).
+// One circuit of a batch whose whole state fits one tile, run start to end by one workgroup
+// (k_small_circuit): forward program, then H psi and the energy, then the reverse program
+// with its gradients. Both programs are one pass over the tile holding qubits 0 .. n-1 in
+// order, with 3 register bits and FP64 matrices.
+struct SmallCircuit {
+    const POp* fops;
+    const PGroupDesc* fgroups;
+    const double* fmats;
+    const POp* rops;
+    const PGroupDesc* rgroups;
+    const double* rmats;
+    const PGroup* hgroups;
+    const PTerm* hterms;
+    void* state;     // psi_N is written here (complex64 or complex128)
+    double* energy;  // <psi_N|H|psi_N>
+    double* grad;    // one value per gradient slot of the reverse program
+    int nfg, nrg, nhg, n;
+    int c64;         // state precision: 1 complex64, 0 complex128
+    int pad[3];
+};
+// One program to bind (k_bind over its records) in a launch that binds many.
+struct BindJob {
+    POp* ops;
+    const BindRec* binds;
+    const BindFac* facs;
+    const double* params;
+    int nb, pad;
+};
+int launch_bind_jobs(const BindJob* jobs, int njobs, int max_nb);
+// count circuits of n qubits each, one workgroup apiece.
+int launch_small_circuits(const SmallCircuit* items, int count, int n);
+constexpr int kSmallMaxQubits = 12;  // psi and lambda in FP64: 32 B x 2^12 = 128 KiB of LDS
+
 struct BoundProgram {
     const yao_circuit* circ = nullptr;
     Program prog;

@@ -539,28 +539,28 @@ __device__ __forceinline__ double row_sum(double v, int c)
 }
 
 // Reduce partials red[s * E + e] for gradient s < S (entry e holds batch slot e mod 2^c) to
-// one value per (gradient, batch slot of the tile) and store it in gpartial at the slot
-// slot_of(s). The order of the sums is fixed.
+// one value per (gradient, batch slot b0 + j of the tile) and store it in gpartial at
+// ((slot_of(s) * B + b0 + j) * pstride + col). The order of the sums is fixed.
 template <typename SlotOf>
 __device__ __forceinline__ void reduce_partials(double* __restrict__ gpartial, int B, int pstride, int c,
-                                                const double* red, SlotOf slot_of, int S, int E, int nthr, int th)
+                                                const double* red, SlotOf slot_of, int S, int E, int nthr, int th,
+                                                int col, int b0)
 {
     const int Bc = 1 << c;
-    const int b0 = blockIdx.y << c;
     if (nthr >= 16) {
         for (int task = th; task < S * 16; task += nthr) {
             const int s = task >> 4, j = task & 15;
             double v = 0;
             for (int e = j; e < E; e += 16) v += red[s * E + e];
             for (int off = 8; off >= Bc; off >>= 1) v += __shfl_xor(v, off, 16);
-            if (j < Bc && b0 + j < B) gpartial[((uint64_t)slot_of(s) * B + b0 + j) * pstride + blockIdx.x] = v;
+            if (j < Bc && b0 + j < B) gpartial[((uint64_t)slot_of(s) * B + b0 + j) * pstride + col] = v;
         }
     } else {
         for (int task = th; task < S * Bc; task += nthr) {
             const int s = task / Bc, bb = task % Bc;
             double v = 0;
             for (int e = bb; e < E; e += Bc) v += red[s * E + e];
-            if (b0 + bb < B) gpartial[((uint64_t)slot_of(s) * B + b0 + bb) * pstride + blockIdx.x] = v;
+            if (b0 + bb < B) gpartial[((uint64_t)slot_of(s) * B + b0 + bb) * pstride + col] = v;
         }
     }
 }
@@ -918,53 +918,32 @@ __host__ __device__ __forceinline__ int grad_entries(int nthr, int c)
     return nthr >= 16 ? (nthr >> 4) << c : nthr;
 }
 
-// C0: tiles of one batch slot (c = 0), where every row-sum step applies. At most 168 VGPRs, so
-// that three 256-thread tiles of 2^11 elements (48 KiB of LDS each) fit on one CU.
+// Where the gradient partials of a reverse sweep go: reduce_partials' gpartial, B, pstride
+// and, for this tile, the column and the first batch slot.
+struct GradOut {
+    double* gpartial;
+    int B, pstride, col, b0;
+};
+
+// The register groups and LDS ops of a reverse pass over the tile in LDS: psi (lp, FP64) and
+// lambda (ll, in RL), with every gradient partial reduced per group into go. tbase holds the
+// qubits outside the tile (for controls there); red0 holds two buffers of kMaxGroupSlots * E
+// partials (a group's partials are reduced after the barrier that ends it, while the next
+// group fills the other buffer). C0: tiles of one batch slot (c = 0).
 template <typename RL, bool C0>
-__global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
+__device__ __forceinline__ void reverse_groups(double2* lp, vec2_t<RL>* ll, double* red0, const YAO_CONST POp* gops,
+                                               const YAO_CONST PGroupDesc* ggrp, const PGroupDesc* groups,
+                                               int ngroups, const double* mats, uint64_t tbase, int t, int c,
+                                               int nthr, int th, const GradOut& go)
 {
     constexpr int RB = kRegBitsBwd, N = 1 << RB;
     using VL = vec2_t<RL>;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int t = a.t;
-    const int nthr = 1 << (t - RB);
-    const int th = threadIdx.x;
-    const int c = C0 ? 0 : a.c;
     const bool rows = nthr >= 16;
     const int E = grad_entries(nthr, c);
-    // LDS: psi | lambda | gradient partials, two buffers of kMaxGroupSlots * E (a group's
-    // partials are reduced after the barrier that ends it, while the next group fills the other
-    // buffer).
-    double2* lp = (double2*)smem;
-    VL* ll = (VL*)(smem + ((size_t)16 << t));
-    double* red0 = (double*)(smem + ((size_t)(16 + sizeof(VL)) << t));
     const int ent = rows ? (th >> 4) * (1 << c) + (th & 15) : th;
     const bool stores = rows ? (th & 15) < (1 << c) : true;
-    const YAO_CONST POp* gops = cptr(a.ops);
-    const YAO_CONST PGroupDesc* ggrp = cptr(a.groups);
-    const TileCtx tc = tile_ctx<RB>(a, th);
-    double2* gp = (double2*)a.psi;
-    VL* gl = (VL*)a.lam;
-    {
-        double2 v[N];
-        VL w[N];
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            const uint64_t off = tile_off<RB>(a, tc, r);
-            v[r] = gp[off];
-            w[r] = gl[off];
-        }
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            const uint32_t e = swz((uint32_t)th + (uint32_t)r * nthr);
-            lp[e] = v[r];
-            ll[e] = w[r];
-        }
-    }
-    __syncthreads();
-
     int buf = 0;
-    for (int gi = 0; gi < a.ngroups; ++gi) {
+    for (int gi = 0; gi < ngroups; ++gi) {
         const GroupCtl G = group_ctl_c(ggrp + gi);
         double* red = red0 + buf * (kMaxGroupSlots * E);
         int nslot = 0;
@@ -972,8 +951,8 @@ __global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
             const YAO_CONST POp* rec = gops + G.op0;
             const uint64_t omask = rec->omask, oval = rec->oval;
             double g = 0;
-            if ((tc.base & omask) == oval) {
-                const double* m = a.mats + rec->mat;
+            if ((tbase & omask) == oval) {
+                const double* m = mats + rec->mat;
                 if (rec->k == 2) g = lds_op_bwd<RL, 2>(lp, ll, rec, m, t, th, nthr);
                 else g = lds_op_bwd<RL, 3>(lp, ll, rec, m, t, th, nthr);
             }
@@ -1001,8 +980,8 @@ __global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
 #define YAO_BWD_CASE(J)                                                                                 \
     case J: {                                                                                           \
         OpCtl op = o.c;                                                                                 \
-        fold_outer_controls(op, tc.base);                                                               \
-        const double* gm = a.mats + op.mat + 8; /* M of a dense generator */                           \
+        fold_outer_controls(op, tbase);                                                                 \
+        const double* gm = mats + op.mat + 8; /* M of a dense generator */                             \
         if (op.slot >= 0) {                                                                             \
             if (op.cmask) g = op_grad<J, true>(x, y, op.gen, gm, gm + 4, ethr, er, op.cmask, op.cval);  \
             else g = op_grad<J, false>(x, y, op.gen, gm, gm + 4, ethr, er, 0u, 0u);                     \
@@ -1061,11 +1040,54 @@ __global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
         }
         __syncthreads();
         if (nslot > 0) {
-            const int* slots = a.groups[gi].slots;
-            reduce_partials(a.gpartial, a.B, a.pstride, c, red, [&](int s) { return slots[s]; }, nslot, E, nthr, th);
+            const int* slots = groups[gi].slots;
+            reduce_partials(go.gpartial, go.B, go.pstride, c, red, [&](int s) { return slots[s]; }, nslot, E, nthr,
+                            th, go.col, go.b0);
             buf ^= 1;
         }
     }
+}
+
+// C0: tiles of one batch slot (c = 0), where every row-sum step applies. At most 168 VGPRs, so
+// that three 256-thread tiles of 2^11 elements (48 KiB of LDS each) fit on one CU.
+template <typename RL, bool C0>
+__global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
+{
+    constexpr int RB = kRegBitsBwd, N = 1 << RB;
+    using VL = vec2_t<RL>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int t = a.t;
+    const int nthr = 1 << (t - RB);
+    const int th = threadIdx.x;
+    const int c = C0 ? 0 : a.c;
+    // LDS: psi | lambda | gradient partials.
+    double2* lp = (double2*)smem;
+    VL* ll = (VL*)(smem + ((size_t)16 << t));
+    double* red0 = (double*)(smem + ((size_t)(16 + sizeof(VL)) << t));
+    const TileCtx tc = tile_ctx<RB>(a, th);
+    double2* gp = (double2*)a.psi;
+    VL* gl = (VL*)a.lam;
+    {
+        double2 v[N];
+        VL w[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            const uint64_t off = tile_off<RB>(a, tc, r);
+            v[r] = gp[off];
+            w[r] = gl[off];
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            const uint32_t e = swz((uint32_t)th + (uint32_t)r * nthr);
+            lp[e] = v[r];
+            ll[e] = w[r];
+        }
+    }
+    __syncthreads();
+
+    const GradOut go{a.gpartial, a.B, a.pstride, (int)blockIdx.x, (int)blockIdx.y << c};
+    reverse_groups<RL, C0>(lp, ll, red0, cptr(a.ops), cptr(a.groups), a.groups, a.ngroups, a.mats, tc.base, t, c,
+                           nthr, th, go);
 
     if (tc.bvalid) {
 #pragma unroll
@@ -1076,6 +1098,142 @@ __global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
             gl[off] = ll[e];
         }
     }
+}
+
+// ------------------------------------------------------------------------------ small circuits
+// The register groups and LDS ops of a forward pass with 3 register bits and FP64 matrices
+// over a tile in LDS that holds every qubit (no controls outside it, no dense blocks).
+__device__ __forceinline__ void forward_groups3(double2* lp, const YAO_CONST POp* gops,
+                                                const YAO_CONST PGroupDesc* ggrp, int ngroups, const double* mats,
+                                                int t, int nthr, int th)
+{
+    constexpr int RB = 3, N = 1 << RB;
+    for (int gi = 0; gi < ngroups; ++gi) {
+        const GroupCtl G = group_ctl_c(ggrp + gi);
+        if (G.lds) {
+            const YAO_CONST POp* rec = gops + G.op0;
+            const double* m = mats + rec->mat;
+            if (rec->k == 2) lds_op_fwd<double, 2>(lp, rec, m, t, th, nthr);
+            else lds_op_fwd<double, 3>(lp, rec, m, t, th, nthr);
+            __syncthreads();
+            continue;
+        }
+        uint32_t ethr, er[N];
+        group_index<RB>(G.rpos, t, th, ethr, er);
+        double2 x[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) x[r] = lp[swz(ethr | er[r])];
+        // The forward classes of op_variant on 3 register bits (see the forward kernel).
+        auto apply = [&](const OpS<double>& o) __attribute__((always_inline)) {
+            const double* mr = o.m;
+            const double* mi = o.m + 4;
+#define YAO_SF_CASE(J) \
+    case J: pairs_dense_ctl_ip<J>(x, mr, mi, ethr, er, o.c.cmask, o.c.cval); break;
+#define YAO_SF_FAST(J)                                                               \
+    case 0 * RB + J: pairs_ip<J, OT_RX>(x, mr, mi); break;                           \
+    case 1 * RB + J: pairs_ip<J, OT_DIAG>(x, mr, mi); break;                         \
+    case 2 * RB + J: pairs_ip<J, OT_DENSE>(x, mr, mi); break;                        \
+    case 3 * RB + J: pairs_cswap_ip<J>(x, ethr, er, o.c.cmask, o.c.cval); break;
+            switch (o.c.var) {
+                YAO_SF_FAST(0) YAO_SF_FAST(1) YAO_SF_FAST(2)
+            default:
+                switch (o.c.rpos) { YAO_SF_CASE(0) YAO_SF_CASE(1) default: YAO_SF_CASE(2) }
+                break;
+            }
+#undef YAO_SF_FAST
+#undef YAO_SF_CASE
+        };
+        const YAO_CONST POp* rec = gops + G.op0;
+        OpS<double> A = load_op_c<double>(rec);
+        for (int oi = 0; oi < G.nops; oi += 2) {
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), as in the forward kernel
+            __builtin_amdgcn_sched_barrier(0);
+            const OpS<double> B = load_op_c<double>(rec + oi + 1);
+            apply(A);
+            if (oi + 1 >= G.nops) break;
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            __builtin_amdgcn_sched_barrier(0);
+            A = load_op_c<double>(rec + oi + 2);
+            apply(B);
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) lp[swz(ethr | er[r])] = x[r];
+        __syncthreads();
+    }
+}
+
+// One workgroup per circuit of a batch whose state fits one tile (eq. apply-back and the
+// outer-product gradient as in the reverse passes, all in LDS): psi = |0..0>, the forward
+// program, psi_N to the state, lambda = H psi and the energy, then the reverse program with
+// its gradients. LDS: psi (FP64) | lambda (FP64) | gradient partials.
+__global__ __launch_bounds__(512, 1) void k_small_circuit(const SmallCircuit* items)
+{
+    constexpr int RB = 3, N = 1 << RB;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const YAO_CONST SmallCircuit* it = cptr(items) + blockIdx.x;
+    const int t = it->n;
+    const int nthr = 1 << (t - RB);
+    const int th = threadIdx.x;
+    double2* lp = (double2*)smem;
+    double2* ll = lp + (size_t(1) << t);
+    double* red0 = (double*)(ll + (size_t(1) << t));
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        const uint32_t e = (uint32_t)th + (uint32_t)r * nthr;
+        lp[swz(e)] = make_double2(e == 0 ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    forward_groups3(lp, cptr(it->fops), cptr(it->fgroups), it->nfg, it->fmats, t, nthr, th);
+
+    // Tile element e is basis state e (the tile holds qubits 0 .. n-1 in order).
+    const YAO_CONST PGroup* hg = cptr(it->hgroups);
+    const YAO_CONST PTerm* ht = cptr(it->hterms);
+    const int nhg = it->nhg;
+    const bool c64 = it->c64 != 0;
+    double acc = 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        const uint32_t e = (uint32_t)th + (uint32_t)r * nthr;
+        const double2 a = lp[swz(e)];
+        if (c64) ((float2*)it->state)[e] = make_float2((float)a.x, (float)a.y);
+        else ((double2*)it->state)[e] = a;
+        double orr = 0, oi = 0;
+        for (int g = 0; g < nhg; ++g) {
+            const uint32_t src = e ^ (uint32_t)hg[g].x;
+            const double2 p = lp[swz(src)];
+            double cr = 0, ci = 0;  // sum of c i^ny (-1)^{|src & z|}
+            for (int k = hg[g].t0; k < hg[g].t1; ++k) {
+                const double cc = (__popcll((uint64_t)src & ht[k].z) & 1) ? -ht[k].c : ht[k].c;
+                switch (ht[k].ny & 3) {
+                case 0: cr += cc; break;
+                case 1: ci += cc; break;
+                case 2: cr -= cc; break;
+                default: ci -= cc; break;
+                }
+            }
+            orr += cr * p.x - ci * p.y;
+            oi += cr * p.y + ci * p.x;
+        }
+        ll[swz(e)] = make_double2(orr, oi);
+        acc += a.x * orr + a.y * oi;
+    }
+    red0[th] = acc;
+    __syncthreads();
+    if (th == 0) {
+        double sum = 0;
+        for (int i = 0; i < nthr; ++i) sum += red0[i];
+        *it->energy = sum;
+    }
+    __syncthreads();
+    const GradOut go{it->grad, 1, 1, 0, 0};
+    reverse_groups<double, true>(lp, ll, red0, cptr(it->rops), cptr(it->rgroups), it->rgroups, it->nrg, it->rmats, 0,
+                                 t, 0, nthr, th, go);
+}
+
+size_t small_circuit_lds_bytes(int n)
+{
+    const int nthr = 1 << (n - 3);
+    return ((size_t)32 << n) + sizeof(double) * 2 * kMaxGroupSlots * (size_t)grad_entries(nthr, 0);
 }
 
 // Raise each pass kernel's dynamic LDS limit to the CU's 160 KiB, once per kernel.
@@ -1118,12 +1276,11 @@ __device__ void gate2(int kind, double th, double (&r)[4], double (&i)[4])
 
 // Parameter binding: one thread per bound record multiplies its factors (in application
 // order) and writes the matrix into the record (see BindRec).
-__global__ void k_bind(POp* __restrict__ ops, const BindRec* __restrict__ binds, int nb,
-                       const BindFac* __restrict__ facs, const double* __restrict__ params)
+// The matrix of one bound record: the product of its factors (gate kind and angle), written
+// as U (forward, float or double) or U^dagger (reverse) into the record.
+__device__ void bind_one(POp* __restrict__ ops, const BindRec br, const BindFac* __restrict__ facs,
+                         const double* __restrict__ params)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
-    const BindRec br = binds[b];
     double ar[4] = {1.0, 0.0, 0.0, 1.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
     for (int f = 0; f < br.nf; ++f) {
         const BindFac x = facs[br.f0 + f];
@@ -1168,7 +1325,44 @@ __global__ void k_bind(POp* __restrict__ ops, const BindRec* __restrict__ binds,
     }
 }
 
+__global__ void k_bind(POp* __restrict__ ops, const BindRec* __restrict__ binds, int nb,
+                       const BindFac* __restrict__ facs, const double* __restrict__ params)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    bind_one(ops, binds[b], facs, params);
+}
+
+// Many programs at once: job blockIdx.y, record blockIdx.x * blockDim.x + threadIdx.x.
+__global__ void k_bind_jobs(const BindJob* __restrict__ jobs)
+{
+    const BindJob j = jobs[blockIdx.y];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= j.nb) return;
+    bind_one(j.ops, j.binds[b], j.facs, j.params);
+}
+
 }  // namespace
+
+int launch_bind_jobs(const BindJob* jobs, int njobs, int max_nb)
+{
+    if (njobs <= 0 || max_nb <= 0) return 0;
+    if (njobs > 65535) return set_error(YAO_EINVAL, "%d bind jobs in one launch", njobs);
+    k_bind_jobs<<<dim3((max_nb + 255) / 256, njobs), 256, 0, stream()>>>(jobs);
+    YAO_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_small_circuits(const SmallCircuit* items, int count, int n)
+{
+    if (count <= 0) return 0;
+    if (n < 5 || n > kSmallMaxQubits) return set_error(YAO_EINVAL, "small-circuit kernel takes 5..%d qubits, not %d",
+                                                       kSmallMaxQubits, n);
+    YAO_TRY(set_lds_limit(k_small_circuit));
+    k_small_circuit<<<count, 1 << (n - 3), small_circuit_lds_bytes(n), stream()>>>(items);
+    YAO_HIP(hipGetLastError());
+    return 0;
+}
 
 int launch_bind(POp* ops, const BindRec* binds, int nbinds, const BindFac* facs, const double* params)
 {
@@ -1187,6 +1381,7 @@ int prepare_pass_kernels()
     YAO_TRY(set_lds_limit(k_pass_bwd<float, false>));
     YAO_TRY(set_lds_limit(k_pass_bwd<double, true>));
     YAO_TRY(set_lds_limit(k_pass_bwd<double, false>));
+    YAO_TRY(set_lds_limit(k_small_circuit));
     return 0;
 }
 

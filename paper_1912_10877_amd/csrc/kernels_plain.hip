@@ -128,17 +128,6 @@ __device__ __forceinline__ double block_sum_by_slot(double v, int logBc, double*
     return red[threadIdx.x];
 }
 
-struct PGroup {
-    uint64_t x;
-    int t0, t1;
-};
-struct PTerm {
-    double c;
-    uint64_t z;
-    int ny;
-    int pad;
-};
-
 // Value of Re(i^ny * w) for w = wr + i wi.
 __device__ __forceinline__ double re_iny(int ny, double wr, double wi)
 {

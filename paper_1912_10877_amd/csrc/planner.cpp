@@ -47,7 +47,7 @@ bool fused_supported(int n, int B)
 }
 
 Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits, int low_fixed, bool reverse,
-               int reg_bits)
+               int reg_bits, int max_ops)
 {
     Plan P;
     P.reg_bits = reg_bits;
@@ -73,7 +73,7 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
     const uint64_t low = low_fixed > 0 ? ((uint64_t(1) << low_fixed) - 1) : 0;
     // Widest gate a pass takes: forward passes over tiles of >= 64 register-group columns apply
     // k <= 4 gates as dense blocks on a register group; other passes apply k <= 3 gates in LDS.
-    const bool dense_ok = !reverse && t - reg_bits >= 6;
+    const bool dense_ok = !reverse && t - reg_bits >= 6 && reg_bits >= kMaxDenseK;
     const int maxk = dense_ok ? kMaxDenseK : kMaxFusedK;
     std::vector<int> remaining(P.ops.size());
     for (size_t e = 0; e < remaining.size(); ++e) remaining[e] = (int)e;
@@ -97,7 +97,7 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
             const HostOp& op = P.ops[oi];
             const int k = circ->gates[op.gate].k;
             const bool dense = dense_ok && k > 1;
-            if ((op.qmask & blocked) || k > maxk || (int)sel.size() >= kMaxPassOps ||
+            if ((op.qmask & blocked) || k > maxk || (int)sel.size() >= max_ops ||
                 (dense && ndense >= kMaxPassDense)) {
                 blocked |= op.qmask;
                 rest.push_back(oi);

@@ -130,6 +130,18 @@ int launch_adjoint_step_strided(double* psi, void* lam, int lam_dtype, int n, in
 int launch_row_sums(const double* partial, int rows, int nblk, double* sums);
 
 // Pauli tables
+// Device tables of a Pauli sum (pauli_upload): terms grouped by X mask x. Term t of a group
+// adds c_t i^{ny} (-1)^{|(j ^ x) & z|} psi[j ^ x] to (H psi)[j].
+struct PGroup {
+    uint64_t x;
+    int t0, t1;
+};
+struct PTerm {
+    double c;
+    uint64_t z;
+    int ny;
+    int pad;
+};
 int pauli_upload(yao_pauli_sum* h);
 
 // Dense 4/5-qubit gates on complex64 states through the FP32 matrix cores.

@@ -52,6 +52,9 @@ def check(e, g, params, refs, dtype, which=None):
         c, H = refs[i]
         e_ref, g_ref, _ = oracle.adjoint(H, c, params[i], w.zero_state(c.n))
         assert abs(e[i] - e_ref[0]) <= te, (i, c.n, e[i], e_ref[0])
+        assert len(g[i]) == c.nparams
+        if c.nparams == 0:
+            continue
         scale = max(1.0, float(np.abs(g_ref[0]).max()))
         err = float(np.abs(g[i] - g_ref[0]).max())
         assert err <= tg * scale, (i, c.n, err)
@@ -85,13 +88,60 @@ def test_replays_with_new_parameters_and_eager_work_between():
         assert np.abs(out - ref).max() <= 1e-5
 
 
+def random_pauli_sum(n, nterms, seed):
+    rng = np.random.default_rng(seed)
+    terms = [(float(rng.uniform(-1, 1)), "".join("IXYZ"[int(k)] for k in rng.integers(0, 4, n))) for _ in range(nterms)]
+    return w.pauli_sum(n, terms)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_small_circuits_general_gates(dtype):
+    """Circuits whose state fits one tile run start to end in one workgroup each: random
+    gates of every kind with controls and control values, 2- and 3-qubit dense gates, QFT,
+    Haar-random layers and the paper's ansatz, under Heisenberg and random Pauli sums. Energies,
+    gradients and the output states against the oracle. Circuits with parameterised 2- or
+    3-qubit rotations cannot be bound on the device and take the pass path in the same batch."""
+    circuits = []
+    for i, n in enumerate([5, 6, 7, 8, 9, 10, 11, 12]):
+        circuits.append(w.random_gate_list(n, 40, seed=6100 + i, kmax=3, max_ctrl=2))
+        circuits.append(w.random_gate_list(n, 30, seed=6200 + i, kmax=1, max_ctrl=2))
+    circuits += [w.qft_circuit(7), w.random_circuit(9, 3, seed=61), w.paper_variational_circuit(8, 2),
+                 w.paper_variational_circuit(12, 3), w.ghz_circuit(12)]
+    states, circs, hams, params, refs = [], [], [], [], []
+    for i, c in enumerate(circuits):
+        H = w.heisenberg(c.n) if i % 2 == 0 else random_pauli_sum(c.n, 6, 6300 + i)
+        states.append(yb.State(c.n, 1, dtype))
+        circs.append(yb.Circuit.from_workload(c))
+        hams.append(yb.PauliSum.from_workload(H))
+        params.append(w.angles(6400 + i, c.nparams))
+        refs.append((c, H))
+    for rep in range(2):
+        if rep:
+            params = [w.angles(6500 + i, len(p)) for i, p in enumerate(params)]
+        e, g = yb.batch_run(states, circs, params, hams)
+        check(e, g, params, refs, dtype)
+        for i, (c, _) in enumerate(refs):
+            ref = oracle.forward(c, params[i], w.zero_state(c.n))
+            assert np.abs(states[i].download() - ref).max() <= (1e-5 if dtype == 0 else 1e-11), (i, c.n)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_uneven_batch_pass_path_matches_oracle(dtype):
+    """States of 13..15 qubits span several tiles: the batch records their fused passes."""
+    spec = w.hetero_batch_spec(ncirc=6, seed=9, nmin=13, nmax=15, dmin=1, dmax=3)
+    states, circs, hams, params, refs = make_batch(spec, dtype)
+    e, g = yb.batch_run(states, circs, params, hams)
+    check(e, g, params, refs, dtype)
+
+
 @pytest.mark.parametrize("width,tq", [(2, 6), (3, 0), (4, 7), (5, 0)])
 def test_forced_fusion_width_and_tile(width, tq):
     """Fusion widths 4 and 5 put standalone dense blocks (matrix cores for complex64) into the
-    graph; their matrices come from the uploaded program."""
+    graph; their matrices come from the uploaded program. (States of up to 12 qubits take the
+    one-workgroup path, so most circuits here have more.)"""
     yb.set_options(autotune=0, fuse_width=width, tile_qubits=tq)
     try:
-        spec = [(n, d, 300 + i) for i, (n, d) in enumerate([(6, 2), (9, 3), (10, 2), (13, 2), (8, 4)])]
+        spec = [(n, d, 300 + i) for i, (n, d) in enumerate([(6, 2), (13, 3), (14, 2), (13, 2), (15, 4)])]
         states, circs, hams, params, refs = make_batch(spec, 0)
         e, g = yb.batch_run(states, circs, params, hams)
         check(e, g, params, refs, 0)
