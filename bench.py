@@ -62,6 +62,7 @@ def parse():
     p.add_argument("--cpu-depth", type=int, default=20, help="depth of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-profile", action="store_true")
+    p.add_argument("--no-configs", action="store_true", help="skip the 10q/25q/20q-batch-64/30q figures")
     p.add_argument("--batch-circuits", type=int, default=1024,
                    help="circuits of the uneven batch measured beside the main step (0: skip)")
     p.add_argument("--batch-steps", type=int, default=5)
@@ -120,6 +121,104 @@ def bench_uneven_batch(yb, w, torch, ncirc, steps):
             "fused_loop_ms": fused_loop_ms, "plain_loop_ms": plain_ms,
             "speedup_vs_plain": plain_ms / batch_ms, "speedup_vs_fused_loop": fused_loop_ms / batch_ms,
             "energy_sum": float(np.sum(e))}
+
+
+def bench_configs(yb, w, torch):
+    """The other configurations of the workload table, one figure set each: a 10-qubit
+    fwd+grad latency, the 25-qubit forward (fused sweep and one per-gate launch against the HBM
+    peak), the same-circuit batch of 64 at 20 qubits, and the 30-qubit precision run
+    (complex64 with 5-qubit blocks on the FP32 matrix cores against complex128)."""
+    import numpy as np
+
+    def timed(f, reps):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    out = {}
+    saved = yb.get_options()
+    try:
+        # 10 qubits, depth 5, complex128: fwd + energy + 150 gradients.
+        c = w.hea_circuit(10, 5)
+        cc, H, p = yb.Circuit.from_workload(c), yb.PauliSum.from_workload(w.heisenberg(10)), w.angles(0, c.nparams)
+        s = yb.State(10, 1, yb.C128)
+
+        def c1():
+            s.reset()
+            yb.backward(s, cc, p, H)
+        out["c1_10q_fwd_grad_c128_us"] = round(timed(c1, 50) * 1e3, 1)
+
+        # 25 qubits, depth 20: forward + energy (autotuned fusion), complex64 and complex128;
+        # and one Rx launch of the per-gate form (reads and writes the state once).
+        c = w.hea_circuit(25, 20)
+        cc, H, p = yb.Circuit.from_workload(c), yb.PauliSum.from_workload(w.heisenberg(25)), w.angles(1, c.nparams)
+        for dt, name, sb in ((yb.C64, "c64", 8), (yb.C128, "c128", 16)):
+            s = yb.State(25, 1, dt)
+
+            def c2():
+                s.reset()
+                yb.forward(s, cc, p)
+            ms = timed(c2, 3)
+            e_ms = timed(lambda: yb.expect(s, H), 3)
+            yb.set_options(plain=1)
+            gate_ms = timed(lambda: s.apply_gate("Rx", (12,), theta=0.3), 20)
+            yb.set_options(plain=saved.plain)
+            gbs = 2.0 * sb * (1 << 25) / (gate_ms / 1e3) / 1e9
+            out[f"c2_25q_fwd_{name}_ms"] = round(ms, 2)
+            out[f"c2_25q_energy_{name}_ms"] = round(e_ms, 2)
+            out[f"c2_25q_amplitude_updates_per_s_{name}"] = len(c.gates) * float(1 << 25) / (ms / 1e3)
+            out[f"c2_25q_per_gate_{name}"] = {"us": round(gate_ms * 1e3, 1), "hbm_gbs": round(gbs, 1),
+                                              "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}
+            del s
+
+        # 20 qubits, depth 20, the same circuit on a batch of 64 states (512 MiB complex64).
+        c = w.hea_circuit(20, 20)
+        cc, H, p = yb.Circuit.from_workload(c), yb.PauliSum.from_workload(w.heisenberg(20)), w.angles(2, c.nparams)
+        s = yb.State(20, 64, yb.C64)
+
+        def c3():
+            s.reset()
+            yb.backward(s, cc, p, H)
+        ms = timed(c3, 2)
+        out["c3_20q_b64_fwd_grad_ms"] = round(ms, 2)
+        out["c3_20q_b64_amplitude_updates_per_s"] = 3.0 * len(c.gates) * float(1 << 20) * 64 / (ms / 1e3)
+        del s
+
+        # 30 qubits, depth 24, Haar-random one-qubit layers + CZ pairs: complex64 with 5-qubit
+        # blocks on the FP32 matrix cores against complex128 (one-qubit runs merged).
+        c = w.random_circuit(30, 24, seed=5)
+        cc = yb.Circuit.from_workload(c)
+        zz = yb.PauliSum.from_workload(w.pauli_sum(30, [(1.0, "ZZ" + "I" * 28)]))
+        t64 = torch.empty(1 << 30, dtype=torch.complex64, device="cuda")
+        t128 = torch.empty(1 << 30, dtype=torch.complex128, device="cuda")
+        s64, s128 = yb.State(30, 1, yb.C64, tensor=t64), yb.State(30, 1, yb.C128, tensor=t128)
+        def f64():
+            s64.reset()
+            yb.forward(s64, cc, [])
+        yb.set_options(autotune=1, mfma=1)
+        ms64_tuned = timed(f64, 2)
+        yb.set_options(autotune=0, fuse_width=5, mfma=1)
+        ms64 = timed(f64, 2)
+        yb.set_options(autotune=0, fuse_width=1)
+
+        def f128():
+            s128.reset()
+            yb.forward(s128, cc, [])
+        ms128 = timed(f128, 2)
+        fid = float(abs(torch.vdot(t128, t64.to(torch.complex128)).item()) ** 2)
+        e64, e128 = float(yb.expect(s64, zz)[0]), float(yb.expect(s128, zz)[0])
+        out["c5_30q"] = {"gates": len(c.gates), "c64_mfma_w5_ms": round(ms64, 1),
+                         "c64_autotuned_ms": round(ms64_tuned, 1), "c128_w1_ms": round(ms128, 1),
+                         "fidelity_c64_vs_c128": fid, "z0z1_c64": e64, "z0z1_c128": e128,
+                         "z0z1_abs_err": abs(e64 - e128)}
+        del s64, s128, t64, t128
+    finally:
+        yb.set_options(autotune=saved.autotune, fuse_width=saved.fuse_width, mfma=saved.mfma, plain=saved.plain)
+    return out
 
 
 def main():
@@ -223,6 +322,10 @@ def main():
     if args.batch_circuits > 0:
         batch = bench_uneven_batch(yb, w, torch, args.batch_circuits, args.batch_steps)
 
+    configs = None
+    if not args.no_configs:
+        configs = bench_configs(yb, w, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -249,7 +352,7 @@ def main():
         "energy": float(e[0]), "drift": drift,
         "plain_ms_per_step": plain_ms,
         "speedup_vs_plain": (plain_ms / ms_step) if plain_ms else None,
-        "roofline": roofline, "cpu_baseline": cpu, "uneven_batch": batch,
+        "roofline": roofline, "cpu_baseline": cpu, "uneven_batch": batch, "configs": configs,
     }
     print(json.dumps(out))
 
