@@ -269,6 +269,7 @@ int yao_pauli_sum_destroy(yao_pauli_sum* h)
 {
     if (!h) return 0;
     drop_batch(h);
+    drop_obs_plans(h);
     if (h->d_groups) (void)hipFree(h->d_groups);
     if (h->d_terms) (void)hipFree(h->d_terms);
     delete h;

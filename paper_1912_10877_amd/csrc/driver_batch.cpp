@@ -232,7 +232,7 @@ int autotune(const yao_circuit* c, const double* params, yao_state* s, yao_pauli
     YAO_TRY(dev_alloc((void**)&tb.psi64, 16 * N));
     YAO_TRY(dev_alloc(&tb.lam, s->elem_bytes() * N));
     YAO_TRY(dev_alloc((void**)&tb.gpart, sizeof(double) * gp));
-    YAO_TRY(dev_alloc((void**)&tb.hpart, sizeof(double) * hpsi_partial_doubles(n, 1)));
+    YAO_TRY(dev_alloc((void**)&tb.hpart, sizeof(double) * hpsi_partial_doubles(h, n, 1, dt)));
     YAO_TRY(dev_alloc((void**)&tb.e, sizeof(double)));
     double best_b = 1e300;
     for (int tq : tile_candidates(n, dt, true)) {
@@ -442,7 +442,7 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
         psi_b[best] = std::max(psi_b[best], 16 * N);
         lam_b[best] = std::max(lam_b[best], it.s->elem_bytes() * N);
         gp_b[best] = std::max(gp_b[best], sizeof(double) * (size_t)std::max(1, it.nslots) * it.W);
-        hp_b[best] = std::max(hp_b[best], sizeof(double) * hpsi_partial_doubles(it.s->n, 1));
+        hp_b[best] = std::max(hp_b[best], sizeof(double) * hpsi_partial_doubles(it.h, it.s->n, 1, it.s->dtype));
         it.out_e = nout++;
         it.off_f = off;
         off += it.bytes_f;

@@ -675,7 +675,7 @@ static int backward_reversible(yao_state* s, const yao_circuit* c, const double*
     double* psi = (double*)workspace(WS_PSI64, elems * 16);
     void* lam = workspace(WS_LAM, s->bytes());
     double* gpartial = (double*)workspace(WS_PARTIAL, sizeof(double) * (size_t)std::max(1, nslots) * B * W);
-    const size_t hp = hpsi_partial_doubles(n, B);
+    const size_t hp = hpsi_partial_doubles(h, n, B, s->dtype);
     double* misc = (double*)workspace(WS_MISC, sizeof(double) * (hp + (size_t)B + (size_t)std::max(1, nslots) * B));
     if (!psi || !lam || !gpartial || !misc) return YAO_ENOMEM;
     double* edev = misc + hp;

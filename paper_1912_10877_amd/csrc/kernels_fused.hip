@@ -14,6 +14,8 @@
 // The pass's op records are copied to LDS together with the tile; LDS reads complete in
 // order, so the record of the next op is fetched while the current op computes.
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <mutex>
 #include <vector>
 
@@ -1236,6 +1238,128 @@ size_t small_circuit_lds_bytes(int n)
     return ((size_t)32 << n) + sizeof(double) * 2 * kMaxGroupSlots * (size_t)grad_entries(nthr, 0);
 }
 
+// ------------------------------------------------------------------------------ observables
+// H psi and <psi|H|psi> in tile passes: the X-mask groups of the Pauli sum are split into
+// passes whose masks lie inside one tile qubit set; a pass reads each tile of psi into LDS once
+// and adds, for every element j of the tile and group g, c_t i^{ny} (-1)^{|(j ^ x) & z|}
+// psi[j ^ x] over the group's terms (eq. expectation). Partners stay inside the tile, so the
+// state is read once per pass instead of once per group.
+constexpr int kObsRegBits = 4;  // elements per thread: 16
+constexpr int kObsMaxTile = 13;
+struct ObsGroupT {
+    uint32_t x;  // X mask in tile-bit coordinates
+    int t0, t1;  // terms
+    int pad;
+};
+struct ObsTermT {
+    double c;
+    uint64_t zout;  // Z mask on qubits outside the tile (qubit coordinates)
+    uint32_t zin;   // Z mask on the tile (tile-bit coordinates)
+    int ny;         // number of Y factors
+};
+
+// One pass: groups[0 .. ng) over every tile. With OUT, (H psi) of these groups is written to
+// a.lam (accumulate: added to what earlier passes wrote there). The pass's part of
+// <psi|H|psi> per batch slot and tile goes to partial[b * W + pcol0 + tile].
+template <typename RP, typename RO, bool OUT>
+__global__ __launch_bounds__(512) void k_obs_pass(PassArgs a, const ObsGroupT* __restrict__ groups, int ng,
+                                                  const ObsTermT* __restrict__ terms, int accumulate,
+                                                  double* __restrict__ partial, int pcol0, int W)
+{
+    constexpr int RB = kObsRegBits, N = 1 << RB;
+    using VP = vec2_t<RP>;
+    using VO = vec2_t<RO>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int t = a.t, c = a.c;
+    const int nthr = 1 << (t - RB);
+    const int th = threadIdx.x;
+    VP* lp = (VP*)smem;
+    double* red = (double*)(smem + (sizeof(VP) << t));
+    const TileCtx tc = tile_ctx<RB>(a, th);
+    const VP* gp = (const VP*)a.psi;
+    {
+        VP v[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) v[r] = gp[tile_off<RB>(a, tc, r)];
+#pragma unroll
+        for (int r = 0; r < N; ++r) lp[swz((uint32_t)th + (uint32_t)r * nthr)] = v[r];
+    }
+    __syncthreads();
+    const YAO_CONST ObsGroupT* gq = cptr(groups);
+    const YAO_CONST ObsTermT* tq = cptr(terms);
+    VO* go = (VO*)a.lam;
+    // Table entries are read once per thread (scalar loads) and applied to the thread's 16
+    // elements: group by group, term by term.
+    double orr[N], oi[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) orr[r] = oi[r] = 0;
+    for (int g = 0; g < ng; ++g) {
+        const uint32_t x = gq[g].x;
+        const int t0 = gq[g].t0, t1 = gq[g].t1;
+        VP p[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) p[r] = lp[swz(((uint32_t)th + (uint32_t)r * nthr) ^ x)];
+        for (int k = t0; k < t1; ++k) {
+            const uint32_t zin = tq[k].zin;
+            const int ny = tq[k].ny;
+            // i^ny and the sign of the Z bits outside the tile, folded into the coefficient.
+            double cb = (__popcll(tc.base & tq[k].zout) & 1) ? -tq[k].c : tq[k].c;
+            if (ny & 2) cb = -cb;
+            if (ny & 1) {
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    const uint32_t src = ((uint32_t)th + (uint32_t)r * nthr) ^ x;
+                    const double cc = (__popc(src & zin) & 1) ? -cb : cb;
+                    orr[r] = fma(-cc, (double)p[r].y, orr[r]);
+                    oi[r] = fma(cc, (double)p[r].x, oi[r]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    const uint32_t src = ((uint32_t)th + (uint32_t)r * nthr) ^ x;
+                    const double cc = (__popc(src & zin) & 1) ? -cb : cb;
+                    orr[r] = fma(cc, (double)p[r].x, orr[r]);
+                    oi[r] = fma(cc, (double)p[r].y, oi[r]);
+                }
+            }
+        }
+    }
+    double acc = 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        const VP ae = lp[swz((uint32_t)th + (uint32_t)r * nthr)];
+        acc += (double)ae.x * orr[r] + (double)ae.y * oi[r];
+        if constexpr (OUT) {
+            if (tc.bvalid) {
+                const uint64_t off = tile_off<RB>(a, tc, r);
+                double wr = orr[r], wi = oi[r];
+                if (accumulate) {
+                    const VO prev = go[off];
+                    wr += (double)prev.x;
+                    wi += (double)prev.y;
+                }
+                go[off] = mkv<VO, RO>((RO)wr, (RO)wi);
+            }
+        }
+    }
+    // Per batch slot of the tile: row sums, then the rows in order.
+    const int Bc = 1 << c;
+    const int E = grad_entries(nthr, c);
+    if (nthr >= 16) {
+        acc = row_sum(acc, c);
+        if ((th & 15) < Bc) red[(th >> 4) * Bc + (th & 15)] = acc;
+    } else {
+        red[th] = acc;
+    }
+    __syncthreads();
+    if (th < Bc) {
+        double sum = 0;
+        for (int k = th; k < E; k += Bc) sum += red[k];
+        const int b = (int)(blockIdx.y << c) + th;
+        if (b < a.B) partial[(uint64_t)b * W + pcol0 + blockIdx.x] = sum;
+    }
+}
+
 // Raise each pass kernel's dynamic LDS limit to the CU's 160 KiB, once per kernel.
 template <typename K> int set_lds_limit(K kernel)
 {
@@ -1392,6 +1516,33 @@ size_t pass_lds_bytes(bool bwd, int t, int c, int psi_bytes, int lam_bytes, int 
     return ((size_t)(16 + lam_bytes) << t) + sizeof(double) * 2 * kMaxGroupSlots * (size_t)grad_entries(nthr, c);
 }
 
+// The tile geometry of a pass: tile qubits (ascending), the qubits outside the tile, and the
+// per-register offsets of the load mapping for RB register bits.
+static void tile_args(PassArgs& a, int n, int B, int c, int t, const std::vector<int>& tile_qubits, int RB)
+{
+    a.n = n;
+    a.B = B;
+    a.c = c;
+    a.t = t;
+    a.ntq = (int)tile_qubits.size();
+    uint64_t T = 0;
+    for (int j = 0; j < a.ntq; ++j) {
+        a.tile_qubits[j] = tile_qubits[j];
+        T |= uint64_t(1) << tile_qubits[j];
+    }
+    a.nnt = 0;
+    for (int q = 0; q < n; ++q)
+        if (!((T >> q) & 1)) a.nontile_qubits[a.nnt++] = q;
+    const int j0 = t - RB - c;
+    for (int r = 0; r < (1 << RB); ++r) {
+        uint64_t d = 0;
+        for (int rb = 0; rb < RB; ++rb)
+            if ((r >> rb) & 1) d |= uint64_t(1) << tile_qubits[j0 + rb];
+        a.rofs[r] = d * (uint64_t)B;
+    }
+    a.ntiles = 1 << a.nnt;
+}
+
 int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, const POp* ops, const PGroupDesc* groups,
                 const double* mats, double* gpartial, int pstride, int n, int B, int c, int t, int group0,
                 int ngroups, const std::vector<int>& tile_qubits, double flops, int op_first, int nops,
@@ -1412,32 +1563,9 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
     a.gpartial = gpartial;
     a.dmats = (const uint4*)dmats;
     a.ndm = dm_words;
-    a.n = n;
-    a.B = B;
-    a.c = c;
-    a.t = t;
     a.ngroups = ngroups;
     a.nops = nops;
-    a.ntq = (int)tile_qubits.size();
-    uint64_t T = 0;
-    for (int j = 0; j < a.ntq; ++j) {
-        a.tile_qubits[j] = tile_qubits[j];
-        T |= uint64_t(1) << tile_qubits[j];
-    }
-    a.nnt = 0;
-    for (int q = 0; q < n; ++q)
-        if (!((T >> q) & 1)) a.nontile_qubits[a.nnt++] = q;
-    {
-        const int RB = bwd ? kRegBitsBwd : kRegBitsFwd;
-        const int j0 = t - RB - c;
-        for (int r = 0; r < (1 << RB); ++r) {
-            uint64_t d = 0;
-            for (int rb = 0; rb < RB; ++rb)
-                if ((r >> rb) & 1) d |= uint64_t(1) << tile_qubits[j0 + rb];
-            a.rofs[r] = d * (uint64_t)B;
-        }
-    }
-    a.ntiles = 1 << a.nnt;
+    tile_args(a, n, B, c, t, tile_qubits, bwd ? kRegBitsBwd : kRegBitsFwd);
     a.pstride = pstride > a.ntiles ? pstride : a.ntiles;
     const int Bc = 1 << c;
     const int RBk = bwd ? kRegBitsBwd : kRegBitsFwd;
@@ -1481,6 +1609,198 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
     prof_end(pi, 2.0 * (double)(uint64_t(1) << n) * B * (pb + lb), flops);
     YAO_HIP(hipGetLastError());
     return 0;
+}
+
+// ---------------------------------------------------------------------- observable passes
+namespace {
+
+struct ObsPass {
+    std::vector<int> tile_qubits;
+    int g0 = 0, g1 = 0;  // groups of the pass in the device table
+};
+struct ObsPlan {
+    bool ok = false;  // false: an X mask is wider than a tile (the observable takes the
+                      // per-group kernels)
+    int c = 0, t = 0;
+    std::vector<ObsPass> passes;
+    ObsGroupT* dgroups = nullptr;
+    ObsTermT* dterms = nullptr;
+};
+using ObsKey = std::tuple<const yao_pauli_sum*, int, int, int>;  // h, n, B, dtype
+std::map<ObsKey, ObsPlan*> g_obs;
+std::mutex g_obs_mu;
+
+// Group the terms by X mask, then put each group in the first pass whose tile qubits can take
+// its mask (first fit, over tiles of t - c qubits that keep the lowest qubits for contiguous
+// rows), and fill every pass's tile with the lowest unused qubits.
+ObsPlan* obs_plan(const yao_pauli_sum* h, int n, int B, int dtype)
+{
+    std::lock_guard<std::mutex> lk(g_obs_mu);
+    const ObsKey key{h, n, B, dtype};
+    auto it = g_obs.find(key);
+    if (it != g_obs.end()) return it->second;
+    const int lb = ilog2_ceil((uint64_t)B);
+    const int c = lb < 3 ? lb : 3;
+    const int tq = std::min(n, kObsMaxTile - c);
+    const int L = std::max(0, std::min((dtype == YAO_C64 ? 4 : 3) - c, tq));
+    std::vector<uint64_t> xs;
+    for (size_t k = 0; k < h->coef.size(); ++k) {
+        bool seen = false;
+        for (uint64_t x : xs) seen |= x == h->x[k];
+        if (!seen) xs.push_back(h->x[k]);
+    }
+    const uint64_t low = L > 0 ? ((uint64_t(1) << L) - 1) : 0;
+    ObsPlan* P = new ObsPlan;
+    P->c = c;
+    P->t = c + tq;
+    for (uint64_t x : xs)
+        if (__builtin_popcountll(x) > tq) {
+            g_obs[key] = P;
+            return P;
+        }
+    std::vector<uint64_t> T;                // qubits of each pass
+    std::vector<std::vector<uint64_t>> gx;  // X masks of each pass
+    for (uint64_t x : xs) {
+        size_t p = 0;
+        while (p < T.size() && __builtin_popcountll(T[p] | x) > tq) ++p;
+        if (p == T.size()) {
+            // A mask too wide for a tile with the low qubits fixed drops them.
+            T.push_back(__builtin_popcountll(low | x) <= tq ? low : 0);
+            gx.emplace_back();
+        }
+        T[p] |= x;
+        gx[p].push_back(x);
+    }
+    std::vector<ObsGroupT> hg;
+    std::vector<ObsTermT> ht;
+    for (size_t p = 0; p < T.size(); ++p) {
+        uint64_t Tp = T[p];
+        for (int q = 0; q < n && __builtin_popcountll(Tp) < tq; ++q) Tp |= uint64_t(1) << q;
+        ObsPass ps;
+        for (int q = 0; q < n; ++q)
+            if ((Tp >> q) & 1) ps.tile_qubits.push_back(q);
+        auto to_tile = [&](uint64_t m) {
+            uint32_t r = 0;
+            for (size_t j = 0; j < ps.tile_qubits.size(); ++j)
+                if ((m >> ps.tile_qubits[j]) & 1) r |= 1u << (c + (int)j);
+            return r;
+        };
+        ps.g0 = (int)hg.size();
+        for (uint64_t x : gx[p]) {
+            ObsGroupT g;
+            g.x = to_tile(x);
+            g.t0 = (int)ht.size();
+            for (size_t k = 0; k < h->coef.size(); ++k) {
+                if (h->x[k] != x) continue;
+                ObsTermT tt;
+                tt.c = h->coef[k];
+                tt.zin = to_tile(h->z[k]);
+                tt.zout = h->z[k] & ~Tp;
+                tt.ny = __builtin_popcountll(h->x[k] & h->z[k]);
+                ht.push_back(tt);
+            }
+            g.t1 = (int)ht.size();
+            g.pad = 0;
+            hg.push_back(g);
+        }
+        ps.g1 = (int)hg.size();
+        P->passes.push_back(ps);
+    }
+    if (hipMalloc((void**)&P->dgroups, sizeof(ObsGroupT) * (hg.size() + 1)) != hipSuccess ||
+        hipMalloc((void**)&P->dterms, sizeof(ObsTermT) * (ht.size() + 1)) != hipSuccess ||
+        hipMemcpy(P->dgroups, hg.data(), sizeof(ObsGroupT) * hg.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->dterms, ht.data(), sizeof(ObsTermT) * ht.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        if (P->dgroups) (void)hipFree(P->dgroups);
+        if (P->dterms) (void)hipFree(P->dterms);
+        delete P;
+        set_error(YAO_ENOMEM, "observable pass tables");
+        return nullptr;
+    }
+    P->ok = true;
+    g_obs[key] = P;
+    return P;
+}
+
+template <typename RP, typename RO, bool OUT> int obs_launch_one(const PassArgs& a, dim3 grid, int nthr, size_t lds,
+                                                                 const ObsPlan* P, const ObsPass& ps, int accumulate,
+                                                                 double* partial, int pcol0, int W)
+{
+    YAO_TRY(set_lds_limit(k_obs_pass<RP, RO, OUT>));
+    k_obs_pass<RP, RO, OUT><<<grid, nthr, lds, stream()>>>(a, P->dgroups + ps.g0, ps.g1 - ps.g0, P->dterms, accumulate,
+                                                           partial, pcol0, W);
+    YAO_HIP(hipGetLastError());
+    return 0;
+}
+
+}  // namespace
+
+bool obs_passes_ok(const yao_pauli_sum* h, int n, int B, int dtype)
+{
+    if (n < kObsRegBits + 1) return false;
+    const ObsPlan* P = obs_plan(h, n, B, dtype);
+    return P && P->ok;
+}
+
+size_t obs_partial_doubles(const yao_pauli_sum* h, int n, int B, int dtype)
+{
+    const ObsPlan* P = obs_plan(h, n, B, dtype);
+    if (!P || !P->ok) return 0;
+    return (size_t)B * P->passes.size() * (size_t(1) << (n - (P->t - P->c)));
+}
+
+// H psi into out (out == nullptr: the energy only) and the pass/tile partials of the energy
+// in partial[b * W + column]; *W receives the row length.
+int launch_obs_passes(const void* psi, int dtype, void* out, int out_dtype, int n, int B, const yao_pauli_sum* h,
+                      double* partial, int* W)
+{
+    const ObsPlan* P = obs_plan(h, n, B, dtype);
+    if (!P) return YAO_ENOMEM;
+    if (!P->ok) return set_error(YAO_EINVAL, "observable has an X mask wider than a tile");
+    const int t = P->t, c = P->c;
+    const int nthr = 1 << (t - kObsRegBits);
+    const int ntiles = 1 << (n - (t - c));
+    *W = (int)P->passes.size() * ntiles;
+    const int Bc = 1 << c;
+    const dim3 grid(ntiles, (B + Bc - 1) / Bc);
+    const size_t lds = ((size_t)(dtype == YAO_C64 ? 8 : 16) << t) + sizeof(double) * (size_t)grad_entries(nthr, c);
+    for (size_t p = 0; p < P->passes.size(); ++p) {
+        const ObsPass& ps = P->passes[p];
+        PassArgs a;
+        memset(&a, 0, sizeof(a));
+        a.psi = const_cast<void*>(psi);
+        a.lam = out;
+        tile_args(a, n, B, c, t, ps.tile_qubits, kObsRegBits);
+        const int acc = p > 0 ? 1 : 0, col = (int)p * ntiles;
+        if (!out) {
+            if (dtype == YAO_C64) YAO_TRY((obs_launch_one<float, float, false>(a, grid, nthr, lds, P, ps, 0, partial, col, *W)));
+            else YAO_TRY((obs_launch_one<double, double, false>(a, grid, nthr, lds, P, ps, 0, partial, col, *W)));
+        } else if (dtype == YAO_C64 && out_dtype == YAO_C64) {
+            YAO_TRY((obs_launch_one<float, float, true>(a, grid, nthr, lds, P, ps, acc, partial, col, *W)));
+        } else if (dtype == YAO_C64) {
+            YAO_TRY((obs_launch_one<float, double, true>(a, grid, nthr, lds, P, ps, acc, partial, col, *W)));
+        } else if (out_dtype == YAO_C64) {
+            YAO_TRY((obs_launch_one<double, float, true>(a, grid, nthr, lds, P, ps, acc, partial, col, *W)));
+        } else {
+            YAO_TRY((obs_launch_one<double, double, true>(a, grid, nthr, lds, P, ps, acc, partial, col, *W)));
+        }
+    }
+    return 0;
+}
+
+void drop_obs_plans(const yao_pauli_sum* h)
+{
+    std::lock_guard<std::mutex> lk(g_obs_mu);
+    for (auto it = g_obs.begin(); it != g_obs.end();) {
+        if (std::get<0>(it->first) == h) {
+            (void)hipDeviceSynchronize();
+            if (it->second->dgroups) (void)hipFree(it->second->dgroups);
+            if (it->second->dterms) (void)hipFree(it->second->dterms);
+            delete it->second;
+            it = g_obs.erase(it);
+        } else {
+            ++it;
+        }
+    }
 }
 
 }  // namespace yao

@@ -583,6 +583,18 @@ static int finish_slot_sums(double* partial, int B, int nblk, double* energy_hos
 
 int launch_expect(const void* data, int dtype, int n, int B, yao_pauli_sum* h, double* energy_host)
 {
+    if (obs_passes_ok(h, n, B, dtype)) {
+        const size_t np = obs_partial_doubles(h, n, B, dtype);
+        if (!np) return YAO_ENOMEM;
+        double* partial = (double*)workspace(WS_PARTIAL, sizeof(double) * np);
+        if (!partial) return YAO_ENOMEM;
+        int W = 0;
+        const int pi = prof_begin(YAO_KF_EXPECT);
+        YAO_TRY(launch_obs_passes(data, dtype, nullptr, dtype, n, B, h, partial, &W));
+        prof_end(pi, (double)(uint64_t(1) << n) * B * (dtype == YAO_C64 ? 8 : 16),
+                 (double)(uint64_t(1) << n) * B * 4.0 * (double)h->coef.size());
+        return finish_slot_sums(partial, B, W, energy_host);
+    }
     YAO_TRY(pauli_upload(h));
     BatchGeom bg = make_batch_geom(B);
     uint64_t rows = uint64_t(1) << n;
@@ -605,6 +617,16 @@ int launch_expect(const void* data, int dtype, int n, int B, yao_pauli_sum* h, d
 int launch_hpsi(const void* data, int dtype, void* out, int out_dtype, int n, int B, yao_pauli_sum* h,
                 double* energy_host)
 {
+    if (obs_passes_ok(h, n, B, dtype)) {
+        const size_t np = obs_partial_doubles(h, n, B, dtype);
+        if (!np) return YAO_ENOMEM;
+        double* partial = (double*)workspace(WS_PARTIAL, sizeof(double) * np);
+        if (!partial) return YAO_ENOMEM;
+        int W = 0;
+        YAO_TRY(launch_obs_passes(data, dtype, out, out_dtype, n, B, h, partial, &W));
+        if (!energy_host) return 0;
+        return finish_slot_sums(partial, B, W, energy_host);
+    }
     YAO_TRY(pauli_upload(h));
     BatchGeom bg = make_batch_geom(B);
     uint64_t rows = uint64_t(1) << n;
@@ -630,8 +652,9 @@ int launch_hpsi(const void* data, int dtype, void* out, int out_dtype, int n, in
     return finish_slot_sums(partial, B, nbx, energy_host);
 }
 
-size_t hpsi_partial_doubles(int n, int B)
+size_t hpsi_partial_doubles(const yao_pauli_sum* h, int n, int B, int dtype)
 {
+    if (obs_passes_ok(h, n, B, dtype)) return std::max<size_t>(1, obs_partial_doubles(h, n, B, dtype));
     BatchGeom bg = make_batch_geom(B);
     return (size_t)B * reduce_grid_x(uint64_t(1) << n, bg.logBc);
 }
@@ -641,6 +664,11 @@ size_t hpsi_partial_doubles(int n, int B)
 int launch_hpsi_dev(const void* data, int dtype, void* out, int out_dtype, int n, int B, const yao_pauli_sum* h,
                     double* partial, double* energy_dev)
 {
+    if (obs_passes_ok(h, n, B, dtype)) {
+        int W = 0;
+        YAO_TRY(launch_obs_passes(data, dtype, out, out_dtype, n, B, h, partial, &W));
+        return launch_row_sums(partial, B, W, energy_dev);
+    }
     if (!h->d_groups) return set_error(YAO_EINVAL, "observable tables not uploaded");
     BatchGeom bg = make_batch_geom(B);
     const uint64_t rows = uint64_t(1) << n;

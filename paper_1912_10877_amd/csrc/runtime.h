@@ -105,7 +105,16 @@ int launch_expect(const void* data, int dtype, int n, int B, yao_pauli_sum* h, d
 int launch_hpsi(const void* data, int dtype, void* out, int out_dtype, int n, int B, yao_pauli_sum* h,
                 double* energy_host);
 // The same with the energy left on the device and no synchronisation (graph-capturable).
-size_t hpsi_partial_doubles(int n, int B);
+// Doubles of partials that launch_hpsi_dev needs for this observable and state shape (builds
+// the observable's pass tables on first use; call it outside graph capture).
+size_t hpsi_partial_doubles(const yao_pauli_sum* h, int n, int B, int dtype);
+// Observables in tile passes (states of >= 5 qubits): H psi into out (nullptr: energy only),
+// energy partials partial[b * W + column].
+bool obs_passes_ok(const yao_pauli_sum* h, int n, int B, int dtype);
+size_t obs_partial_doubles(const yao_pauli_sum* h, int n, int B, int dtype);
+int launch_obs_passes(const void* psi, int dtype, void* out, int out_dtype, int n, int B, const yao_pauli_sum* h,
+                      double* partial, int* W);
+void drop_obs_plans(const yao_pauli_sum* h);
 int launch_hpsi_dev(const void* data, int dtype, void* out, int out_dtype, int n, int B, const yao_pauli_sum* h,
                     double* partial, double* energy_dev);
 // Precision conversion / copies between states of equal shape.

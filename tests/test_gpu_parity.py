@@ -93,6 +93,29 @@ def test_state_create_is_zero_state_and_upload_roundtrip(dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,B", [(16, 1), (15, 4), (14, 9)])
+def test_expectation_and_hpsi_over_several_tiles(dtype, n, B):
+    """States wider than a tile: the observable's X-mask groups are split over several tile
+    passes (H psi accumulated across them), and a mask wider than a tile falls back to the
+    per-group kernels."""
+    rng = np.random.default_rng(100 + n)
+    terms = [(float(rng.normal()), "".join("IXYZ"[int(v)] for v in rng.integers(0, 4, n))) for _ in range(10)]
+    wide = [(0.5, "X" * n), (-0.3, "Z" + "Y" * (n - 1))]
+    for H in (w.heisenberg(n), w.pauli_sum(n, terms), w.pauli_sum(n, terms[:3] + wide)):
+        psi = w.random_state(n, B, 5)
+        s = yb.State(n, B, dtype)
+        s.upload(psi)
+        h = yb.PauliSum.from_workload(H)
+        ref_psi = psi.astype(s.np_dtype).astype(np.complex128)
+        re, _ = oracle.expect(H, ref_psi)
+        np.testing.assert_allclose(yb.expect(s, h), re, atol=1e-11 if dtype == 1 else 2e-5)
+        out = yb.State(n, B, dtype)
+        np.testing.assert_allclose(yb.hpsi(s, h, out), re, atol=1e-11 if dtype == 1 else 2e-5)
+        want = oracle.hpsi(H, ref_psi)
+        assert np.abs(out.download() - want).max() <= (1e-12 if dtype == 1 else 1e-5) * max(1, np.abs(want).max())
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("B", [1, 4, 70])
 def test_expectation_and_hpsi(dtype, B):
     n = 8
