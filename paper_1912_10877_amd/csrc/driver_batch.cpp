@@ -26,7 +26,7 @@ int prepare_pass_kernels();
 
 namespace {
 
-constexpr int kBanks = 4;  // streams of the graph
+constexpr int kBanks = 16;  // streams of the graph
 
 // Circuits are recorded in phases by state size, each phase waiting for the previous one on
 // every stream: a pass over a tile takes about as long whatever the state size, so a small
