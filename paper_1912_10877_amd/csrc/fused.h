@@ -15,7 +15,7 @@ constexpr int kMaxTileBits = 13;  // 2^13 complex64 = 64 KiB of LDS
 constexpr int kMaxFusedK = 3;     // reverse passes: wider gates run as standalone launches
 constexpr int kMaxDenseK = 4;     // forward passes: gates up to 4 qubits as dense register blocks
 constexpr int kMaxGroupSlots = 12;  // gradient-carrying gates per register group
-constexpr int kMaxPassOps = 80;     // op records of a pass, staged in LDS at the start of the pass
+constexpr int kMaxPassOps = 4096;   // op records of a pass (read in place through the scalar cache)
 constexpr int kMaxPassDense = 8;    // dense blocks of a forward pass (their matrices are staged too)
 
 // Structure classes of a one-qubit matrix inside a pass.

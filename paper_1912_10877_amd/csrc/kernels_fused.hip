@@ -1549,7 +1549,7 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
                 const double* dmats, int dm_words)
 {
     if (nops > kMaxPassOps || ngroups > kMaxPassOps)
-        return set_error(YAO_EINVAL, "pass of %d ops exceeds the staged program size", nops);
+        return set_error(YAO_EINVAL, "pass of %d ops exceeds %d", nops, kMaxPassOps);
     const int dm_max = bwd ? 0 : kMaxPassDense * 256;  // 4 KiB per block in every layout
     if (dm_words < 0 || dm_words > dm_max)
         return set_error(YAO_EINVAL, "pass carries %d words of dense matrices (at most %d)", dm_words, dm_max);
