@@ -14,7 +14,8 @@ namespace yao {
 
 int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, const POp* ops, const PGroupDesc* groups,
                 const double* mats, double* gpartial, int pstride, int n, int B, int c, int t, int group0,
-                int ngroups, const std::vector<int>& tile_qubits, double flops, int op_first, int nops,
+                int ngroups, const std::vector<int>& tile_qubits, const std::vector<int>& store_src, double flops,
+                int op_first, int nops,
                 const double* dmats, int dm_words);
 int launch_fill(double* p, size_t count, double v);
 
@@ -162,11 +163,14 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
             }
             continue;
         }
+        // Tile index bits, and the index bit of each qubit in this pass's layout.
         uint64_t T = 0;
         for (int q : pass.tile_qubits) T |= uint64_t(1) << q;
+        auto ph = [&](int q) { return pass.phys.empty() ? q : pass.phys[q]; };
+        auto in_tile = [&](int q) { return ((T >> ph(q)) & 1) != 0; };
         auto tile_bit = [&](int q) {
             int r = 0;
-            for (int j = 0; j < q; ++j) r += (T >> j) & 1;
+            for (int j = 0; j < ph(q); ++j) r += (T >> j) & 1;
             return P.c + r;
         };
         for (const HostGroup& hg : pass.groups) {
@@ -243,7 +247,7 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     }
                     for (int m = 0; m < g.nctrl; ++m) {
                         cpos[m] = -1;
-                        if ((T >> g.ctrls[m]) & 1)
+                        if (in_tile(g.ctrls[m]))
                             for (int r = 0; r < kRegBitsFwd; ++r)
                                 if (gd.rpos[r] == tile_bit(g.ctrls[m])) cpos[m] = r;
                     }
@@ -329,15 +333,15 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                 for (int m = 0; m < g.nctrl; ++m) {
                     const int q = g.ctrls[m];
                     bool folded = false;  // a control on a dense block's register bit is in its matrix
-                    if (hg.dense && ((T >> q) & 1))
+                    if (hg.dense && in_tile(q))
                         for (int r = 0; r < kRegBitsFwd; ++r) folded |= gd.rpos[r] == tile_bit(q);
                     if (folded) continue;
-                    if ((T >> q) & 1) {
+                    if (in_tile(q)) {
                         op.cmask |= 1u << tile_bit(q);
                         if (g.cvals[m]) op.cval |= 1u << tile_bit(q);
                     } else {
-                        op.omask |= uint64_t(1) << q;
-                        if (g.cvals[m]) op.oval |= uint64_t(1) << q;
+                        op.omask |= uint64_t(1) << ph(q);
+                        if (g.cvals[m]) op.oval |= uint64_t(1) << ph(q);
                     }
                 }
                 {
@@ -421,9 +425,18 @@ static int upload_program(const Program& prog, DevProgram& d, int slot = WS_MAT)
     return 0;
 }
 
+// A standalone gate's targets and controls on the index bits of the pass's layout.
+static void layout_qubits(const HostPass& pass, const GateRec& g, int* locs, int* ctrls)
+{
+    auto ph = [&](int q) { return pass.phys.empty() ? q : pass.phys[q]; };
+    for (int j = 0; j < g.k; ++j) locs[j] = ph(g.locs[j]);
+    for (int m = 0; m < g.nctrl; ++m) ctrls[m] = ph(g.ctrls[m]);
+}
+
 int launch_forward_passes(const Plan& P, const Program& prog, const DevProgram& d, void* data, int dtype, int n, int B,
                           const yao_circuit* c, const double* params)
 {
+    if (!P.valid) return set_error(YAO_EINVAL, "pass plan could not restore the qubit layout");
     for (size_t p = 0; p < P.passes.size(); ++p) {
         const HostPass& pass = P.passes[p];
         if (pass.standalone >= 0) {
@@ -431,12 +444,14 @@ int launch_forward_passes(const Plan& P, const Program& prog, const DevProgram& 
             const GateRec& g = c->gates[P.ops[pass.standalone].gate];
             HostMat U;
             U.k = g.k;
-            YAO_TRY(launch_gate(data, dtype, n, B, U, g.locs, make_ctrl(g.nctrl, g.ctrls, g.cvals),
+            int locs[8], ctrls[8];
+            layout_qubits(pass, g, locs, ctrls);
+            YAO_TRY(launch_gate(data, dtype, n, B, U, locs, make_ctrl(g.nctrl, ctrls, g.cvals),
                                 d.mats + prog.pass_mat[p]));
             continue;
         }
         YAO_TRY(launch_pass(false, dtype, dtype, data, nullptr, d.ops, d.groups, d.mats, nullptr, 0, n, B, P.c, P.t,
-                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits,
+                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits, pass.store_src,
                             prog.pass_flops[p] * (double)(uint64_t(1) << n) * B, prog.pass_op0[p],
                             prog.pass_nops[p], d.mats + prog.pass_dmat0[p], prog.pass_dmat_words[p]));
     }
@@ -447,6 +462,7 @@ int launch_backward_passes(const Plan& P, const Program& prog, const DevProgram&
                            const double* params, double* psi, void* lam, int lam_dtype, int n, int B, double* gpartial,
                            int W)
 {
+    if (!P.valid) return set_error(YAO_EINVAL, "pass plan could not restore the qubit layout");
     for (size_t p = 0; p < P.passes.size(); ++p) {
         const HostPass& pass = P.passes[p];
         if (pass.standalone >= 0) {
@@ -456,13 +472,15 @@ int launch_backward_passes(const Plan& P, const Program& prog, const DevProgram&
             HostMat Ud, M;
             Ud.k = M.k = g.k;
             const int slot = prog.slot_of_gate[gi];
-            YAO_TRY(launch_adjoint_step_strided(psi, lam, lam_dtype, n, B, Ud, slot >= 0 ? &M : nullptr, g.locs,
-                                                make_ctrl(g.nctrl, g.ctrls, g.cvals), d.mats + prog.pass_mat[p],
+            int locs[8], ctrls[8];
+            layout_qubits(pass, g, locs, ctrls);
+            YAO_TRY(launch_adjoint_step_strided(psi, lam, lam_dtype, n, B, Ud, slot >= 0 ? &M : nullptr, locs,
+                                                make_ctrl(g.nctrl, ctrls, g.cvals), d.mats + prog.pass_mat[p],
                                                 slot >= 0 ? gpartial + (size_t)slot * B * W : nullptr, W));
             continue;
         }
         YAO_TRY(launch_pass(true, YAO_C128, lam_dtype, psi, lam, d.ops, d.groups, d.mats, gpartial, W, n, B, P.c, P.t,
-                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits,
+                            prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits, pass.store_src,
                             prog.pass_flops[p] * (double)(uint64_t(1) << n) * B, prog.pass_op0[p],
                             prog.pass_nops[p], nullptr, 0));
     }

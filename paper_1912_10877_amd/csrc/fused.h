@@ -84,16 +84,25 @@ struct HostGroup {
     bool lds = false;       // one k = 2, 3 gate applied in LDS (reverse passes)
     bool dense = false;     // one k = 2..4 gate as a 16 x 16 matrix on the register bits (forward)
 };
+// Qubit layout: inside a plan the state may be held with its qubits permuted, qubit q at
+// amplitude-index bit phys[q]. A pass loads its tile from the index bits tile_qubits and may
+// store it back permuted among those same bits (store_src), which lets the next pass find the
+// qubits it needs on the low, contiguous index bits. Every plan starts and ends with qubit q
+// on bit q.
 struct HostPass {
-    std::vector<int> tile_qubits;   // ascending
+    std::vector<int> tile_qubits;   // index bits of the tile, ascending
     std::vector<HostGroup> groups;
     int standalone = -1;            // op index for a standalone launch
+    std::vector<int> phys;          // layout at the start of the pass (empty: identity)
+    std::vector<int> store_src;     // t entries: tile bit i of the stored tile comes from tile
+                                    // bit store_src[i] of the tile in LDS (empty: identity)
 };
 struct Plan {
     int n = 0, B = 1, c = 0, t = 0;
     int reg_bits = kRegBitsFwd;
     int g0 = 0, g1 = 0;  // gate range
     bool reverse = false;
+    bool valid = true;   // false: the layout could not be put back (never expected)
     std::vector<HostOp> ops;        // in application order (reverse order of gates if reverse)
     std::vector<HostPass> passes;
 };

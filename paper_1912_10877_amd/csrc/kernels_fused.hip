@@ -42,6 +42,10 @@ struct PassArgs {
     uint64_t rofs[1 << kMaxRegBits];  // element offset (x B) of load register r from the thread's first
     const uint4* dmats;     // the pass's dense block matrices (forward), staged in LDS
     int ndm;                // their size in 16-byte words
+    // Store permutation: stored tile element e = th + r * nthr comes from LDS tile element
+    // store_thread_bits(th) | sreg[r] (thread bit i of e moves to tile bit ssrc[i]).
+    int ssrc[kMaxTileBits];
+    uint32_t sreg[1 << kMaxRegBits];
 };
 
 __device__ __forceinline__ uint32_t swz(uint32_t e)
@@ -445,6 +449,16 @@ template <int RB> __device__ __forceinline__ TileCtx tile_ctx(const PassArgs& a,
     tc.bidx = tc.bvalid ? tc.b0 + tc.bl : a.B - 1;
     tc.toff = (base | dth) * (uint64_t)a.B + (uint64_t)tc.bidx;
     return tc;
+}
+
+// LDS tile bits of the thread part (the low nb bits of th) of a stored element.
+__device__ __forceinline__ uint32_t store_thread_bits(const PassArgs& a, int th, int nb)
+{
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxTileBits; ++i)
+        if (i < nb) v |= (((uint32_t)th >> i) & 1u) << a.ssrc[i];
+    return v;
 }
 
 // The register bits of the load mapping are tile qubits whose offsets are the same for every
@@ -907,8 +921,9 @@ __global__ __launch_bounds__(512, sizeof(RP) == 4 ? 3 : 1) void k_pass_fwd(PassA
     }
 
     if (tc.bvalid) {
+        const uint32_t sth = store_thread_bits(a, th, t - RB);
 #pragma unroll
-        for (int r = 0; r < N; ++r) gp[tile_off<RB>(a, tc, r)] = lp[swz((uint32_t)th + (uint32_t)r * nthr)];
+        for (int r = 0; r < N; ++r) gp[tile_off<RB>(a, tc, r)] = lp[swz(sth | a.sreg[r])];
     }
 }
 
@@ -1092,10 +1107,11 @@ __global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
                            nthr, th, go);
 
     if (tc.bvalid) {
+        const uint32_t sth = store_thread_bits(a, th, t - RB);
 #pragma unroll
         for (int r = 0; r < N; ++r) {
             const uint64_t off = tile_off<RB>(a, tc, r);
-            const uint32_t e = swz((uint32_t)th + (uint32_t)r * nthr);
+            const uint32_t e = swz(sth | a.sreg[r]);
             gp[off] = lp[e];
             gl[off] = ll[e];
         }
@@ -1518,8 +1534,20 @@ size_t pass_lds_bytes(bool bwd, int t, int c, int psi_bytes, int lam_bytes, int 
 
 // The tile geometry of a pass: tile qubits (ascending), the qubits outside the tile, and the
 // per-register offsets of the load mapping for RB register bits.
-static void tile_args(PassArgs& a, int n, int B, int c, int t, const std::vector<int>& tile_qubits, int RB)
+static void tile_args(PassArgs& a, int n, int B, int c, int t, const std::vector<int>& tile_qubits, int RB,
+                      const std::vector<int>& store_src = {})
 {
+    // Store permutation (identity when store_src is empty).
+    for (int i = 0; i < t; ++i) {
+        const int src = store_src.empty() ? i : store_src[i];
+        if (i < t - RB) a.ssrc[i] = src;
+    }
+    for (int r = 0; r < (1 << RB); ++r) {
+        uint32_t v = 0;
+        for (int j = 0; j < RB; ++j)
+            if ((r >> j) & 1) v |= 1u << (store_src.empty() ? t - RB + j : store_src[t - RB + j]);
+        a.sreg[r] = v;
+    }
     a.n = n;
     a.B = B;
     a.c = c;
@@ -1545,9 +1573,20 @@ static void tile_args(PassArgs& a, int n, int B, int c, int t, const std::vector
 
 int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, const POp* ops, const PGroupDesc* groups,
                 const double* mats, double* gpartial, int pstride, int n, int B, int c, int t, int group0,
-                int ngroups, const std::vector<int>& tile_qubits, double flops, int op_first, int nops,
-                const double* dmats, int dm_words)
+                int ngroups, const std::vector<int>& tile_qubits, const std::vector<int>& store_src, double flops,
+                int op_first, int nops, const double* dmats, int dm_words)
 {
+    if (!store_src.empty() && (int)store_src.size() != t)
+        return set_error(YAO_EINVAL, "store permutation of %zu bits for a tile of %d", store_src.size(), t);
+    if (!store_src.empty()) {
+        uint32_t seen = 0;
+        for (int v : store_src) {
+            if (v < 0 || v >= t || ((seen >> v) & 1)) return set_error(YAO_EINVAL, "store permutation is not one");
+            seen |= 1u << v;
+        }
+        for (int b = 0; b < c; ++b)
+            if (store_src[b] != b) return set_error(YAO_EINVAL, "store permutation moves a batch bit");
+    }
     if (nops > kMaxPassOps || ngroups > kMaxPassOps)
         return set_error(YAO_EINVAL, "pass of %d ops exceeds %d", nops, kMaxPassOps);
     const int dm_max = bwd ? 0 : kMaxPassDense * 256;  // 4 KiB per block in every layout
@@ -1565,7 +1604,7 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
     a.ndm = dm_words;
     a.ngroups = ngroups;
     a.nops = nops;
-    tile_args(a, n, B, c, t, tile_qubits, bwd ? kRegBitsBwd : kRegBitsFwd);
+    tile_args(a, n, B, c, t, tile_qubits, bwd ? kRegBitsBwd : kRegBitsFwd, store_src);
     a.pstride = pstride > a.ntiles ? pstride : a.ntiles;
     const int Bc = 1 << c;
     const int RBk = bwd ? kRegBitsBwd : kRegBitsFwd;
