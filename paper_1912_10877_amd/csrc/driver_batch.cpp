@@ -165,7 +165,7 @@ const Plan& plan_for(const yao_circuit* c, int n, int dtype, bool bwd, int tq)
 {
     int t, cb, L;
     tile_geometry_tq(n, 1, dtype, bwd, tq, &t, &cb, &L);
-    return get_plan(c, 0, (int)c->gates.size(), 1, t, cb, L, bwd);
+    return get_plan(c, 0, (int)c->gates.size(), 1, t, cb, L, bwd, dtype == YAO_C64 ? 8 : 16);
 }
 
 int reverse_stride(int n, int dtype, int tq)

@@ -13,29 +13,31 @@
 namespace yao {
 
 int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, const POp* ops, const PGroupDesc* groups,
-                const double* mats, double* gpartial, int pstride, int n, int B, int c, int t, int group0,
+                const double* mats, double* gpartial, int pstride, int mslots, int n, int B, int c, int t, int group0,
                 int ngroups, const std::vector<int>& tile_qubits, const std::vector<int>& store_src, double flops,
                 int op_first, int nops,
                 const double* dmats, int dm_words);
 int launch_fill(double* p, size_t count, double v);
 
-using PlanKey = std::tuple<const yao_circuit*, uint64_t, int, int, int, int, int, int, bool, int, int>;
+using PlanKey = std::tuple<const yao_circuit*, uint64_t, int, int, int, int, int, int, bool, int, int, int>;
 static std::map<PlanKey, Plan> g_plans;
 static std::mutex g_plan_mu;
 
 const Plan& get_plan_ex(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse, int reg_bits,
-                        int max_ops)
+                        int max_ops, int max_slots)
 {
     std::lock_guard<std::mutex> lk(g_plan_mu);
-    PlanKey key{c, c->version, g0, g1, B, t, cb, L, reverse, reg_bits, max_ops};
+    PlanKey key{c, c->version, g0, g1, B, t, cb, L, reverse, reg_bits, max_ops, max_slots};
     auto it = g_plans.find(key);
     if (it != g_plans.end()) return it->second;
-    return g_plans.emplace(key, make_plan(c, g0, g1, B, t, cb, L, reverse, reg_bits, max_ops)).first->second;
+    return g_plans.emplace(key, make_plan(c, g0, g1, B, t, cb, L, reverse, reg_bits, max_ops, max_slots))
+        .first->second;
 }
 
-const Plan& get_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse)
+const Plan& get_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse, int lam_bytes)
 {
-    return get_plan_ex(c, g0, g1, B, t, cb, L, reverse, reverse ? kRegBitsBwd : kRegBitsFwd, kMaxPassOps);
+    return get_plan_ex(c, g0, g1, B, t, cb, L, reverse, reverse ? kRegBitsBwd : kRegBitsFwd, kMaxPassOps,
+                       reverse ? reverse_slot_limit(t, cb, lam_bytes) : kMaxGroupSlots);
 }
 
 int op_type_of(const HostMat& U)
@@ -223,8 +225,9 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     if (op.slot >= 0) {
                         gate_grad_matrix(g, th, M);
                         op.gen = gen_type_of(g);
-                        if (gd.nslot >= kMaxGroupSlots)
-                            return set_error(YAO_EINVAL, "register group carries more than %d gradients", kMaxGroupSlots);
+                        if (gd.nslot >= std::min(kMaxGroupSlots, P.max_slots))
+                            return set_error(YAO_EINVAL, "register group carries more than %d gradients",
+                                             std::min(kMaxGroupSlots, P.max_slots));
                         gd.slots[gd.nslot++] = op.slot;
                     } else {
                         M.resize(g.k);
@@ -450,7 +453,7 @@ int launch_forward_passes(const Plan& P, const Program& prog, const DevProgram& 
                                 d.mats + prog.pass_mat[p]));
             continue;
         }
-        YAO_TRY(launch_pass(false, dtype, dtype, data, nullptr, d.ops, d.groups, d.mats, nullptr, 0, n, B, P.c, P.t,
+        YAO_TRY(launch_pass(false, dtype, dtype, data, nullptr, d.ops, d.groups, d.mats, nullptr, 0, 0, n, B, P.c, P.t,
                             prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits, pass.store_src,
                             prog.pass_flops[p] * (double)(uint64_t(1) << n) * B, prog.pass_op0[p],
                             prog.pass_nops[p], d.mats + prog.pass_dmat0[p], prog.pass_dmat_words[p]));
@@ -479,7 +482,8 @@ int launch_backward_passes(const Plan& P, const Program& prog, const DevProgram&
                                                 slot >= 0 ? gpartial + (size_t)slot * B * W : nullptr, W));
             continue;
         }
-        YAO_TRY(launch_pass(true, YAO_C128, lam_dtype, psi, lam, d.ops, d.groups, d.mats, gpartial, W, n, B, P.c, P.t,
+        YAO_TRY(launch_pass(true, YAO_C128, lam_dtype, psi, lam, d.ops, d.groups, d.mats, gpartial, W, P.max_slots, n,
+                            B, P.c, P.t,
                             prog.pass_group0[p], (int)pass.groups.size(), pass.tile_qubits, pass.store_src,
                             prog.pass_flops[p] * (double)(uint64_t(1) << n) * B, prog.pass_op0[p],
                             prog.pass_nops[p], nullptr, 0));
@@ -709,7 +713,7 @@ static int backward_reversible(yao_state* s, const yao_circuit* c, const double*
     }
     YAO_TRY(forward_sweep(s->data, s->dtype, n, B, c, params, width, options().tile_qubits, dp));
 
-    const Plan& P = get_plan(c, 0, G, B, t, cb, L, true);
+    const Plan& P = get_plan(c, 0, G, B, t, cb, L, true, s->dtype == YAO_C64 ? 8 : 16);
     const BoundProgram* bp = bound_program(P, c, true, s->dtype, nullptr, nullptr);
     Program hprog;
     if (!bp) YAO_TRY(build_program(P, c, params, true, s->dtype, hprog));
@@ -800,7 +804,7 @@ int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao
             }
             if (resync) YAO_TRY(launch_convert(ref, s->dtype, psi, YAO_C128, elems));
         }
-        const Plan& P = get_plan(c, cuts[sg], cuts[sg + 1], B, t, cb, L, true);
+        const Plan& P = get_plan(c, cuts[sg], cuts[sg + 1], B, t, cb, L, true, s->dtype == YAO_C64 ? 8 : 16);
         YAO_TRY(run_backward_plan(P, c, params, psi, lam, s->dtype, n, B, gpartial, W, &slot_of_gate));
     }
     const int P_ = c->nparams;

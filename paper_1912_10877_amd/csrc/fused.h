@@ -14,9 +14,26 @@ constexpr int kMaxRegBits = 4;
 constexpr int kMaxTileBits = 13;  // 2^13 complex64 = 64 KiB of LDS
 constexpr int kMaxFusedK = 3;     // reverse passes: wider gates run as standalone launches
 constexpr int kMaxDenseK = 4;     // forward passes: gates up to 4 qubits as dense register blocks
-constexpr int kMaxGroupSlots = 12;  // gradient-carrying gates per register group
+constexpr int kMaxGroupSlots = 32;  // gradient-carrying gates per register group (at most)
 constexpr int kMaxPassOps = 4096;   // op records of a pass (read in place through the scalar cache)
 constexpr int kMaxPassDense = 8;    // dense blocks of a forward pass (their matrices are staged too)
+
+// Entries of gradient partials per register group of a reverse pass: one per 16-lane row and
+// batch slot of the tile (row sums), or one per thread in tiles of fewer than 16 threads.
+__host__ __device__ __forceinline__ int grad_entries(int nthr, int c)
+{
+    return nthr >= 16 ? (nthr >> 4) << c : nthr;
+}
+
+// Gradient-carrying ops per register group of a reverse pass, so that the two partial buffers
+// fit in the LDS a tile of 2^t elements of psi (FP64) and lambda (lam_bytes each) leaves.
+inline int reverse_slot_limit(int t, int c, int lam_bytes)
+{
+    const long avail = 160L * 1024 - ((long)(16 + lam_bytes) << t);
+    const long per = 2L * (long)sizeof(double) * grad_entries(1 << (t - kRegBitsBwd), c);
+    const long s = avail > 0 ? avail / per : 0;
+    return (int)(s < 1 ? 1 : (s > kMaxGroupSlots ? kMaxGroupSlots : s));
+}
 
 // Structure classes of a one-qubit matrix inside a pass.
 enum OpType : int {
@@ -103,6 +120,7 @@ struct Plan {
     int g0 = 0, g1 = 0;  // gate range
     bool reverse = false;
     bool valid = true;   // false: the layout could not be put back (never expected)
+    int max_slots = kMaxGroupSlots;  // gradient-carrying ops per register group
     std::vector<HostOp> ops;        // in application order (reverse order of gates if reverse)
     std::vector<HostPass> passes;
 };
@@ -110,8 +128,9 @@ struct Plan {
 // Build the pass structure of gates [g0, g1); taken in circuit order, or reversed for the
 // backward.
 // max_ops: at most that many ops per pass.
+// max_slots: at most that many gradient-carrying ops per register group.
 Plan make_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cbits, int low_fixed, bool reverse,
-               int reg_bits, int max_ops = kMaxPassOps);
+               int reg_bits, int max_ops = kMaxPassOps, int max_slots = kMaxGroupSlots);
 // Choose tile geometry for a state (tile qubits from the options, 0 = default).
 void tile_geometry(int n, int B, int dtype, bool backward, int* t, int* cbits, int* low_fixed);
 // The same for an explicit number of tile qubits (<= 0: default).
@@ -154,10 +173,13 @@ struct DevProgram {
     PGroupDesc* groups;
     double* mats;
 };
-const Plan& get_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse);
-// A plan with the given register bits and pass size (cached like get_plan's).
+// lam_bytes: bytes per element of the adjoint state (reverse plans size their register groups'
+// gradient buffers by it).
+const Plan& get_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse,
+                     int lam_bytes = 16);
+// A plan with the given register bits, pass size and group slots (cached like get_plan's).
 const Plan& get_plan_ex(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse, int reg_bits,
-                        int max_ops);
+                        int max_ops, int max_slots = kMaxGroupSlots);
 // dtype: the state's (forward) or the adjoint state's (backward) precision. With params null
 // the program is built for binding on the device (Program::binds); when c is the structure of a
 // fused circuit (fused_shape), parts and orig describe its multi-gate placeholders.

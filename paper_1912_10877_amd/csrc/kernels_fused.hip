@@ -46,6 +46,7 @@ struct PassArgs {
     // store_thread_bits(th) | sreg[r] (thread bit i of e moves to tile bit ssrc[i]).
     int ssrc[kMaxTileBits];
     uint32_t sreg[1 << kMaxRegBits];
+    int mslots;             // reverse passes: gradient-carrying ops per register group (at most)
 };
 
 __device__ __forceinline__ uint32_t swz(uint32_t e)
@@ -928,12 +929,6 @@ __global__ __launch_bounds__(512, sizeof(RP) == 4 ? 3 : 1) void k_pass_fwd(PassA
 }
 
 // ------------------------------------------------------------------------------ backward kernel
-// Entries of gradient partials per register group: one per 16-lane row and batch slot of the
-// tile (row sums), or one per thread in tiles of fewer than 16 threads.
-__host__ __device__ __forceinline__ int grad_entries(int nthr, int c)
-{
-    return nthr >= 16 ? (nthr >> 4) << c : nthr;
-}
 
 // Where the gradient partials of a reverse sweep go: reduce_partials' gpartial, B, pstride
 // and, for this tile, the column and the first batch slot.
@@ -944,14 +939,14 @@ struct GradOut {
 
 // The register groups and LDS ops of a reverse pass over the tile in LDS: psi (lp, FP64) and
 // lambda (ll, in RL), with every gradient partial reduced per group into go. tbase holds the
-// qubits outside the tile (for controls there); red0 holds two buffers of kMaxGroupSlots * E
+// qubits outside the tile (for controls there); red0 holds two buffers of mslots * E
 // partials (a group's partials are reduced after the barrier that ends it, while the next
 // group fills the other buffer). C0: tiles of one batch slot (c = 0).
 template <typename RL, bool C0>
 __device__ __forceinline__ void reverse_groups(double2* lp, vec2_t<RL>* ll, double* red0, const YAO_CONST POp* gops,
                                                const YAO_CONST PGroupDesc* ggrp, const PGroupDesc* groups,
                                                int ngroups, const double* mats, uint64_t tbase, int t, int c,
-                                               int nthr, int th, const GradOut& go)
+                                               int nthr, int th, int mslots, const GradOut& go)
 {
     constexpr int RB = kRegBitsBwd, N = 1 << RB;
     using VL = vec2_t<RL>;
@@ -962,7 +957,7 @@ __device__ __forceinline__ void reverse_groups(double2* lp, vec2_t<RL>* ll, doub
     int buf = 0;
     for (int gi = 0; gi < ngroups; ++gi) {
         const GroupCtl G = group_ctl_c(ggrp + gi);
-        double* red = red0 + buf * (kMaxGroupSlots * E);
+        double* red = red0 + buf * (mslots * E);
         int nslot = 0;
         if (G.lds) {
             const YAO_CONST POp* rec = gops + G.op0;
@@ -1104,7 +1099,7 @@ __global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
 
     const GradOut go{a.gpartial, a.B, a.pstride, (int)blockIdx.x, (int)blockIdx.y << c};
     reverse_groups<RL, C0>(lp, ll, red0, cptr(a.ops), cptr(a.groups), a.groups, a.ngroups, a.mats, tc.base, t, c,
-                           nthr, th, go);
+                           nthr, th, a.mslots, go);
 
     if (tc.bvalid) {
         const uint32_t sth = store_thread_bits(a, th, t - RB);
@@ -1245,7 +1240,7 @@ __global__ __launch_bounds__(512, 1) void k_small_circuit(const SmallCircuit* it
     __syncthreads();
     const GradOut go{it->grad, 1, 1, 0, 0};
     reverse_groups<double, true>(lp, ll, red0, cptr(it->rops), cptr(it->rgroups), it->rgroups, it->nrg, it->rmats, 0,
-                                 t, 0, nthr, th, go);
+                                 t, 0, nthr, th, kMaxGroupSlots, go);
 }
 
 size_t small_circuit_lds_bytes(int n)
@@ -1525,11 +1520,11 @@ int prepare_pass_kernels()
     return 0;
 }
 
-size_t pass_lds_bytes(bool bwd, int t, int c, int psi_bytes, int lam_bytes, int dm_words)
+size_t pass_lds_bytes(bool bwd, int t, int c, int psi_bytes, int lam_bytes, int dm_words, int mslots)
 {
     if (!bwd) return ((size_t)psi_bytes << t) + 16 * (size_t)dm_words;
     const int nthr = 1 << (t - kRegBitsBwd);
-    return ((size_t)(16 + lam_bytes) << t) + sizeof(double) * 2 * kMaxGroupSlots * (size_t)grad_entries(nthr, c);
+    return ((size_t)(16 + lam_bytes) << t) + sizeof(double) * 2 * mslots * (size_t)grad_entries(nthr, c);
 }
 
 // The tile geometry of a pass: tile qubits (ascending), the qubits outside the tile, and the
@@ -1572,10 +1567,12 @@ static void tile_args(PassArgs& a, int n, int B, int c, int t, const std::vector
 }
 
 int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, const POp* ops, const PGroupDesc* groups,
-                const double* mats, double* gpartial, int pstride, int n, int B, int c, int t, int group0,
+                const double* mats, double* gpartial, int pstride, int mslots, int n, int B, int c, int t, int group0,
                 int ngroups, const std::vector<int>& tile_qubits, const std::vector<int>& store_src, double flops,
                 int op_first, int nops, const double* dmats, int dm_words)
 {
+    if (bwd && (mslots < 1 || mslots > kMaxGroupSlots))
+        return set_error(YAO_EINVAL, "%d gradient slots per register group (1 .. %d)", mslots, kMaxGroupSlots);
     if (!store_src.empty() && (int)store_src.size() != t)
         return set_error(YAO_EINVAL, "store permutation of %zu bits for a tile of %d", store_src.size(), t);
     if (!store_src.empty()) {
@@ -1604,6 +1601,7 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
     a.ndm = dm_words;
     a.ngroups = ngroups;
     a.nops = nops;
+    a.mslots = mslots;
     tile_args(a, n, B, c, t, tile_qubits, bwd ? kRegBitsBwd : kRegBitsFwd, store_src);
     a.pstride = pstride > a.ntiles ? pstride : a.ntiles;
     const int Bc = 1 << c;
@@ -1614,7 +1612,7 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
     dim3 block(1 << (t - RBk));
     const int pb = bwd ? 16 : (psi_dtype == YAO_C64 ? 8 : 16);
     const int lb = bwd ? (lam_dtype == YAO_C64 ? 8 : 16) : 0;
-    const size_t lds = pass_lds_bytes(bwd, t, c, pb, lb, bwd ? 0 : dm_words);
+    const size_t lds = pass_lds_bytes(bwd, t, c, pb, lb, bwd ? 0 : dm_words, mslots);
     if (lds > 160 * 1024) return set_error(YAO_EINVAL, "tile of 2^%d needs %zu bytes of LDS", t, lds);
     hipStream_t st = stream();
     const int pi = prof_begin(bwd ? YAO_KF_PASS_BWD : YAO_KF_PASS_FWD);

@@ -153,10 +153,11 @@ void permute_tile(HostPass& pass, uint64_t T, int c, std::vector<int>& phys, std
 }  // namespace
 
 Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits, int low_fixed, bool reverse,
-               int reg_bits, int max_ops)
+               int reg_bits, int max_ops, int max_slots)
 {
     Plan P;
     P.reg_bits = reg_bits;
+    P.max_slots = max_slots;
     P.g0 = g0;
     P.g1 = g1;
     P.n = circ->n;
@@ -382,7 +383,7 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
                 const bool grad = is_param_kind(gr.kind) && gr.param >= 0;
                 uint64_t rb = 0;
                 for (int j = 0; j < k1; ++j) rb |= bit(tile_bit(gr.locs[j]));
-                if ((op.qmask & gblocked) || k1 > 1 || (grad && nslot >= kMaxGroupSlots)) {
+                if ((op.qmask & gblocked) || k1 > 1 || (grad && nslot >= max_slots)) {
                     gblocked |= op.qmask;
                     grest.push_back(oi);
                     continue;

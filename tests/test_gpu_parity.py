@@ -300,3 +300,32 @@ def test_fused_hea_deep(dtype):
     e, g, drift = yb.backward(s, yb.Circuit.from_workload(circ), params, yb.PauliSum.from_workload(H))
     assert abs(e[0] - e_ref[0]) <= (1e-10 if dtype == 1 else 1e-5)
     assert np.abs(g - g_ref).max() <= grad_tol(dtype, g_ref)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,B,tq", [(16, 1, 7), (15, 3, 6), (17, 1, 0)])
+def test_permuted_layouts_between_passes(dtype, n, B, tq):
+    """Deep layered circuits over tiles much narrower than the state: most passes store their
+    tile with qubits moved onto other index bits, and the plan must restore qubit q to bit q at
+    its end (also around a 5-qubit gate launched on its own in the reverse sweep)."""
+    yb.set_options(plain=0, tile_qubits=tq)
+    try:
+        circ = with_gate_of_width(w.hea_circuit(n, 5), 5, n)
+        H = w.heisenberg(n)
+        params = w.angles(n + 3, circ.nparams)
+        psi0 = w.random_state(n, B, n + 1)
+        s = yb.State(n, B, dtype)
+        s.upload(psi0)
+        yb.forward(s, yb.Circuit.from_workload(circ), params)
+        want = oracle.forward(circ, params, psi0)
+        assert np.abs(s.download() - want).max() <= amp_tol(dtype, len(circ.gates))
+        e_ref, g_ref, _ = oracle.adjoint(H, circ, params, psi0)
+        s.upload(psi0)
+        e, g, drift = yb.backward(s, yb.Circuit.from_workload(circ), params, yb.PauliSum.from_workload(H))
+        np.testing.assert_allclose(e, e_ref, atol=1e-10 if dtype == 1 else 1e-5)
+        assert np.abs(g - g_ref).max() <= grad_tol(dtype, g_ref)
+        assert drift <= (1e-11 if dtype == 1 else 1e-5)
+        assert np.abs(s.download() - want).max() <= amp_tol(dtype, len(circ.gates))
+    finally:
+        yb.set_options(tile_qubits=0)
