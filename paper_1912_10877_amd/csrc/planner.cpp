@@ -380,7 +380,7 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
                 const HostOp& op = P.ops[oi];
                 const GateRec& gr = circ->gates[op.gate];
                 const int k1 = gr.k;
-                const bool grad = is_param_kind(gr.kind) && gr.param >= 0;
+                const bool grad = reverse && is_param_kind(gr.kind) && gr.param >= 0;
                 uint64_t rb = 0;
                 for (int j = 0; j < k1; ++j) rb |= bit(tile_bit(gr.locs[j]));
                 if ((op.qmask & gblocked) || k1 > 1 || (grad && nslot >= max_slots)) {
