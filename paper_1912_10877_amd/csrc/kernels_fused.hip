@@ -343,6 +343,16 @@ template <int J, typename V, int N>
 __device__ __forceinline__ void pairs_cswap_ip(V (&x)[N], uint32_t ethr, const uint32_t (&er)[N], uint32_t cmask,
                                                uint32_t cval)
 {
+    if ((cmask & ~er[N - 1]) == 0) {
+        // Controls on register bits only (er[N - 1] holds them all): a pair is swapped in
+        // every lane or in none, so the pairs that fail them cost nothing.
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            if (a & (1 << J)) continue;
+            if ((er[a] & cmask) == cval) cswap_ip(x[a], x[a + (1 << J)], __builtin_amdgcn_read_exec());
+        }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < N; ++a) {
         if (a & (1 << J)) continue;
@@ -354,6 +364,16 @@ template <int J, int N>
 __device__ __forceinline__ void pairs_cswap_ip(double2 (&x)[N], double2 (&y)[N], uint32_t ethr,
                                                const uint32_t (&er)[N], uint32_t cmask, uint32_t cval)
 {
+    if ((cmask & ~er[N - 1]) == 0) {
+        // Controls on register bits only, as above.
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            if (a & (1 << J)) continue;
+            if ((er[a] & cmask) == cval)
+                cswap_ip(x[a], x[a + (1 << J)], y[a], y[a + (1 << J)], __builtin_amdgcn_read_exec());
+        }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < N; ++a) {
         if (a & (1 << J)) continue;
