@@ -227,6 +227,20 @@ int yao_profile_enable(int on);
  * real arithmetic of the gate applications). Synchronises. */
 int yao_profile_read(int family, int* launches, double* total_ms, double* algo_bytes, double* algo_flops);
 
+/* Planner check (host only) ----------------------------------------------------------- */
+
+/* Runs the pass plan of circuit c (forward, or the reverse sweep U^dagger in reverse gate order
+ * when reverse = 1) for a state of dtype dt and batch 1 over tiles of tile_qubits qubits (0:
+ * default) on the host, the way the pass kernels run it: tiles gathered from the index bits
+ * the plan's qubit layout gives each pass, every op applied from its device record on tile
+ * bits, tiles stored back through the pass's bit permutation. The start state is a seeded
+ * Gaussian vector; *max_err receives the largest amplitude difference from applying the
+ * gates one by one (Sec. "Representing Quantum Circuits": the chain as matrix product) and
+ * *npasses the number of passes. params: nparams host doubles (or null when there are none).
+ * At most 20 qubits; no GPU is used. */
+int yao_plan_selfcheck(const yao_circuit* c, const double* params, enum yao_dtype dt, int reverse, int tile_qubits,
+                       double* max_err, int* npasses);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,6 +69,7 @@ _SIGS = {
     "yao_batch_run": [I, P, P, P, P, P, P],
     "yao_profile_enable": [I],
     "yao_profile_read": [I, P, P, P, P],
+    "yao_plan_selfcheck": [P, P, I, I, I, P, P],
 }
 
 
@@ -324,3 +325,13 @@ def header_symbols(path=None):
     path = path or os.path.join(HERE, "..", "include", "yao.h")
     src = open(path).read()
     return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(yao_\w+)\s*\(", src, re.M)))
+
+
+def plan_selfcheck(circ: Circuit, params, dtype=0, reverse=False, tile_qubits=0):
+    """Host run of the circuit's pass plan (qubit layouts, permuted stores, records on tile bits)
+    against gate-by-gate application: returns (max amplitude error, number of passes)."""
+    p = _params(params)
+    err, npass = ctypes.c_double(), ctypes.c_int()
+    _check(lib().yao_plan_selfcheck(circ.h, _ptr(p), int(dtype), int(bool(reverse)), int(tile_qubits),
+                                    ctypes.byref(err), ctypes.byref(npass)))
+    return err.value, npass.value

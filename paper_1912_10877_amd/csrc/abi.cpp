@@ -409,4 +409,14 @@ int yao_profile_read(int family, int* launches, double* total_ms, double* algo_b
     return prof_read(family, launches, total_ms, algo_bytes, algo_flops);
 }
 
+int yao_plan_selfcheck(const yao_circuit* c, const double* params, enum yao_dtype dt, int reverse, int tile_qubits,
+                       double* max_err, int* npasses)
+{
+    if (!c || !max_err || !npasses) return set_error(YAO_EINVAL, "null argument");
+    if (dt != YAO_C64 && dt != YAO_C128) return set_error(YAO_EINVAL, "unknown dtype %d", (int)dt);
+    if (tile_qubits < 0 || tile_qubits > 14) return set_error(YAO_EINVAL, "tile_qubits must be 0..14");
+    if (c->nparams > 0 && !params) return set_error(YAO_EINVAL, "circuit takes %d parameters", c->nparams);
+    return yao::plan_selfcheck(c, params, dt, reverse, tile_qubits, max_err, npasses);
+}
+
 }  // extern "C"

@@ -30,6 +30,10 @@ const yao_circuit* fused_circuit(const yao_circuit* c, const double* params, int
 const yao_circuit* fused_shape(const yao_circuit* c, int width, const std::vector<FusedPart>** parts);
 void drop_fused(const yao_circuit* c);
 
+// Host run of a circuit's pass plan against gate-by-gate application (plan_check.cpp).
+int plan_selfcheck(const yao_circuit* c, const double* params, int dtype, int reverse, int tile_qubits, double* max_err,
+                   int* npasses);
+
 // Per-gate form.
 int forward_plain(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params);
 int backward_plain(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h, bool reduce_batch,
