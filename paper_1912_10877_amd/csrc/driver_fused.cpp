@@ -364,6 +364,8 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                                                                                                  : kBwdGenericClass;
                     }
                     op.var = g.k == 1 ? cls * P.reg_bits + op.rpos : 0;
+                    // The reverse Z-generator diagonal class leaves d0 to a phase of the tile.
+                    if (bwd && g.k == 1 && cls == 1 && !pdep) split_diag_phase(op.u);
                 }
                 prog.ops.push_back(op);
                 prog.pass_flops.back() += op_flops(op, bwd) / double(uint64_t(1) << g.nctrl);

@@ -68,11 +68,22 @@ struct POp {
     uint32_t cmask, cval;  // controls on tile bits
     uint64_t omask, oval;  // controls on qubits outside the tile
     double u[8];    // one-qubit matrix (forward U, backward U^dagger): re[4] then im[4]; in
-                    // forward programs of complex64 states the same entries as float[8]
+                    // forward programs of complex64 states the same entries as float[8]; for
+                    // reverse ops of the Z-generator diagonal class (var / 3 == 1) entry 3
+                    // holds d1 / d0 instead of d1 (split_diag_phase)
     int tpos[3];    // tile-bit positions of the targets of a k = 2, 3 op, in locs order
     int var;        // code path of a one-qubit op (see op_variant)
 };
 static_assert(sizeof(POp) == 128, "op record layout");
+
+// diag(d0, d1) as d0 * diag(1, d1 / d0): entry 3 of u (re[4] then im[4]) becomes d1 / d0.
+__host__ __device__ inline void split_diag_phase(double* u)
+{
+    const double n = u[0] * u[0] + u[4] * u[4];
+    const double rr = (u[3] * u[0] + u[7] * u[4]) / n, ri = (u[7] * u[0] - u[3] * u[4]) / n;
+    u[3] = rr;
+    u[7] = ri;
+}
 
 struct PGroupDesc {
     int rpos[kMaxRegBits];  // tile-bit positions of the register bits, ascending

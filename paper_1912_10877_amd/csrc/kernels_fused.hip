@@ -290,7 +290,12 @@ __device__ __forceinline__ void cswap_ip(double2& a, double2& b, double2& c, dou
                  : [m] "s"(m));
 }
 
-// An uncontrolled one-qubit op of structure TYPE (OT_RX, OT_DIAG or OT_DENSE) on register bit J.
+// diag(1, d) on a register bit: the reverse passes' Z-generator diagonal ops, whose first entry
+// is carried as a phase of the whole tile.
+constexpr int kDiagHigh = 100;
+
+// An uncontrolled one-qubit op of structure TYPE (OT_RX, OT_DIAG, kDiagHigh or OT_DENSE) on
+// register bit J.
 template <int J, int TYPE, typename RR, typename V, int N>
 __device__ __forceinline__ void pairs_ip(V (&x)[N], const RR* mr, const RR* mi)
 {
@@ -303,6 +308,8 @@ __device__ __forceinline__ void pairs_ip(V (&x)[N], const RR* mr, const RR* mi)
             rx_ip(p, q, mr[0], mi[1]);
         } else if constexpr (TYPE == OT_DIAG) {
             diag_ip(p, mr[0], mi[0]);
+            diag_ip(q, mr[3], mi[3]);
+        } else if constexpr (TYPE == kDiagHigh) {
             diag_ip(q, mr[3], mi[3]);
         } else {
             dense_ip(p, q, mr, mi);
@@ -963,7 +970,7 @@ struct GradOut {
 // partials (a group's partials are reduced after the barrier that ends it, while the next
 // group fills the other buffer). C0: tiles of one batch slot (c = 0).
 template <typename RL, bool C0>
-__device__ __forceinline__ void reverse_groups(double2* lp, vec2_t<RL>* ll, double* red0, const YAO_CONST POp* gops,
+__device__ __forceinline__ double2 reverse_groups(double2* lp, vec2_t<RL>* ll, double* red0, const YAO_CONST POp* gops,
                                                const YAO_CONST PGroupDesc* ggrp, const PGroupDesc* groups,
                                                int ngroups, const double* mats, uint64_t tbase, int t, int c,
                                                int nthr, int th, int mslots, const GradOut& go)
@@ -971,6 +978,10 @@ __device__ __forceinline__ void reverse_groups(double2* lp, vec2_t<RL>* ll, doub
     constexpr int RB = kRegBitsBwd, N = 1 << RB;
     using VL = vec2_t<RL>;
     const bool rows = nthr >= 16;
+    // Product of the first diagonal entries of the uncontrolled Z-generator ops applied so far:
+    // those ops apply diag(1, d1 / d0) to both states and leave d0, a phase common to every
+    // element of every tile, to the caller (gradients do not see a phase psi and lambda share).
+    double2 phase = make_double2(1.0, 0.0);
     const int E = grad_entries(nthr, c);
     const int ent = rows ? (th >> 4) * (1 << c) + (th & 15) : th;
     const bool stores = rows ? (th & 15) < (1 << c) : true;
@@ -1027,11 +1038,15 @@ __device__ __forceinline__ void reverse_groups(double2* lp, vec2_t<RL>* ll, doub
         pairs_ip<J, OT_RX>(x, m, m + 4);                                         \
         pairs_ip<J, OT_RX>(y, m, m + 4);                                         \
         break;                                                                   \
-    case 1 * kRegBitsBwd + J:                                                    \
+    case 1 * kRegBitsBwd + J: {                                                  \
         g = pairs_grad<J, false, GEN_Z>(x, y, m, m + 4, ethr, er, 0u, 0u);         \
-        pairs_ip<J, OT_DIAG>(x, m, m + 4);                                       \
-        pairs_ip<J, OT_DIAG>(y, m, m + 4);                                       \
+        pairs_ip<J, kDiagHigh>(x, m, m + 4);                                     \
+        pairs_ip<J, kDiagHigh>(y, m, m + 4);                                     \
+        const double pr = phase.x * m[0] - phase.y * m[4];                       \
+        phase.y = phase.x * m[4] + phase.y * m[0];                               \
+        phase.x = pr;                                                            \
         break;                                                                   \
+    }                                                                            \
     case 2 * kRegBitsBwd + J:                                                    \
         pairs_cswap_ip<J>(x, y, ethr, er, o.c.cmask, o.c.cval);                  \
         break;
@@ -1078,6 +1093,7 @@ __device__ __forceinline__ void reverse_groups(double2* lp, vec2_t<RL>* ll, doub
             buf ^= 1;
         }
     }
+    return phase;
 }
 
 // C0: tiles of one batch slot (c = 0), where every row-sum step applies. At most 168 VGPRs, so
@@ -1118,8 +1134,8 @@ __global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
     __syncthreads();
 
     const GradOut go{a.gpartial, a.B, a.pstride, (int)blockIdx.x, (int)blockIdx.y << c};
-    reverse_groups<RL, C0>(lp, ll, red0, cptr(a.ops), cptr(a.groups), a.groups, a.ngroups, a.mats, tc.base, t, c,
-                           nthr, th, a.mslots, go);
+    const double2 ph = reverse_groups<RL, C0>(lp, ll, red0, cptr(a.ops), cptr(a.groups), a.groups, a.ngroups,
+                                              a.mats, tc.base, t, c, nthr, th, a.mslots, go);
 
     if (tc.bvalid) {
         const uint32_t sth = store_thread_bits(a, th, t - RB);
@@ -1127,8 +1143,11 @@ __global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
         for (int r = 0; r < N; ++r) {
             const uint64_t off = tile_off<RB>(a, tc, r);
             const uint32_t e = swz(sth | a.sreg[r]);
-            gp[off] = lp[e];
-            gl[off] = ll[e];
+            const double2 v = lp[e];
+            const VL w = ll[e];
+            const double wx = (double)w.x, wy = (double)w.y;
+            gp[off] = make_double2(ph.x * v.x - ph.y * v.y, ph.x * v.y + ph.y * v.x);
+            gl[off] = mkv<VL, RL>((RL)(ph.x * wx - ph.y * wy), (RL)(ph.x * wy + ph.y * wx));
         }
     }
 }
@@ -1477,6 +1496,7 @@ __device__ void bind_one(POp* __restrict__ ops, const BindRec br, const BindFac*
             op.u[e] = ar[e];
             op.u[4 + e] = ai[e];
         }
+        if (br.mode == 2 && op.var / kRegBitsBwd == 1) split_diag_phase(op.u);
     }
 }
 

@@ -118,6 +118,9 @@ int run_passes(const Plan& P, const Program& prog, const yao_circuit* c, const d
                     std::vector<cd> M(D * D);
                     if (op.k == 1) {
                         for (int e = 0; e < 4; ++e) M[e] = cd(op.u[e], op.u[4 + e]);
+                        // Reverse Z-generator diagonal ops hold d1 / d0; the kernel applies d0
+                        // as a phase of the whole tile at the store.
+                        if (P.reverse && op.var / P.reg_bits == 1) M[3] *= M[0];
                     } else {
                         const double* m = prog.mats.data() + op.mat;
                         for (int e = 0; e < D * D; ++e) M[e] = cd(m[e], m[D * D + e]);
