@@ -6,7 +6,9 @@ imports nothing from it; circuits and observables come from the `workloads` modu
 only describes inputs.
 
 Finite differences and the parameter-shift rule (Sec. "Forward Mode", eq. shiftrule) are
-written here on top of the oracle's energy; they pin the oracle's adjoint gradient.
+written here on top of the oracle's energy; they pin the oracle's adjoint gradient. Time
+evolution (Sec. "Matrix Representation": time_evolve) is the exponential series of -iHt applied
+through the oracle's H psi.
 """
 from __future__ import annotations
 
@@ -17,7 +19,7 @@ import subprocess
 
 import numpy as np
 
-from workloads import Circuit, PauliSum
+from workloads import Circuit, Gate, PauliSum
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
@@ -70,6 +72,11 @@ def lib():
         L.orc_gate_deriv.argtypes = [P, d, P]
         L.orc_gate_deriv.restype = l
         L.orc_num_threads.restype = i
+        L.orc_permute_qubits.argtypes = [i, l, P, P, P]
+        L.orc_qft_at.argtypes = [i, l, P, i, P, i, l, P, P]
+        L.orc_probs.argtypes = [i, l, P, i, P, P]
+        L.orc_sample.argtypes = [i, l, P, i, P, l, P, P]
+        L.orc_collapse.argtypes = [i, l, P, i, P, P, P]
         _lib = L
     return _lib
 
@@ -248,3 +255,139 @@ def shift_grad(H, circ, params, psi0, which=None):
         pm[k] -= math.pi / 2
         out[k] = 0.5 * (energy(H, circ, pp, psi0) - energy(H, circ, pm, psi0))
     return out
+
+
+# --------------------------------------------------------------------------------------------
+# focus! / relax! (Sec. "Active qubits and environment qubits")
+# --------------------------------------------------------------------------------------------
+
+def permute_qubits(psi, n, perm):
+    """The register with qubit q moved to position perm[q]."""
+    psi, B = _state(psi, n)
+    perm = np.ascontiguousarray(np.asarray(perm, np.int32))
+    if sorted(perm.tolist()) != list(range(n)):
+        raise ValueError("perm must be a permutation of 0..n-1")
+    out = np.empty_like(psi)
+    lib().orc_permute_qubits(n, B, _ptr(psi), _ptr(out), _ptr(perm))
+    return out
+
+
+def focus_perm(n, locs):
+    """focus!(reg, locs): locs[j] becomes active qubit j; the other qubits follow in order."""
+    locs = list(locs)
+    rest = [q for q in range(n) if q not in locs]
+    perm = [0] * n
+    for j, q in enumerate(locs + rest):
+        perm[q] = j
+    return perm
+
+
+def focus(psi, n, locs):
+    return permute_qubits(psi, n, focus_perm(n, locs))
+
+
+def relax(psi, n, locs):
+    """relax!(reg, locs): the inverse of focus!(reg, locs)."""
+    fp = focus_perm(n, locs)
+    inv = [0] * n
+    for q, j in enumerate(fp):
+        inv[j] = q
+    return permute_qubits(psi, n, inv)
+
+
+# --------------------------------------------------------------------------------------------
+# QFT on a set of qubits (Listing "QFT circuit"; App. "Extending QBIR: emulating QFT circuit")
+# --------------------------------------------------------------------------------------------
+
+def qft(psi, n, locs, inverse=False, idx=None):
+    """QFT (or its inverse) on the qubits locs by its matrix definition; idx: the output
+    indices to compute (all when None). Returns [len(idx)][B]."""
+    psi, B = _state(psi, n)
+    locs_a = np.ascontiguousarray(np.asarray(locs, np.int32))
+    idx = np.arange(1 << n, dtype=np.int64) if idx is None else np.ascontiguousarray(np.asarray(idx, np.int64))
+    out = np.zeros((len(idx), B), np.complex128)
+    lib().orc_qft_at(n, B, _ptr(psi), len(locs_a), _ptr(locs_a), int(bool(inverse)), len(idx), _ptr(idx), _ptr(out))
+    return out
+
+
+# --------------------------------------------------------------------------------------------
+# measure / measure! (Listing "instruct! and measure")
+# --------------------------------------------------------------------------------------------
+
+def probs(psi, n, locs):
+    """[B][2^k] probabilities of the outcomes of the qubits locs (locs[j] -> bit j)."""
+    psi, B = _state(psi, n)
+    locs_a = np.ascontiguousarray(np.asarray(locs, np.int32))
+    out = np.zeros((B, 1 << len(locs_a)))
+    lib().orc_probs(n, B, _ptr(psi), len(locs_a), _ptr(locs_a), _ptr(out))
+    return out
+
+
+def sample(psi, n, locs, u):
+    """Outcomes [B][nshots] for the uniform numbers u [B][nshots] by inverse-CDF sampling."""
+    psi, B = _state(psi, n)
+    locs_a = np.ascontiguousarray(np.asarray(locs, np.int32))
+    u = np.ascontiguousarray(np.asarray(u, np.float64).reshape(B, -1))
+    out = np.zeros(u.shape, np.int64)
+    lib().orc_sample(n, B, _ptr(psi), len(locs_a), _ptr(locs_a), u.shape[1], _ptr(u), _ptr(out))
+    return out
+
+
+def collapse(psi, n, locs, outcome):
+    """measure! after the outcome is known: (projected and renormalised state, p[B])."""
+    psi, B = _state(psi, n)
+    psi = psi.copy()
+    locs_a = np.ascontiguousarray(np.asarray(locs, np.int32))
+    oc = np.ascontiguousarray(np.asarray(outcome, np.int64).reshape(B))
+    p = np.zeros(B)
+    lib().orc_collapse(n, B, _ptr(psi), len(locs_a), _ptr(locs_a), _ptr(oc), _ptr(p))
+    return psi, p
+
+
+# --------------------------------------------------------------------------------------------
+# Time evolution exp(-iHt) psi (Sec. "Matrix Representation", time_evolve)
+# --------------------------------------------------------------------------------------------
+
+def time_evolve(H: PauliSum, psi, t):
+    """exp(-i H t) psi by the exponential series: t is cut into m equal steps with
+    |dt| * sum_t |c_t| <= 1/2 (sum |c_t| bounds the spectral norm of H), and each step sums
+    (-i H dt)^j psi / j! until the term falls below 1e-18 of the partial sum."""
+    psi, B = _state(psi, H.n)
+    bound = float(np.abs(np.asarray(H.coef, np.float64)).sum())
+    m = max(1, int(math.ceil(abs(t) * bound / 0.5)))
+    dt = t / m
+    v = psi.copy()
+    for _ in range(m):
+        term = v.copy()
+        acc = v.copy()
+        for j in range(1, 200):
+            term = (-1j * dt / j) * hpsi(H, term)
+            acc += term
+            if np.abs(term).max() <= 1e-18 * max(1e-300, np.abs(acc).max()):
+                break
+        v = acc
+    return v
+
+
+# --------------------------------------------------------------------------------------------
+# Faithful gradient of every gate occurrence (Sec. "Forward Mode", eq. shiftrule)
+# --------------------------------------------------------------------------------------------
+
+def shift_grad_gates(H, circ, params, psi0):
+    """grad[B][nparams]: for every parametrised gate occurrence k with parameter p,
+    (E(angle of gate k + pi/2) - E(angle of gate k - pi/2)) / 2 is added to grad[p] (only that
+    occurrence shifted, so a shared parameter gets the sum over its gates)."""
+    params = np.asarray(params, np.float64)
+    psi, B = _state(psi0, circ.n)
+    P = circ.nparams
+    grad = np.zeros((B, P))
+    for k, g in enumerate(circ.gates):
+        if g.param < 0:
+            continue
+        gates = list(circ.gates)
+        gates[k] = Gate(g.kind, g.locs, ctrls=g.ctrls, cvals=g.cvals, param=P, theta=g.theta, G=g.G)
+        c2 = Circuit(circ.n, gates, P + 1)
+        ep = energy(H, c2, np.append(params, params[g.param] + math.pi / 2), psi)
+        em = energy(H, c2, np.append(params, params[g.param] - math.pi / 2), psi)
+        grad[:, g.param] += 0.5 * (ep - em)
+    return grad

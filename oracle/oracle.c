@@ -162,7 +162,7 @@ void orc_apply_op(int n, long B, const cplx* in, cplx* out, const cplx* M, int k
 {
     const long N = 1L << n;
     const long d = 1L << k;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((1L << n) * B >= (1L << 14))
     for (long i = 0; i < N; ++i) {
         int pass = 1;
         for (int m = 0; m < nctrl; ++m)
@@ -338,4 +338,147 @@ void orc_adjoint(int n, long B, const cplx* psi0, int ngates, const orc_gate* ga
     }
     if (psi0_back) memcpy(psi0_back, psi, sizeof(cplx) * len);
     free(res); free(dpsi); free(bar); free(prev); free(psi);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Qubit management: focus! / relax! (Sec. "Active qubits and environment qubits").       */
+/* ------------------------------------------------------------------------------------ */
+
+/* out = the register with qubit q moved to position perm[q]: for every index i, the index i'
+ * whose bit perm[q] is bit q of i receives in[i]. perm is a permutation of 0..n-1. */
+void orc_permute_qubits(int n, long B, const cplx* in, cplx* out, const int* perm)
+{
+    const long N = 1L << n;
+#pragma omp parallel for schedule(static) if ((1L << n) * B >= (1L << 14))
+    for (long i = 0; i < N; ++i) {
+        long ip = 0;
+        for (int q = 0; q < n; ++q) ip |= ((i >> q) & 1L) << perm[q];
+        for (long b = 0; b < B; ++b) out[ip * B + b] = in[i * B + b];
+    }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Quantum Fourier transform on a set of qubits (Listing "QFT circuit", App. "Extending    */
+/* QBIR: emulating QFT circuit").                                                          */
+/* ------------------------------------------------------------------------------------ */
+
+/* Bits of the locs of index i, locs[j] -> bit j. */
+static long sub_index(long i, int k, const int* locs)
+{
+    long r = 0;
+    for (int j = 0; j < k; ++j) r |= ((i >> locs[j]) & 1L) << j;
+    return r;
+}
+
+static long with_sub_index(long i, int k, const int* locs, long s)
+{
+    for (int j = 0; j < k; ++j) {
+        i &= ~(1L << locs[j]);
+        i |= ((s >> j) & 1L) << locs[j];
+    }
+    return i;
+}
+
+static long reverse_bits(long x, int k)
+{
+    long r = 0;
+    for (int j = 0; j < k; ++j) r |= ((x >> j) & 1L) << (k - 1 - j);
+    return r;
+}
+
+/* The QFT on the k qubits locs as a matrix acting on the sub-index x = sum_j bit(locs[j]) 2^j:
+ *   F[y][x] = 2^{-k/2} exp(+2 pi i rev(x) y / 2^k)     (the paper's circuit: the emulation
+ * reverses the qubit order, then applies the unitary inverse DFT), and its inverse
+ *   F^dagger[x][y] = 2^{-k/2} exp(-2 pi i rev(x) y / 2^k).
+ * Output element idx[m] (every batch slot) is the sum over the sub-index of the row of F (or
+ * F^dagger) for idx[m]'s own sub-index. out is [nidx][B]. The phase rev(x) y is reduced mod 2^k
+ * in integers before the exponential. */
+void orc_qft_at(int n, long B, const cplx* psi, int k, const int* locs, int inverse, long nidx, const long* idx,
+                cplx* out)
+{
+    const long d = 1L << k;
+    const double norm = 1.0 / sqrt((double)d);
+    (void)n;
+#pragma omp parallel for schedule(static) if ((1L << n) * B >= (1L << 14))
+    for (long m = 0; m < nidx; ++m) {
+        const long i = idx[m];
+        const long r = sub_index(i, k, locs);
+        for (long b = 0; b < B; ++b) {
+            cplx acc = 0;
+            for (long s = 0; s < d; ++s) {
+                long ph;
+                if (!inverse) ph = (reverse_bits(s, k) * r) & (d - 1);       /* F[r][s] */
+                else ph = (d - ((reverse_bits(r, k) * s) & (d - 1))) & (d - 1);  /* F^dagger[r][s] */
+                acc += cexp(I * 2.0 * M_PI * (double)ph / (double)d) * psi[with_sub_index(i, k, locs, s) * B + b];
+            }
+            out[m * B + b] = norm * acc;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Measurement (Listing "instruct! and measure": measure and measure!).                   */
+/* ------------------------------------------------------------------------------------ */
+
+/* probs[b][x] = sum over indices i whose locs bits read x of |psi[i][b]|^2, in index order. */
+void orc_probs(int n, long B, const cplx* psi, int k, const int* locs, double* probs)
+{
+    const long N = 1L << n, d = 1L << k;
+    memset(probs, 0, sizeof(double) * B * d);
+    for (long i = 0; i < N; ++i) {
+        const long x = sub_index(i, k, locs);
+        for (long b = 0; b < B; ++b) {
+            const cplx a = psi[i * B + b];
+            probs[b * d + x] += creal(a) * creal(a) + cimag(a) * cimag(a);
+        }
+    }
+}
+
+/* measure(reg; nshots): outcome of shot s in slot b is the smallest x whose cumulative
+ * probability cdf[x] = sum_{y <= x} p[y] (summed in order of y) exceeds u[b][s] * cdf[last],
+ * for uniform numbers u in [0, 1) supplied by the caller (inverse-CDF sampling). */
+void orc_sample(int n, long B, const cplx* psi, int k, const int* locs, long nshots, const double* u, long* out)
+{
+    const long d = 1L << k;
+    double* p = malloc(sizeof(double) * B * d);
+    double* cdf = malloc(sizeof(double) * d);
+    orc_probs(n, B, psi, k, locs, p);
+    for (long b = 0; b < B; ++b) {
+        double run = 0;
+        for (long x = 0; x < d; ++x) {
+            run += p[b * d + x];
+            cdf[x] = run;
+        }
+        for (long s = 0; s < nshots; ++s) {
+            const double target = u[b * nshots + s] * cdf[d - 1];
+            long lo = 0, hi = d - 1;  /* smallest x with cdf[x] > target; cdf[d-1] > target */
+            while (lo < hi) {
+                long mid = (lo + hi) / 2;
+                if (cdf[mid] > target) hi = mid;
+                else lo = mid + 1;
+            }
+            out[b * nshots + s] = lo;
+        }
+    }
+    free(cdf);
+    free(p);
+}
+
+/* measure!: project slot b onto the outcome x_b of the locs and renormalise:
+ * psi[i][b] <- psi[i][b] / sqrt(p_b) where the locs bits of i read x_b, else 0. p_out[b]
+ * receives p_b. */
+void orc_collapse(int n, long B, cplx* psi, int k, const int* locs, const long* outcome, double* p_out)
+{
+    const long N = 1L << n, d = 1L << k;
+    double* p = malloc(sizeof(double) * B * d);
+    orc_probs(n, B, psi, k, locs, p);
+    for (long i = 0; i < N; ++i) {
+        const long x = sub_index(i, k, locs);
+        for (long b = 0; b < B; ++b) {
+            const double pb = p[b * d + outcome[b]];
+            psi[i * B + b] = x == outcome[b] ? psi[i * B + b] / sqrt(pb) : 0;
+        }
+    }
+    for (long b = 0; b < B; ++b) p_out[b] = p[b * d + outcome[b]];
+    free(p);
 }

@@ -438,3 +438,214 @@ def test_haar_su2_inputs_are_special_unitary():
         U = w.haar_su2(rng)
         np.testing.assert_allclose(U @ U.conj().T, np.eye(2), atol=1e-14)
         assert abs(np.linalg.det(U) - 1) < 1e-14
+
+
+# ---------------------------------------------------------------------------------------
+# Qubit management, QFT emulation, measurement, time evolution, faithful gradient.
+# ---------------------------------------------------------------------------------------
+
+def numpy_permute(psi, n, perm):
+    """Qubit q -> position perm[q] through numpy's transpose of the [2]*n tensor (tensor axis
+    a holds qubit n-1-a)."""
+    B = psi.shape[1]
+    t = psi.reshape([2] * n + [B])
+    axes = [0] * n
+    for q in range(n):
+        axes[n - 1 - perm[q]] = n - 1 - q
+    return np.transpose(t, axes + [n]).reshape(1 << n, B)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_permute_qubits_matches_numpy_transpose(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 7))
+    perm = rng.permutation(n).tolist()
+    psi = w.random_state(n, 3, seed)
+    np.testing.assert_array_equal(oracle.permute_qubits(psi, n, perm), numpy_permute(psi, n, perm))
+
+
+def test_focus_relax_listing_example():
+    """Listing "focus! and relax!": focus!(reg, (3,6,1,2)) on a 10-qubit register, qft(4) on
+    the active qubits, relax! back, equals the QFT circuit placed on those qubits."""
+    n, locs = 10, [2, 5, 0, 1]  # 1-based (3, 6, 1, 2)
+    psi = w.random_state(n, 2, 77)
+    f = oracle.focus(psi, n, locs)
+    # the 4 active qubits are the lowest; the QFT circuit acts on them
+    q4 = w.qft_circuit(4)
+    circ_low = w.Circuit(n, list(q4.gates), 0)
+    got = oracle.relax(oracle.forward(circ_low, None, f), n, locs)
+    placed = w.Circuit(n, [w.Gate(g.kind, tuple(locs[q] for q in g.locs), tuple(locs[c] for c in g.ctrls), g.cvals,
+                                  theta=g.theta) for g in q4.gates], 0)
+    np.testing.assert_allclose(got, oracle.forward(placed, None, psi), atol=1e-13)
+    np.testing.assert_allclose(oracle.relax(f, n, locs), psi, atol=0)
+    # active qubit j of the focused register is qubit locs[j] of the original
+    x = w.zero_state(n)
+    x[:, 0] = 0
+    x[(1 << 5) | (1 << 1), 0] = 1  # qubits 5 and 1 set
+    fx = oracle.focus(x, n, locs)
+    assert np.argmax(np.abs(fx[:, 0])) == (1 << 1) | (1 << 3)
+
+
+@pytest.mark.parametrize("n,locs", [(4, [0, 1, 2, 3]), (6, [5, 1, 3]), (7, [2, 6, 0, 4, 1])])
+def test_qft_definition_matches_circuit_and_fft(n, locs):
+    """The QFT by its matrix definition on locs equals the gate circuit of Listing "QFT circuit"
+    placed on locs, and on all qubits equals sqrt(N) ifft after reversing the qubit order
+    (App. "Extending QBIR", with numpy's FFT); the inverse undoes it."""
+    psi = w.random_state(n, 2, n + len(locs))
+    k = len(locs)
+    qk = w.qft_circuit(k)
+    placed = w.Circuit(n, [w.Gate(g.kind, tuple(locs[q] for q in g.locs), tuple(locs[c] for c in g.ctrls), g.cvals,
+                                  theta=g.theta) for g in qk.gates], 0)
+    got = oracle.qft(psi, n, locs)
+    np.testing.assert_allclose(got, oracle.forward(placed, None, psi), atol=1e-13)
+    np.testing.assert_allclose(oracle.qft(got, n, locs, inverse=True), psi, atol=1e-13)
+    if locs == list(range(n)):
+        N = 1 << n
+        perm = np.array([bit_reverse(i, n) for i in range(N)])
+        for b in range(2):
+            np.testing.assert_allclose(got[:, b], math.sqrt(N) * np.fft.ifft(psi[perm, b]), atol=1e-13)
+    idx = [3, 17 % (1 << n), (1 << n) - 1]
+    np.testing.assert_allclose(oracle.qft(psi, n, locs, idx=idx), got[idx], atol=0)
+
+
+def test_measure_listing_example():
+    """Listing "instruct! and measure": X on (1-based) qubit 2 of zero_state(4); three shots all
+    read 0010."""
+    psi = oracle.forward(w.Circuit(4, [w.Gate("X", (1,))], 0), None, w.zero_state(4))
+    out = oracle.sample(psi, 4, [0, 1, 2, 3], np.array([[0.0, 0.37, 0.999]]))
+    assert out.tolist() == [[0b0010] * 3]
+
+
+def test_probs_closed_forms():
+    n = 5
+    ghz = oracle.forward(w.ghz_circuit(n), None, w.zero_state(n))
+    p = oracle.probs(ghz, n, list(range(n)))[0]
+    want = np.zeros(1 << n)
+    want[0] = want[-1] = 0.5
+    np.testing.assert_allclose(p, want, atol=1e-15)
+    np.testing.assert_allclose(oracle.probs(ghz, n, [3, 1])[0], [0.5, 0, 0, 0.5], atol=1e-15)
+    # product state Rx(a_q)|0>: P(bit q = 1) = sin^2(a_q / 2), marginals multiply
+    a = np.random.default_rng(3).uniform(0, 2 * math.pi, n)
+    circ = w.Circuit(n, [w.Gate("Rx", (q,), theta=a[q]) for q in range(n)], 0)
+    psi = oracle.forward(circ, None, w.zero_state(n))
+    locs = [4, 0, 2]
+    p1 = np.sin(a / 2) ** 2
+    want = np.array([np.prod([p1[q] if (x >> j) & 1 else 1 - p1[q] for j, q in enumerate(locs)])
+                     for x in range(8)])
+    np.testing.assert_allclose(oracle.probs(psi, n, locs)[0], want, atol=1e-15)
+
+
+def test_probs_and_sampling_rule():
+    """probs against |psi|^2 summed with numpy; the inverse-CDF rule on a distribution with
+    zeros (p = 1/4 at outcomes 0, 2, 3, 5, so the CDF is exact): zero-probability outcomes never
+    come out, and u on a CDF step moves to the next outcome; shot frequencies of a random state
+    within 5 sigma."""
+    n = 6
+    psi = w.random_state(n, 2, 12)
+    locs = [1, 4]
+    t = (np.abs(psi) ** 2).reshape([2] * n + [2])
+    want = np.zeros((2, 4))
+    for i in range(1 << n):
+        x = ((i >> 1) & 1) | (((i >> 4) & 1) << 1)
+        want[:, x] += np.abs(psi[i]) ** 2
+    np.testing.assert_allclose(oracle.probs(psi, n, locs), want, atol=1e-15)
+    amp = np.array([0.5, 0, 0.5, 0.5, 0, 0.5, 0, 0])[:, None]  # p = 1/4 at 0, 2, 3, 5: exact
+    u = np.array([[0.0, 0.2499, 0.25, 0.5, 0.74, 0.75, 0.999]])
+    assert oracle.sample(amp, 3, [0, 1, 2], u).tolist() == [[0, 0, 2, 3, 3, 5, 5]]
+    shots = 200000
+    u = np.random.default_rng(7).random((2, shots))
+    out = oracle.sample(psi, n, [0, 2, 5], u)
+    p = oracle.probs(psi, n, [0, 2, 5])
+    for b in range(2):
+        freq = np.bincount(out[b], minlength=8) / shots
+        assert np.all(np.abs(freq - p[b]) <= 5 * np.sqrt(p[b] * (1 - p[b]) / shots) + 1e-12)
+
+
+def test_collapse_projects_and_renormalises():
+    n = 7
+    psi = w.random_state(n, 3, 31)
+    locs = [6, 2]
+    outcome = [1, 3, 0]
+    post, p = oracle.collapse(psi, n, locs, outcome)
+    pr = oracle.probs(psi, n, locs)
+    np.testing.assert_allclose(p, [pr[b, outcome[b]] for b in range(3)], atol=1e-15)
+    np.testing.assert_allclose(np.sum(np.abs(post) ** 2, axis=0), 1.0, atol=1e-14)
+    pp = oracle.probs(post, n, locs)
+    for b in range(3):
+        assert abs(pp[b, outcome[b]] - 1) < 1e-14
+        keep = [i for i in range(1 << n) if (((i >> 6) & 1) | (((i >> 2) & 1) << 1)) == outcome[b]]
+        np.testing.assert_allclose(post[keep, b], psi[keep, b] / math.sqrt(p[b]), atol=1e-15)
+
+
+def dense_pauli_sum(H):
+    n = H.n
+    M = np.zeros((1 << n, 1 << n), complex)
+    for c, x, z in zip(H.coef, H.xmask, H.zmask):
+        ops = []
+        for q in range(n):
+            bx, bz = (int(x) >> q) & 1, (int(z) >> q) & 1
+            ops.append(PAULI["Y" if bx and bz else ("X" if bx else ("Z" if bz else "I"))])
+        M += c * kron_list(ops)
+    return M
+
+
+@pytest.mark.parametrize("n,t", [(4, 0.1), (4, 1.3), (6, 0.7)])
+def test_time_evolution_against_expm(n, t):
+    """exp(-iHt) psi by the exponential series against scipy's expm of the dense H."""
+    rng = np.random.default_rng(n)
+    H = w.pauli_sum(n, [(float(rng.normal()), "".join(rng.choice(list("IXYZ"), n))) for _ in range(3 * n)])
+    psi = w.random_state(n, 2, 5)
+    want = scipy.linalg.expm(-1j * t * dense_pauli_sum(H)) @ psi
+    np.testing.assert_allclose(oracle.time_evolve(H, psi, t), want, atol=1e-12)
+
+
+def test_time_evolution_closed_forms_and_invariants():
+    n = 8
+    h = np.random.default_rng(1).normal(size=n)
+    Hz = w.pauli_sum(n, [(h[q], "I" * q + "Z" + "I" * (n - q - 1)) for q in range(n)])
+    psi = w.random_state(n, 1, 3)
+    t = 2.1
+    phase = np.array([np.exp(-1j * t * sum(h[q] * (1 - 2 * ((i >> q) & 1)) for q in range(n))) for i in range(1 << n)])
+    np.testing.assert_allclose(oracle.time_evolve(Hz, psi, t)[:, 0], phase * psi[:, 0], atol=1e-12)
+    H = w.heisenberg(n)
+    a = oracle.time_evolve(H, psi, 0.4)
+    b = oracle.time_evolve(H, oracle.time_evolve(H, psi, 0.25), 0.15)
+    np.testing.assert_allclose(a, b, atol=1e-12)
+    assert abs(np.linalg.norm(a) - 1) < 1e-12
+    assert abs(oracle.expect(H, a)[0][0] - oracle.expect(H, psi)[0][0]) < 1e-11
+
+
+def test_shift_rule_per_gate_occurrence():
+    """Every gate occurrence shifted on its own: with unshared parameters this is the shift rule
+    of the oracle; with a parameter shared by several uncontrolled rotations it is the exact
+    derivative (finite differences), where shifting the parameter everywhere at once is not."""
+    n = 4
+    circ = w.hea_circuit(n, 2)
+    params = w.angles(8, circ.nparams)
+    psi0 = w.random_state(n, 2, 8)
+    sg = oracle.shift_grad_gates(w.heisenberg(n), circ, params, psi0)
+    ref = oracle.shift_grad(w.heisenberg(n), circ, params, psi0)
+    for p in range(circ.nparams):
+        np.testing.assert_allclose(sg[:, p], ref[p], atol=1e-13)
+    shared = w.Circuit(n, [w.Gate(g.kind, g.locs, g.ctrls, g.cvals, param=(g.param % 5) if g.param >= 0 else -1)
+                           for g in circ.gates], 5)
+    p5 = w.angles(9, 5)
+    sg = oracle.shift_grad_gates(w.heisenberg(n), shared, p5, psi0)
+    fd = oracle.fd_grad(w.heisenberg(n), shared, p5, psi0, h=1e-5)
+    for p in range(5):
+        np.testing.assert_allclose(sg[:, p], fd[p], atol=1e-8)
+    naive = oracle.shift_grad(w.heisenberg(n), shared, p5, psi0)
+    assert max(abs(naive[p][0] - fd[p][0]) for p in range(5)) > 1e-3
+
+
+def test_adjoint_at_20_qubits_matches_stored_differences():
+    """The 20-qubit differentiation workload: the oracle's adjoint gradient (computed here)
+    against central differences and the shift rule of 24 seeded parameters, both taken from
+    oracle energies alone (tests/golden/make_golden.py fd20)."""
+    gold = read_golden("fd20.txt")
+    n, depth = 20, 20
+    circ = w.hea_circuit(n, depth)
+    e, g, _ = oracle.adjoint(w.heisenberg(n), circ, w.angles(2, circ.nparams), w.zero_state(n))
+    idx = [int(k) for k in gold["index"]]
+    np.testing.assert_allclose(g[0, idx], gold["shift"], atol=1e-10)
+    np.testing.assert_allclose(g[0, idx], gold["fd"], atol=1e-6)
