@@ -70,9 +70,10 @@ enum yao_gate {
 /* Backward strategies. REVERSIBLE uncomputes the state with inverse gates (constant memory
  * in depth, Sec. "Reverse Mode"). CHECKPOINT cuts the circuit into segments of
  * checkpoint_every gates, keeps the forward state at every segment end and restarts the
- * reverse sweep of each segment from it (memory grows with depth). AUTO keeps the same
- * states but restarts from one only where the uncomputed state differs from it by more
- * than drift_tol. */
+ * reverse sweep of each segment from it (memory grows with depth). AUTO runs the reversible
+ * sweep (constant memory) and, when the uncomputed input differs from the input by more than
+ * drift_tol, restores the input and runs the CHECKPOINT sweep instead; only then are
+ * checkpoints allocated. */
 enum yao_grad_mode { YAO_GRAD_REVERSIBLE = 0, YAO_GRAD_CHECKPOINT = 1, YAO_GRAD_AUTO = 2 };
 
 /* Execution options (process-wide; set before the calls they should affect).
@@ -84,7 +85,7 @@ enum yao_grad_mode { YAO_GRAD_REVERSIBLE = 0, YAO_GRAD_CHECKPOINT = 1, YAO_GRAD_
  *                    2..5 = gates folded into dense blocks of up to that many qubits (the
  *                    reverse sweep always takes the gates one by one).
  *   checkpoint_every gates per segment in CHECKPOINT / AUTO mode (0 = max(sqrt(#gates), 4n)).
- *   drift_tol        max |psi_uncomputed - psi_stored| accepted by AUTO before falling back
+ *   drift_tol        max |psi_0 uncomputed - psi_0| accepted by AUTO before falling back
  *                    (0 = 1e-5 for complex64 states, 1e-10 for complex128). In REVERSIBLE
  *                    mode a drift_tol > 0 makes yao_backward return YAO_EDRIFT when the
  *                    uncomputed input differs from the input by more than drift_tol (the
@@ -166,6 +167,55 @@ int yao_hpsi(const yao_state* s, const yao_pauli_sum* h, yao_state* out, double*
  * dtypes may differ. Synchronises. */
 int yao_inner(const yao_state* a, const yao_state* b, double* re, double* im);
 
+/* Qubit management and the QFT (f4) ------------------------------------------------------- */
+
+/* dst = src with qubit q moved to index bit perm[q] (perm: a permutation of 0..n-1); the
+ * building block of focus! / relax! (Sec. "Active qubits and environment qubits"). src and dst
+ * must match in n, batch and dtype; dst == src permutes in place (through a library buffer of
+ * the state's size). Batch * element bytes <= 16 KiB. */
+int yao_permute_qubits(const yao_state* src, yao_state* dst, const int* perm);
+/* focus!(reg, locs): qubit locs[j] becomes qubit j (the active qubits, in the given order) and
+ * the other qubits follow in ascending order; relax! with the same locs undoes it. In place;
+ * 1 <= k <= n distinct locs. */
+int yao_focus(yao_state* s, const int* locs, int k);
+int yao_relax(yao_state* s, const int* locs, int k);
+/* QFT on the k qubits locs (locs[j] = bit j of the transform's index x), in place (App.
+ * "Extending QBIR: emulating QFT circuit"): out[y] = 2^{-k/2} sum_x exp(2 pi i rev_k(x) y / 2^k)
+ * psi[x], which is the QFT circuit of Listing "QFT circuit" on those qubits (no final swaps),
+ * i.e. the paper's emulation by reversing the qubit order and applying the unitary inverse
+ * DFT. inverse = 1 applies the adjoint. Computed by in-place radix-2 stages in LDS tiles (a
+ * few passes over the state), not by gates. Batch * element bytes <= 16 KiB. */
+int yao_qft(yao_state* s, const int* locs, int k, int inverse);
+
+/* Time evolution (f3) --------------------------------------------------------------------- */
+
+/* psi_b <- exp(-i H t) psi_b for every slot (time_evolve of Sec. "Matrix Representation"), by
+ * the Krylov (Lanczos) method: H is applied to the register krylov_dim times per substep (the
+ * H psi tile passes; 0 = 30 vectors, at most 64), the projected tridiagonal problem is
+ * exponentiated on the host, and the substep is halved until the error estimate
+ * |psi| beta_m |(exp(-i tau T) e_1)_m| <= tol (0 = 1e-12 for complex128, 1e-6 for complex64).
+ * Needs krylov_dim + 2 state-sized library buffers. nsteps (may be NULL) receives the number of
+ * substeps. Synchronises. */
+int yao_time_evolve(yao_state* s, const yao_pauli_sum* h, double t, double tol, int krylov_dim, int* nsteps);
+
+/* Measurement (f2) ---------------------------------------------------------------------- */
+
+/* Outcomes of the k qubits locs are x = sum_j bit(locs[j]) 2^j (1 <= k <= min(n, 30)); every
+ * batch slot is measured on its own (Sec. "Batched Quantum Registers"). Probabilities are summed
+ * in FP64 in a fixed order, so results repeat bit for bit. Batch * element bytes <= 16 KiB.
+ *
+ * probs[b * 2^k + x] = sum of |psi_b[i]|^2 over the indices i whose locs read x. Synchronises. */
+int yao_probs(const yao_state* s, const int* locs, int k, double* probs);
+/* measure(reg; nshots) (Listing "instruct! and measure"): shot j of slot b is the smallest x
+ * with C_b(x) > u[b * nshots + j] * C_b(2^k - 1), C_b the cumulative sums of the probabilities in
+ * the order of x (inverse-CDF sampling). The caller supplies the uniform numbers u in [0, 1)
+ * (YAO_EINVAL otherwise); out[b * nshots + j] receives x. The state is unchanged. Synchronises. */
+int yao_measure(const yao_state* s, const int* locs, int k, int nshots, const double* u, uint64_t* out);
+/* measure!: one shot per slot from u[b] as in yao_measure, then slot b is projected onto its
+ * outcome and renormalised (amplitudes whose locs read x_b divided by sqrt(p_b), the others
+ * set to 0). out[b] = x_b; prob[b] = p_b if prob != NULL. Synchronises. */
+int yao_measure_collapse(yao_state* s, const int* locs, int k, const double* u, uint64_t* out, double* prob);
+
 /* Circuits ---------------------------------------------------------------------------- */
 
 int yao_circuit_create(int n, yao_circuit** out);
@@ -185,9 +235,14 @@ int yao_forward(yao_state* s, const yao_circuit* c, const double* params);
  * holding the output state), energy[b] = <psi_b|H|psi_b> and the gradient of every
  * parameter: grad[b * nparams + p] if reduce_batch == 0, else grad[p] summed over the
  * batch (the paper's batched gradient). If drift != NULL it receives
- * max |psi_0 uncomputed - psi_0| (0 in CHECKPOINT mode). Synchronises. */
+ * max |psi_0 uncomputed - psi_0| of the reversible sweep (REVERSIBLE and AUTO, also when AUTO
+ * fell back) or 0 (CHECKPOINT). Synchronises. */
 int yao_backward(yao_state* s, const yao_circuit* c, const double* params, const yao_pauli_sum* h,
                  enum yao_grad_mode mode, int reduce_batch, double* energy, double* grad, double* drift);
+
+/* Number of YAO_GRAD_AUTO backward calls since the library loaded whose reversible sweep
+ * drifted past drift_tol and fell back to the checkpointed sweep (process-wide). */
+int yao_auto_fallbacks(long* count);
 
 /* Batches of independent circuits (a9) --------------------------------------------------- */
 
@@ -216,7 +271,11 @@ enum yao_kernel_family {
     YAO_KF_HPSI = 5,      /* H psi (adjoint seed) */
     YAO_KF_MFMA = 6,      /* dense 4/5-qubit blocks on matrix cores */
     YAO_KF_BATCH = 7,     /* persistent batch kernel */
-    YAO_KF_COUNT = 8
+    YAO_KF_PERMUTE = 8,   /* qubit permutations (focus! / relax!) */
+    YAO_KF_QFT = 9,       /* QFT passes */
+    YAO_KF_MEASURE = 10,  /* outcome probabilities, cumulative sums, sampling, collapse */
+    YAO_KF_KRYLOV = 11,   /* vector updates of the Krylov time evolution */
+    YAO_KF_COUNT = 12
 };
 /* on = 1 clears earlier records and starts bracketing every launch with a pair of HIP
  * events on the bound stream; on = 0 stops. */

@@ -67,6 +67,15 @@ _SIGS = {
     "yao_forward": [P, P, P],
     "yao_backward": [P, P, P, P, I, I, P, P, P],
     "yao_batch_run": [I, P, P, P, P, P, P],
+    "yao_auto_fallbacks": [P],
+    "yao_permute_qubits": [P, P, P],
+    "yao_focus": [P, P, I],
+    "yao_relax": [P, P, I],
+    "yao_qft": [P, P, I, I],
+    "yao_probs": [P, P, I, P],
+    "yao_time_evolve": [P, P, D, D, I, P],
+    "yao_measure": [P, P, I, I, P, P],
+    "yao_measure_collapse": [P, P, I, P, P, P],
     "yao_profile_enable": [I],
     "yao_profile_read": [I, P, P, P, P],
     "yao_plan_selfcheck": [P, P, I, I, I, P, P],
@@ -303,6 +312,72 @@ def backward(state: State, circ: Circuit, params, H: PauliSum, mode=GRAD_REVERSI
     if reduce_batch:
         return e, g[:P_], drift.value
     return e, g[:P_ * state.batch].reshape(state.batch, P_) if P_ else np.zeros((state.batch, 0)), drift.value
+
+
+def permute_qubits(src: State, dst: State, perm):
+    """dst = src with qubit q moved to index bit perm[q] (dst may be src)."""
+    p = _i32(perm)
+    _check(lib().yao_permute_qubits(src.h, dst.h, _ptr(p)))
+
+
+def focus(state: State, locs):
+    """focus!: qubit locs[j] becomes qubit j, the others follow in ascending order."""
+    l = _i32(locs)
+    _check(lib().yao_focus(state.h, _ptr(l), len(l)))
+
+
+def relax(state: State, locs):
+    """relax!: undoes focus(state, locs)."""
+    l = _i32(locs)
+    _check(lib().yao_relax(state.h, _ptr(l), len(l)))
+
+
+def qft(state: State, locs, inverse=False):
+    """QFT (or its inverse) on the qubits locs, in place."""
+    l = _i32(locs)
+    _check(lib().yao_qft(state.h, _ptr(l), len(l), int(bool(inverse))))
+
+
+def time_evolve(state: State, H: PauliSum, t: float, tol: float = 0.0, krylov_dim: int = 0) -> int:
+    """psi <- exp(-i H t) psi in place; returns the number of Krylov substeps."""
+    steps = ctypes.c_int()
+    _check(lib().yao_time_evolve(state.h, H.h, float(t), float(tol), int(krylov_dim), ctypes.byref(steps)))
+    return steps.value
+
+
+def probs(state: State, locs) -> np.ndarray:
+    """[B][2^k] probabilities of the outcomes of the qubits locs."""
+    l = _i32(locs)
+    out = np.zeros((state.batch, 1 << len(l)))
+    _check(lib().yao_probs(state.h, _ptr(l), len(l), _ptr(out)))
+    return out
+
+
+def measure(state: State, locs, u) -> np.ndarray:
+    """Outcomes [B][nshots] for the caller's uniform numbers u [B][nshots] in [0, 1)."""
+    l = _i32(locs)
+    u = np.ascontiguousarray(np.asarray(u, np.float64).reshape(state.batch, -1))
+    out = np.zeros(u.shape, np.uint64)
+    _check(lib().yao_measure(state.h, _ptr(l), len(l), u.shape[1], _ptr(u), _ptr(out)))
+    return out.astype(np.int64)
+
+
+def measure_collapse(state: State, locs, u):
+    """measure!: (outcome[B], probability[B]) from one uniform number per slot; the state
+    collapses."""
+    l = _i32(locs)
+    u = np.ascontiguousarray(np.asarray(u, np.float64).reshape(state.batch))
+    out = np.zeros(state.batch, np.uint64)
+    p = np.zeros(state.batch)
+    _check(lib().yao_measure_collapse(state.h, _ptr(l), len(l), _ptr(u), _ptr(out), _ptr(p)))
+    return out.astype(np.int64), p
+
+
+def auto_fallbacks() -> int:
+    """AUTO backward calls that fell back to the checkpointed sweep since the library loaded."""
+    v = ctypes.c_long()
+    _check(lib().yao_auto_fallbacks(ctypes.byref(v)))
+    return v.value
 
 
 def batch_run(states: Sequence[State], circs: Sequence[Circuit], params: Sequence[np.ndarray],

@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-mllvm", "-structurizecfg-skip-uniform-regions=true",
-         "-munsafe-fp-atomics", "-ffp-contract=fast"]
+         "-ffp-contract=fast"]
 
 
 def sources():

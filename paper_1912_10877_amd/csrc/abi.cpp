@@ -4,6 +4,7 @@
 #include <cstdio>
 
 #include "driver.h"
+#include "fused.h"
 #include "tuner.h"
 #include "runtime.h"
 
@@ -43,6 +44,30 @@ int check_qubits(int n, const int* locs, int k, int nctrl, const int* ctrls, con
     return 0;
 }
 
+// A rotation exp(-i theta G / 2) = cos(theta/2) I - i sin(theta/2) G needs G Hermitian and
+// reflexive (G G = I; Sec. "Forward Mode"), or the formula is not the exponential and not
+// unitary. Checked entry-wise to 1e-12.
+int check_reflexive(const double* G, int k)
+{
+    const int d = 1 << k;
+    auto re = [&](int r, int c) { return G[2 * ((size_t)r * d + c)]; };
+    auto im = [&](int r, int c) { return G[2 * ((size_t)r * d + c) + 1]; };
+    constexpr double tol = 1e-12;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            if (std::fabs(re(r, c) - re(c, r)) > tol || std::fabs(im(r, c) + im(c, r)) > tol)
+                return set_error(YAO_EINVAL, "rotation generator is not Hermitian at (%d, %d)", r, c);
+            double sr = 0, si = 0;
+            for (int m = 0; m < d; ++m) {
+                sr += re(r, m) * re(m, c) - im(r, m) * im(m, c);
+                si += re(r, m) * im(m, c) + im(r, m) * re(m, c);
+            }
+            if (std::fabs(sr - (r == c ? 1.0 : 0.0)) > tol || std::fabs(si) > tol)
+                return set_error(YAO_EINVAL, "rotation generator G does not satisfy G G = I at (%d, %d)", r, c);
+        }
+    return 0;
+}
+
 int check_gate_kind(int g, int k, const double* G)
 {
     if (g < YAO_X || g > YAO_DENSE) return set_error(YAO_EINVAL, "unknown gate kind %d", g);
@@ -56,6 +81,7 @@ int check_gate_kind(int g, int k, const double* G)
         for (size_t t = 0; t < n; ++t)
             if (!std::isfinite(G[t])) return set_error(YAO_EINVAL, "matrix entry %zu is not finite", t);
     }
+    if (g == YAO_ROT) YAO_TRY(check_reflexive(G, k));
     return 0;
 }
 
@@ -261,6 +287,7 @@ int yao_pauli_sum_create(int n, int nterms, const double* coef, const uint64_t* 
     h->coef.assign(coef, coef + nterms);
     h->x.assign(xmask, xmask + nterms);
     h->z.assign(zmask, zmask + nterms);
+    pauli_group_host(h);
     *out = h;
     return 0;
 }
@@ -377,6 +404,13 @@ int yao_backward(yao_state* s, const yao_circuit* c, const double* params, const
     for (int p = 0; p < c->nparams; ++p)
         if (!std::isfinite(params[p])) return set_error(YAO_EINVAL, "params[%d] is not finite", p);
     return backward(s, c, params, const_cast<yao_pauli_sum*>(h), (int)mode, reduce_batch != 0, energy, grad, drift);
+}
+
+int yao_auto_fallbacks(long* count)
+{
+    if (!count) return set_error(YAO_EINVAL, "count is NULL");
+    *count = auto_fallbacks();
+    return 0;
 }
 
 int yao_batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* circs, const double* const* params,

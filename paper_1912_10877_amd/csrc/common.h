@@ -122,6 +122,9 @@ struct yao_pauli_sum {
     int n;
     std::vector<double> coef;
     std::vector<uint64_t> x, z;
+    // Terms grouped by X mask on the host (built at creation): group records of 16 bytes
+    // (x, first term, end term) and term records of 24 bytes (c, z, ny), as the kernels read them.
+    std::vector<uint64_t> host_groups, host_terms;
     // Device tables (grouped by X mask), built on first use.
     void* d_groups = nullptr;
     void* d_terms = nullptr;

@@ -1,6 +1,7 @@
 // Fused execution of circuits: plans are cached per circuit and geometry; each call lowers
 // the current parameters to one device program (ops, groups, FP64 matrices) and launches one
 // kernel per pass.
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -65,13 +66,16 @@ int gen_type_of(const GateRec& g)
     }
 }
 
-// Real flops per state element of one op (complex multiply = 6, complex add = 2).
-double op_flops(const POp& op, bool bwd)
+// Real flops per state element of one op as the pass kernels execute it (complex multiply = 6,
+// complex add = 2). diag_high: a reverse uncontrolled Z-generator diagonal, which multiplies only
+// the second element of each pair (d1/d0) and leaves d0 to the pass's running phase.
+double op_flops(const POp& op, bool bwd, bool diag_high)
 {
     double f;
     switch (op.type) {
     case OT_SWAP: f = 0; break;
-    case OT_DIAG: case OT_REAL: case OT_RX: f = 6; break;
+    case OT_DIAG: f = diag_high ? 3 : 6; break;
+    case OT_REAL: case OT_RX: f = 6; break;
     case OT_LDSK: f = 8.0 * (1 << op.k) - 2.0; break;
     default: f = 14; break;
     }
@@ -333,6 +337,7 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     for (int j = 0; j < P.reg_bits; ++j)
                         if (gd.rpos[j] == op.tpos[0]) op.rpos = j;
                 }
+                bool diag_high = false;
                 for (int m = 0; m < g.nctrl; ++m) {
                     const int q = g.ctrls[m];
                     bool folded = false;  // a control on a dense block's register bit is in its matrix
@@ -365,10 +370,11 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     }
                     op.var = g.k == 1 ? cls * P.reg_bits + op.rpos : 0;
                     // The reverse Z-generator diagonal class leaves d0 to a phase of the tile.
-                    if (bwd && g.k == 1 && cls == 1 && !pdep) split_diag_phase(op.u);
+                    diag_high = bwd && g.k == 1 && cls == 1;
+                    if (diag_high && !pdep) split_diag_phase(op.u);
                 }
                 prog.ops.push_back(op);
-                prog.pass_flops.back() += op_flops(op, bwd) / double(uint64_t(1) << g.nctrl);
+                prog.pass_flops.back() += op_flops(op, bwd, diag_high) / double(uint64_t(1) << g.nctrl);
             }
             prog.groups.push_back(gd);
         }
@@ -685,7 +691,8 @@ static void gather_gradients(const yao_circuit* c, const std::vector<int>& slot_
 // it may fold gates into dense blocks; the reverse program is built on the host while the
 // device runs the forward sweep, and nothing waits for the device until the results are read.
 static int backward_reversible(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h,
-                               bool reduce_batch, double* energy, double* grad, double* drift, const void* psi0)
+                               bool reduce_batch, double* energy, double* grad, double* drift, const void* psi0,
+                               bool check_drift)
 {
     const int n = s->n, B = s->batch;
     const size_t elems = s->elems();
@@ -737,10 +744,17 @@ static int backward_reversible(yao_state* s, const yao_circuit* c, const double*
     for (int b = 0; b < B; ++b) energy[b] = hres[b];
     gather_gradients(c, prog.slot_of_gate, hres + B, B, reduce_batch, grad);
     if (drift) *drift = dend;
-    if (options().drift_tol > 0 && dend > options().drift_tol)
+    if (check_drift && options().drift_tol > 0 && dend > options().drift_tol)
         return set_error(YAO_EDRIFT, "uncomputed input differs from the input by %.3g > %.3g", dend,
                          options().drift_tol);
     return 0;
+}
+
+static std::atomic<long> g_auto_fallbacks{0};
+
+long auto_fallbacks()
+{
+    return g_auto_fallbacks.load();
 }
 
 int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h, int mode,
@@ -752,10 +766,27 @@ int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao
     hipStream_t st = stream();
     const double tol = options().drift_tol > 0 ? options().drift_tol : (s->dtype == YAO_C64 ? 1e-5 : 1e-10);
 
-    // Segments: the reversible sweep runs the circuit as one plan; the checkpointed modes cut
-    // it into gate ranges whose end states the forward keeps.
+    void* psi0 = workspace(WS_PSI0, s->bytes());
+    if (!psi0) return YAO_ENOMEM;
+    YAO_HIP(hipMemcpyAsync(psi0, s->data, s->bytes(), hipMemcpyDeviceToDevice, st));
+    if (mode != YAO_GRAD_CHECKPOINT) {
+        // Reversible sweep in constant memory. AUTO checks how far the uncomputed input strayed
+        // from the kept input and, past the tolerance, restores the input and runs the
+        // checkpointed sweep instead (its checkpoints are allocated only then).
+        double d = 0;
+        YAO_TRY(backward_reversible(s, c, params, h, reduce_batch, energy, grad, &d, psi0,
+                                    mode == YAO_GRAD_REVERSIBLE));
+        if (drift) *drift = d;
+        if (mode == YAO_GRAD_REVERSIBLE || !(d > tol)) return 0;
+        g_auto_fallbacks.fetch_add(1);
+        YAO_HIP(hipMemcpyAsync(s->data, psi0, s->bytes(), hipMemcpyDeviceToDevice, st));
+        return backward_fused(s, c, params, h, YAO_GRAD_CHECKPOINT, reduce_batch, energy, grad, nullptr);
+    }
+
+    // Checkpointed sweep: the circuit is cut into gate ranges whose end states the forward
+    // keeps; the reverse sweep of each range restarts from the kept state.
     std::vector<int> cuts{0};
-    if (mode != YAO_GRAD_REVERSIBLE && G > 0) {
+    if (G > 0) {
         int len = options().checkpoint_every;
         if (len <= 0) len = std::max((int)std::ceil(std::sqrt((double)G)), 4 * n);
         for (int g = len; g < G; g += len) cuts.push_back(g);
@@ -763,15 +794,10 @@ int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao
     cuts.push_back(G);
     const int nseg = (int)cuts.size() - 1;
 
-    void* psi0 = workspace(WS_PSI0, s->bytes());
-    if (!psi0) return YAO_ENOMEM;
-    YAO_HIP(hipMemcpyAsync(psi0, s->data, s->bytes(), hipMemcpyDeviceToDevice, st));
-    char* ckpt = nullptr;
-    if (nseg > 1) {
-        ckpt = (char*)workspace(WS_CKPT, s->bytes() * (size_t)(nseg - 1));
-        if (!ckpt) return YAO_ENOMEM;
-    }
-    if (nseg == 1) return backward_reversible(s, c, params, h, reduce_batch, energy, grad, drift, psi0);
+    if (nseg == 1)
+        return backward_reversible(s, c, params, h, reduce_batch, energy, grad, drift, psi0, false);
+    char* ckpt = (char*)workspace(WS_CKPT, s->bytes() * (size_t)(nseg - 1));
+    if (!ckpt) return YAO_ENOMEM;
     for (int sg = 0; sg < nseg; ++sg) {
         YAO_TRY(forward_fused_range(s->data, s->dtype, n, B, c, params, cuts[sg], cuts[sg + 1]));
         if (sg + 1 < nseg)
@@ -792,19 +818,10 @@ int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao
     if (!gpartial) return YAO_ENOMEM;
     if (nslots) YAO_TRY(launch_fill(gpartial, (size_t)nslots * B * W, 0.0));
     std::vector<int> slot_of_gate;
-    double worst = 0;
     for (int sg = nseg - 1; sg >= 0; --sg) {
         if (sg + 1 < nseg) {
             // psi now stands at the end of segment sg, where the forward kept a copy.
-            const void* ref = ckpt + s->bytes() * sg;
-            bool resync = mode == YAO_GRAD_CHECKPOINT;
-            if (mode == YAO_GRAD_AUTO) {
-                double dv = 0;
-                YAO_TRY(launch_maxdiff(psi, YAO_C128, ref, s->dtype, elems, &dv));
-                worst = std::max(worst, dv);
-                resync = dv > tol;
-            }
-            if (resync) YAO_TRY(launch_convert(ref, s->dtype, psi, YAO_C128, elems));
+            YAO_TRY(launch_convert(ckpt + s->bytes() * sg, s->dtype, psi, YAO_C128, elems));
         }
         const Plan& P = get_plan(c, cuts[sg], cuts[sg + 1], B, t, cb, L, true, s->dtype == YAO_C64 ? 8 : 16);
         YAO_TRY(run_backward_plan(P, c, params, psi, lam, s->dtype, n, B, gpartial, W, &slot_of_gate));
@@ -831,12 +848,7 @@ int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao
             }
         }
     }
-    double dend = 0;
-    YAO_TRY(launch_maxdiff(psi, YAO_C128, psi0, s->dtype, elems, &dend));
-    if (drift) *drift = std::max(dend, worst);
-    if (mode == YAO_GRAD_REVERSIBLE && options().drift_tol > 0 && dend > options().drift_tol)
-        return set_error(YAO_EDRIFT, "uncomputed input differs from the input by %.3g > %.3g", dend,
-                         options().drift_tol);
+    if (drift) *drift = 0;
     return 0;
 }
 

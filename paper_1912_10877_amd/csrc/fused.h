@@ -268,6 +268,8 @@ int forward_fused_range(void* data, int dtype, int n, int B, const yao_circuit* 
                         int g1);
 int backward_fused(yao_state* s, const yao_circuit* c, const double* params, yao_pauli_sum* h, int mode,
                    bool reduce_batch, double* energy, double* grad, double* drift);
+// AUTO sweeps that fell back to the checkpointed form since the library loaded.
+long auto_fallbacks();
 // Tiles need more qubits than register bits.
 bool fused_supported(int n, int B);
 

@@ -525,9 +525,9 @@ int launch_row_sums(const double* partial, int rows, int nblk, double* sums)
     return 0;
 }
 
-int pauli_upload(yao_pauli_sum* h)
+void pauli_group_host(yao_pauli_sum* h)
 {
-    if (h->d_groups) return 0;
+    static_assert(sizeof(PGroup) == 16 && sizeof(PTerm) == 24, "table record sizes");
     std::vector<PGroup> groups;
     std::vector<PTerm> terms;
     std::vector<uint64_t> xs;
@@ -553,19 +553,52 @@ int pauli_upload(yao_pauli_sum* h)
         g.t1 = (int)terms.size();
         groups.push_back(g);
     }
+    h->host_groups.assign(groups.size() * 2, 0);
+    memcpy(h->host_groups.data(), groups.data(), sizeof(PGroup) * groups.size());
+    h->host_terms.assign(terms.size() * 3, 0);
+    memcpy(h->host_terms.data(), terms.data(), sizeof(PTerm) * terms.size());
+}
+
+int pauli_upload(yao_pauli_sum* h)
+{
+    if (h->d_groups) return 0;
+    if (h->host_groups.empty()) pauli_group_host(h);
+    const size_t ng = h->host_groups.size() / 2, nt = h->host_terms.size() / 3;
     void *dg = nullptr, *dt = nullptr;
-    if (hipMalloc(&dg, sizeof(PGroup) * (groups.size() + 1)) != hipSuccess) return set_error(YAO_ENOMEM, "pauli tables");
-    if (hipMalloc(&dt, sizeof(PTerm) * (terms.size() + 1)) != hipSuccess) {
+    if (hipMalloc(&dg, sizeof(PGroup) * (ng + 1)) != hipSuccess) return set_error(YAO_ENOMEM, "pauli tables");
+    if (hipMalloc(&dt, sizeof(PTerm) * (nt + 1)) != hipSuccess) {
         (void)hipFree(dg);
         return set_error(YAO_ENOMEM, "pauli tables");
     }
-    YAO_HIP(hipMemcpy(dg, groups.data(), sizeof(PGroup) * groups.size(), hipMemcpyHostToDevice));
-    YAO_HIP(hipMemcpy(dt, terms.data(), sizeof(PTerm) * terms.size(), hipMemcpyHostToDevice));
+    YAO_HIP(hipMemcpy(dg, h->host_groups.data(), sizeof(PGroup) * ng, hipMemcpyHostToDevice));
+    YAO_HIP(hipMemcpy(dt, h->host_terms.data(), sizeof(PTerm) * nt, hipMemcpyHostToDevice));
     h->d_groups = dg;
     h->d_terms = dt;
-    h->ngroups = (int)groups.size();
-    h->nterms_dev = (int)terms.size();
+    h->ngroups = (int)ng;
+    h->nterms_dev = (int)nt;
     return 0;
+}
+
+int expect_grid_x(int n, int B)
+{
+    return reduce_grid_x(uint64_t(1) << n, make_batch_geom(B).logBc);
+}
+
+int launch_expect_into(const void* data, int dtype, int n, int B, const void* groups, int ngroups, const void* terms,
+                       double* partial, double* sums)
+{
+    BatchGeom bg = make_batch_geom(B);
+    const uint64_t rows = uint64_t(1) << n;
+    const int nbx = reduce_grid_x(rows, bg.logBc);
+    dim3 grid(nbx, bg.nchunks);
+    if (dtype == YAO_C64)
+        k_expect<float><<<grid, kThreads, 0, stream()>>>((const float2*)data, rows, B, bg.logBc, (const PGroup*)groups,
+                                                         ngroups, (const PTerm*)terms, partial);
+    else
+        k_expect<double><<<grid, kThreads, 0, stream()>>>((const double2*)data, rows, B, bg.logBc, (const PGroup*)groups,
+                                                          ngroups, (const PTerm*)terms, partial);
+    YAO_HIP(hipGetLastError());
+    return launch_row_sums(partial, B, nbx, sums);
 }
 
 static int finish_slot_sums(double* partial, int B, int nblk, double* energy_host)

@@ -39,6 +39,10 @@ enum WsSlot {
     WS_TUNE,        // copy of a state while schedules are timed on it
     WS_PARAMS,      // circuit parameters for the device-side binding of programs
     WS_MISC,
+    WS_PERM,        // out-of-place target of an in-place qubit permutation
+    WS_MEAS,        // outcome probabilities, cumulative sums and sampled outcomes
+    WS_KRYLOV,      // Krylov vectors of the time evolution
+    WS_SHIFT,       // the shifted-circuit register of the faithful gradient
     WS_COUNT
 };
 void* workspace(int slot, size_t bytes);
@@ -151,7 +155,36 @@ struct PTerm {
     int ny;
     int pad;
 };
+// Group the terms by X mask into h->host_groups / h->host_terms (PGroup / PTerm records).
+void pauli_group_host(yao_pauli_sum* h);
 int pauli_upload(yao_pauli_sum* h);
+// Expectation through the one-read-per-X-mask-group kernel into caller-given device buffers:
+// groups / terms hold the PGroup / PTerm tables, partial B * expect_grid_x(n, B) doubles,
+// sums[b] receives the energy of slot b. Nothing is allocated and nothing synchronises.
+int expect_grid_x(int n, int B);
+int launch_expect_into(const void* data, int dtype, int n, int B, const void* groups, int ngroups, const void* terms,
+                       double* partial, double* sums);
+
+// Qubit permutation (qubit q -> index bit perm[q]) from in to out (distinct buffers), and the
+// QFT (or its inverse) on the qubits locs in place (kernels_qubits.hip). Batch * element bytes
+// must stay <= 16 KiB.
+int launch_permute(const void* in, void* out, int dtype, int n, int B, const int* perm);
+int launch_qft(void* data, int dtype, int n, int B, const int* locs, int k, bool inverse);
+int qft_passes(int dtype, int n, int B, const int* locs, int k);
+
+// psi <- exp(-i H t) psi per slot by the Lanczos method (krylov.hip); nsteps: substeps taken.
+int time_evolve(yao_state* s, yao_pauli_sum* h, double t, double tol, int krylov_dim, int* nsteps);
+
+// Measurement (kernels_measure.hip). prob: B * 2^k doubles [b][x]; launch_cdf scans p into q
+// (tot: cdf_tot_doubles(k, B)); launch_sample draws nshots outcomes per slot from u (device,
+// [B][nshots]); launch_collapse projects s onto the outcomes x (device, [B]) and writes dep, scale
+// and prob (device, B each). locs_dev: the k locs in device memory.
+int launch_outcome_probs(const yao_state* s, const int* locs, int k, double* prob);
+int launch_cdf(const double* p, double* q, int k, int B, double* tot);
+size_t cdf_tot_doubles(int k, int B);
+int launch_sample(const double* cdf, int k, int B, int nshots, const double* u, uint64_t* out);
+int launch_collapse(yao_state* s, const double* probs, const int* locs_dev, const int* locs, int k, const uint64_t* x,
+                    uint64_t* dep, double* scale, double* prob);
 
 // Dense 4/5-qubit gates on complex64 states through the FP32 matrix cores.
 bool mfma_supported(int k, int n, int B);

@@ -21,6 +21,7 @@ def test_circuit_push_validation():
     c.push("Rx", [0], param=0)
     c.push("X", [1], ctrls=[0])
     c.push("rot", [0, 1], param=3, G=np.kron(np.array([[0, 1], [1, 0]]), np.array([[0, 1], [1, 0]])))
+    c.push("rot", [2], param=1, G=np.array([[0, -1j], [1j, 0]]))      # Y: Hermitian and reflexive
     assert c.nparams == 4
     bad = [
         dict(kind="Rx", locs=[4], param=0),             # loc out of range
@@ -31,6 +32,10 @@ def test_circuit_push_validation():
         dict(kind="rot", locs=[0], param=0),            # rot without generator
         dict(kind="Rx", locs=[0, 1], param=0),          # one-qubit kind on two qubits
         dict(kind="dense", locs=[0, 1, 2, 3, 0, 1], G=np.eye(64)),  # k too large / repeated
+        dict(kind="rot", locs=[0], param=0, G=np.diag([1.0, 2.0])),        # Hermitian, G G != 1
+        dict(kind="rot", locs=[0], param=0, G=np.array([[0, 1], [0, 0]])),  # not Hermitian
+        dict(kind="rot", locs=[0], param=0, G=np.array([[0, 1j], [1j, 0]])),  # G G = -1, anti-Hermitian
+        dict(kind="rot", locs=[0, 1], param=0, G=np.kron(np.eye(2), np.diag([1.0, 1.0 + 1e-9]))),
     ]
     for kw in bad:
         with pytest.raises(yb.YaoError) as ei:

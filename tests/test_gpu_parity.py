@@ -289,6 +289,30 @@ def test_fused_backward_matches_oracle(dtype, n, B, tq):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,B", [(10, 64), (12, 16), (9, 100)])
+def test_fused_backward_many_batch_blocks(dtype, n, B):
+    """Batches wider than one tile's batch bits: several batch blocks per pass, per-slot
+    gradients and the batch-summed gradient (Sec. "Reverse Mode": batched gradients are
+    summed) against the oracle."""
+    circ = w.random_gate_list(n, 40, seed=2500 + n + B, kmax=3, max_ctrl=2)
+    H = w.heisenberg(n)
+    params = w.angles(n + 5, circ.nparams)
+    psi0 = w.random_state(n, B, n + 7)
+    e_ref, g_ref, _ = oracle.adjoint(H, circ, params, psi0)
+    c, h = yb.Circuit.from_workload(circ), yb.PauliSum.from_workload(H)
+    s = yb.State(n, B, dtype)
+    s.upload(psi0)
+    e, g, _ = yb.backward(s, c, params, h)
+    np.testing.assert_allclose(e, e_ref, atol=1e-10 if dtype == 1 else 1e-5)
+    assert np.abs(g - g_ref).max() <= grad_tol(dtype, g_ref)
+    s.upload(psi0)
+    e2, gsum, _ = yb.backward(s, c, params, h, reduce_batch=True)
+    np.testing.assert_allclose(e2, e_ref, atol=1e-10 if dtype == 1 else 1e-5)
+    gsum_ref = g_ref.sum(axis=0)
+    assert np.abs(gsum - gsum_ref).max() <= B * grad_tol(dtype, g_ref)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_fused_hea_deep(dtype):
     """The workload ansatz at 14 qubits, depth 6: several passes and register groups per layer."""
     n, depth = 14, 6

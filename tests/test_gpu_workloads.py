@@ -73,6 +73,34 @@ def test_vqe20_checkpoint_segments(vqe20):
     yb.set_options(checkpoint_every=0)
 
 
+def test_vqe20_batch64_per_slot_and_summed_gradients(vqe20):
+    """The 20-qubit differentiation workload on a 64-slot batch (the shape the batched bench
+    line times): 4 seeded input states placed on the slots in a seeded pattern; every slot's
+    energy and 1200 gradients and the batch-summed gradient against stored oracle values."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(GOLDEN, "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    circ, H, params, _ = vqe20
+    gold = golden("b64_states.txt")
+    n, B = 20, 64
+    pat = mg.b64_pattern(B)
+    states = [w.random_state(n, 1, seed)[:, 0] for seed in mg.B64_SEEDS]
+    psi0 = np.stack([states[j] for j in pat], axis=1)
+    e_ref = np.array([gold[f"energy{j}"][0] for j in pat])
+    g_ref = np.stack([gold[f"grad{j}"] for j in pat])
+    s = yb.State(n, B, 0)
+    s.upload(psi0)
+    e, g, drift = yb.backward(s, circ, params, H)
+    np.testing.assert_allclose(e, e_ref, atol=1e-5)
+    assert grad_ok(g, g_ref, 1e-4)
+    assert drift <= 1e-5
+    s.upload(psi0)
+    e2, gsum, _ = yb.backward(s, circ, params, H, reduce_batch=True)
+    np.testing.assert_allclose(e2, e_ref, atol=1e-5)
+    assert np.abs(gsum - g_ref.sum(axis=0)).max() <= 1e-4 * B * max(1.0, float(np.abs(g_ref).max()))
+
+
 def test_backward_is_deterministic(vqe20):
     circ, H, params, _ = vqe20
     s = yb.State(20, 1, 0)
@@ -102,6 +130,51 @@ def test_checkpoint_modes_match_oracle(mode, every):
             assert grad_ok(g, g_ref, 1e-10 if dtype == 1 else 1e-4)
     finally:
         yb.set_options(checkpoint_every=0)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_auto_falls_back_to_checkpoints_past_drift_tol(dtype):
+    """AUTO runs the reversible sweep; with a drift bound below the rounding floor it restores
+    the input and reruns checkpointed, and the results still match the oracle."""
+    n = 9
+    circ = w.random_gate_list(n, 60, seed=4242, kmax=3)
+    H = w.heisenberg(n)
+    params = w.angles(17, circ.nparams)
+    psi0 = w.random_state(n, 3, 18)
+    e_ref, g_ref, _ = oracle.adjoint(H, circ, params, psi0)
+    c, h = yb.Circuit.from_workload(circ), yb.PauliSum.from_workload(H)
+    tol_e, tol_g = (1e-10, 1e-10) if dtype == 1 else (1e-5, 1e-4)
+    try:
+        for drift_tol, fallback in ((1e-300, True), (0.0, False)):
+            yb.set_options(drift_tol=drift_tol, checkpoint_every=13)
+            s = yb.State(n, 3, dtype)
+            s.upload(psi0)
+            before = yb.auto_fallbacks()
+            e, g, drift = yb.backward(s, c, params, h, mode=yb.GRAD_AUTO)
+            assert yb.auto_fallbacks() - before == (1 if fallback else 0)
+            assert drift <= (1e-10 if dtype == 1 else 1e-5)
+            np.testing.assert_allclose(e, e_ref, atol=tol_e)
+            assert grad_ok(g, g_ref, tol_g)
+            out = oracle.forward(circ, params, psi0)
+            got = s.download()
+            assert np.abs(got - out).max() <= (1e-12 if dtype == 1 else 1e-5)
+    finally:
+        yb.set_options(drift_tol=0.0, checkpoint_every=0)
+
+
+def test_auto_fallback_at_full_size(vqe20):
+    """The 20-qubit differentiation workload through AUTO's fallback path."""
+    circ, H, params, gold = vqe20
+    yb.set_options(drift_tol=1e-300)
+    try:
+        s = yb.State(20, 1, 0)
+        before = yb.auto_fallbacks()
+        e, g, _ = yb.backward(s, circ, params, H, mode=yb.GRAD_AUTO)
+        assert yb.auto_fallbacks() == before + 1
+        assert abs(e[0] - gold["energy"][0]) <= 1e-5
+        assert grad_ok(g[0], gold["grad"], 1e-4)
+    finally:
+        yb.set_options(drift_tol=0.0)
 
 
 def test_strict_reversible_drift_bound_reports_error():
