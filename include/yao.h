@@ -158,6 +158,16 @@ int yao_pauli_sum_create(int n, int nterms, const double* coef, const uint64_t* 
 int yao_pauli_sum_destroy(yao_pauli_sum* h);
 /* energy[b] = Re <psi_b|H|psi_b> for every batch slot, accumulated in FP64. Synchronises. */
 int yao_expect(const yao_state* s, const yao_pauli_sum* h, double* energy);
+/* yao_expect for callers that cannot allocate device memory (code under graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc). Same result as yao_expect (one read of the
+ * state per X-mask group of the terms), but the term tables and every partial sum live in a
+ * static device array of 2 MiB that each GPU holds from the library's load until the process
+ * ends; no hipMalloc, hipFree or other allocating call is made. Limits: at most 4096 terms and
+ * batch * min(2^n * batch_block / 256, 1024) <= 131072 partial sums (batch <= 128 for n >= 10);
+ * YAO_EINVAL beyond them. All calls on one GPU share the array, which keeps the last call's
+ * contents (every value a call reads is written earlier in that call): calls that overlap on
+ * one GPU, from several threads or streams, race. Synchronises the bound stream. */
+int yao_expect_noalloc(const yao_state* s, const yao_pauli_sum* h, double* energy);
 /* out = H psi (the adjoint seed of the reverse mode) and, if energy != NULL,
  * energy[b] = Re <psi_b|H psi_b> from the same pass. out must match s in n, batch, dtype. */
 int yao_hpsi(const yao_state* s, const yao_pauli_sum* h, yao_state* out, double* energy);

@@ -58,6 +58,7 @@ _SIGS = {
     "yao_pauli_sum_create": [I, I, P, P, P, PP],
     "yao_pauli_sum_destroy": [P],
     "yao_expect": [P, P, P],
+    "yao_expect_noalloc": [P, P, P],
     "yao_hpsi": [P, P, P, P],
     "yao_inner": [P, P, P, P],
     "yao_circuit_create": [I, PP],
@@ -278,6 +279,13 @@ def _params(p):
 def expect(state: State, H: PauliSum) -> np.ndarray:
     e = np.zeros(state.batch)
     _check(lib().yao_expect(state.h, H.h, _ptr(e)))
+    return e
+
+
+def expect_noalloc(state: State, H: PauliSum) -> np.ndarray:
+    """yao_expect_noalloc: the expectation with every device buffer in the library's static array."""
+    e = np.zeros(state.batch)
+    _check(lib().yao_expect_noalloc(state.h, H.h, _ptr(e)))
     return e
 
 

@@ -11,6 +11,7 @@
 using namespace yao;
 
 namespace yao {
+int noalloc_setup();
 const char* last_error();
 void set_stream(hipStream_t s);
 void set_options(const yao_options& o);
@@ -117,6 +118,7 @@ extern "C" {
 int yao_init(void)
 {
     YAO_TRY(ensure_device());
+    YAO_TRY(noalloc_setup());
     yao_options o;
     default_options(o);
     set_options(o);
