@@ -24,9 +24,11 @@ METRIC = "amplitude-updates/s & HBM GB/s, 20q fwd+grad; batched-adjoint vs plain
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
-FAMILIES = {0: "gate", 1: "adjoint", 2: "pass_fwd", 3: "pass_bwd", 4: "expect", 5: "hpsi", 6: "mfma", 7: "batch"}
+FAMILIES = {0: "gate", 1: "adjoint", 2: "pass_fwd", 3: "pass_bwd", 4: "expect", 5: "hpsi", 6: "mfma", 7: "batch",
+            8: "permute", 9: "qft", 10: "measure", 11: "krylov"}
 KERNEL_NAMES = {0: "k_gate1/k_gatek", 1: "k_adjoint", 2: "k_pass_fwd", 3: "k_pass_bwd", 4: "k_expect", 5: "k_hpsi",
-                6: "k_dense_mfma", 7: "k_batch"}
+                6: "k_dense_mfma", 7: "k_batch", 8: "k_permute", 9: "k_qft_pass", 10: "measure kernels",
+                11: "Krylov vector kernels"}
 
 
 def measured_traffic(kernel):
@@ -63,6 +65,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-profile", action="store_true")
     p.add_argument("--no-configs", action="store_true", help="skip the 10q/25q/20q-batch-64/30q figures")
+    p.add_argument("--case", choices=CASES, help="run one workload --steps times for a profiler, and nothing else")
+    p.add_argument("--no-next", action="store_true",
+                   help="skip the shift-rule, QFT, permutation, sampling and time-evolution figures")
     p.add_argument("--batch-circuits", type=int, default=1024,
                    help="circuits of the uneven batch measured beside the main step (0: skip)")
     p.add_argument("--batch-steps", type=int, default=5)
@@ -221,8 +226,203 @@ def bench_configs(yb, w, torch):
     return out
 
 
+def bench_next_rows(yb, w, torch):
+    """Figures of the rows beyond the gradient path: the faithful gradient (shift rule, every
+    shifted circuit in one register) against the reversible adjoint at 10 and 20 qubits; the QFT
+    kernel and a qubit permutation at 25 qubits against the HBM peak, and the QFT as a gate
+    circuit; sampling a million shots from all 24 qubits; Krylov time evolution at 16 and 20
+    qubits; and the 20-qubit step in checkpointed mode and in complex128."""
+    import numpy as np
+
+    def timed(f, reps):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    out = {}
+    # Faithful gradient vs the reversible adjoint.
+    for n, depth, dt, reps in ((10, 5, yb.C128, 3), (20, 20, yb.C64, 1)):
+        c = w.hea_circuit(n, depth)
+        cc, H, p = yb.Circuit.from_workload(c), yb.PauliSum.from_workload(w.heisenberg(n)), w.angles(2, c.nparams)
+        s = yb.State(n, 1, dt)
+        shift_ms = timed(lambda: yb.shift_grad(s, cc, p, H), reps)
+
+        def adj():
+            s.reset()
+            yb.backward(s, cc, p, H)
+        adj_ms = timed(adj, 10)
+        out[f"f1_shift_{n}q"] = {"params": c.nparams, "circuits": 2 * c.nparams + 1,
+                                 "dtype": "c128" if dt == yb.C128 else "c64", "shift_ms": round(shift_ms, 2),
+                                 "adjoint_ms": round(adj_ms, 3), "shift_over_adjoint": round(shift_ms / adj_ms, 1)}
+        del s
+    # QFT kernel and qubit permutation at 25 qubits.
+    n = 25
+    for dt, name, es in ((yb.C128, "c128", 16), (yb.C64, "c64", 8)):
+        s = yb.State(n, 1, dt)
+        locs = list(range(n))
+        yb.lib().yao_profile_enable(1)
+        qms = timed(lambda: yb.qft(s, locs), 5)
+        yb.lib().yao_profile_enable(0)
+        prof = profile_family(yb, 9)
+        t = yb.State(n, 1, dt)
+        perm = list(range(n - 1, -1, -1))
+        yb.lib().yao_profile_enable(1)
+        pms = timed(lambda: yb.permute_qubits(s, t, perm), 5)
+        yb.lib().yao_profile_enable(0)
+        pprof = profile_family(yb, 8)
+        out[f"f4_qft_25q_{name}"] = {"ms": round(qms, 3), **prof}
+        out[f"f4_permute_25q_{name}"] = {"ms": round(pms, 3), **pprof}
+        if dt == yb.C128:
+            qc = yb.Circuit.from_workload(w.qft_circuit(n))
+            out["f4_qft_25q_c128"]["gate_circuit_ms"] = round(timed(lambda: yb.forward(s, qc, []), 2), 3)
+        del s, t
+    # Sampling: all 24 qubits of a state after two ansatz layers, 2^20 shots.
+    n = 24
+    c = w.hea_circuit(n, 2)
+    s = yb.State(n, 1, yb.C128)
+    yb.forward(s, yb.Circuit.from_workload(c), w.angles(3, c.nparams))
+    u = np.random.default_rng(0).random((1, 1 << 20))
+    yb.lib().yao_profile_enable(1)
+    mms = timed(lambda: yb.measure(s, list(range(n)), u), 3)
+    yb.lib().yao_profile_enable(0)
+    out["f2_measure_24q_c128"] = {"shots": 1 << 20, "ms": round(mms, 3), **profile_family(yb, 10)}
+    del s
+    # Time evolution (the 16-qubit size of Listing "Hamiltonian evolution is faster with cache").
+    for n in (16, 20):
+        H = yb.PauliSum.from_workload(w.heisenberg(n))
+        s = yb.State(n, 1, yb.C128)
+        psi = w.random_state(n, 1, n)
+
+        def te():
+            s.upload(psi)
+            return yb.time_evolve(s, H, 0.1)
+        steps = te()
+        up_ms = timed(lambda: s.upload(psi), 3)
+        te_ms = timed(te, 3) - up_ms
+        out[f"f3_evolve_{n}q_c128"] = {"t": 0.1, "substeps": steps, "ms": round(te_ms, 3)}
+        del s
+    # The headline step in checkpointed mode, and in complex128.
+    c = w.hea_circuit(20, 20)
+    cc, H, p = yb.Circuit.from_workload(c), yb.PauliSum.from_workload(w.heisenberg(20)), w.angles(2, c.nparams)
+    for dt, mode, key in ((yb.C64, yb.GRAD_CHECKPOINT, "c3_20q_checkpoint_c64_ms"),
+                          (yb.C128, yb.GRAD_REVERSIBLE, "c3_20q_reversible_c128_ms")):
+        s = yb.State(20, 1, dt)
+
+        def st():
+            s.reset()
+            yb.backward(s, cc, p, H, mode=mode)
+        out[key] = round(timed(st, 10), 3)
+        del s
+    return out
+
+
+def profile_family(yb, fam):
+    """Launches, mean duration and algorithmic GB/s of one kernel family since profiling was
+    last enabled (HIP events on the library's stream)."""
+    import ctypes
+    yb.lib().yao_profile_read.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    nl, ms, by, fl = ctypes.c_int(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    yb.lib().yao_profile_read(fam, ctypes.byref(nl), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl))
+    if not nl.value:
+        return {}
+    gbs = by.value / (ms.value / 1e3) / 1e9
+    return {"launches": nl.value, "avg_launch_us": round(ms.value * 1e3 / nl.value, 2),
+            "algo_bytes_per_launch": by.value / nl.value, "achieved_gbs": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}
+
+
+CASES = ("step20", "step20_b64", "rx25_c128", "rx25_c64", "fwd25_c128", "fwd25_c64", "w5mfma30_c64",
+         "qft25_c128", "perm25_c128", "measure24_c128", "copy1g")
+
+
+def run_case(name, reps):
+    """One workload, repeated, for profiling runs (rocprofv3 kernel traces and counters): each
+    case launches only what it names, after one untimed run, and prints its wall time per rep."""
+    import numpy as np
+    import torch
+
+    import workloads as w
+    from paper_1912_10877_amd import binding as yb
+
+    torch.cuda.set_device(0)
+    yb.init()
+    yb.use_torch_stream()
+    if name == "copy1g":
+        # Calibration of the traffic counters: a copy of known size, 1 GiB read and 1 GiB written
+        # per launch (a 27-qubit complex64 register with its two top qubits swapped, so every
+        # row of the tile moves whole), rotating over three registers so that each source was
+        # last written two launches (2 GiB, 8x the 256 MB Infinity Cache) earlier.
+        regs = [yb.State(27, 1, yb.C64) for _ in range(3)]
+        perm = list(range(25)) + [26, 25]
+        it = [0]
+
+        def f():
+            i = it[0] % 3
+            yb.permute_qubits(regs[i], regs[(i + 1) % 3], perm)
+            it[0] += 1
+    elif name in ("step20", "step20_b64"):
+        B = 64 if name == "step20_b64" else 1
+        c = w.hea_circuit(20, 20)
+        cc, H, p = yb.Circuit.from_workload(c), yb.PauliSum.from_workload(w.heisenberg(20)), w.angles(2, c.nparams)
+        s = yb.State(20, B, yb.C64)
+
+        def f():
+            s.reset()
+            yb.backward(s, cc, p, H)
+    elif name.startswith("rx25"):
+        s = yb.State(25, 1, yb.C128 if name.endswith("c128") else yb.C64)
+        yb.set_options(plain=1)
+        f = lambda: s.apply_gate("Rx", (12,), theta=0.3)
+    elif name.startswith("fwd25"):
+        c = w.hea_circuit(25, 20)
+        cc, p = yb.Circuit.from_workload(c), w.angles(1, c.nparams)
+        s = yb.State(25, 1, yb.C128 if name.endswith("c128") else yb.C64)
+        yb.set_options(autotune=0, fuse_width=1)
+
+        def f():
+            s.reset()
+            yb.forward(s, cc, p)
+    elif name == "w5mfma30_c64":
+        cc = yb.Circuit.from_workload(w.random_circuit(30, 24, seed=5))
+        s = yb.State(30, 1, yb.C64)
+        yb.set_options(autotune=0, fuse_width=5, mfma=1)
+
+        def f():
+            s.reset()
+            yb.forward(s, cc, [])
+    elif name == "qft25_c128":
+        s = yb.State(25, 1, yb.C128)
+        f = lambda: yb.qft(s, list(range(25)))
+    elif name == "perm25_c128":
+        s, t = yb.State(25, 1, yb.C128), yb.State(25, 1, yb.C128)
+        perm = list(range(24, -1, -1))
+        f = lambda: yb.permute_qubits(s, t, perm)
+    elif name == "measure24_c128":
+        c = w.hea_circuit(24, 2)
+        s = yb.State(24, 1, yb.C128)
+        yb.forward(s, yb.Circuit.from_workload(c), w.angles(3, c.nparams))
+        u = np.random.default_rng(0).random((1, 1 << 20))
+        f = lambda: yb.measure(s, list(range(24)), u)
+    else:
+        raise SystemExit(f"unknown case {name}; cases: {', '.join(CASES)}")
+    f()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        f()
+    torch.cuda.synchronize()
+    print(json.dumps({"case": name, "reps": reps, "ms_per_rep": (time.perf_counter() - t0) * 1e3 / reps}))
+
+
 def main():
     args = parse()
+    if args.case:
+        run_case(args.case, args.steps)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
               "(the multi-GPU sharding of the state is described in DESIGN.md, not built)", file=sys.stderr)
@@ -325,6 +525,9 @@ def main():
     configs = None
     if not args.no_configs:
         configs = bench_configs(yb, w, torch)
+    nxt = None
+    if not args.no_next:
+        nxt = bench_next_rows(yb, w, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -352,7 +555,7 @@ def main():
         "energy": float(e[0]), "drift": drift,
         "plain_ms_per_step": plain_ms,
         "speedup_vs_plain": (plain_ms / ms_step) if plain_ms else None,
-        "roofline": roofline, "cpu_baseline": cpu, "uneven_batch": batch, "configs": configs,
+        "roofline": roofline, "cpu_baseline": cpu, "uneven_batch": batch, "configs": configs, "next_rows": nxt,
     }
     print(json.dumps(out))
 

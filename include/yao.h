@@ -197,6 +197,22 @@ int yao_relax(yao_state* s, const int* locs, int k);
  * few passes over the state), not by gates. Batch * element bytes <= 16 KiB. */
 int yao_qft(yao_state* s, const int* locs, int k, int inverse);
 
+/* Faithful gradient (f1) ------------------------------------------------------------------ */
+
+/* The gradient by the shift rule (Sec. "Forward Mode: Faithful Quantum Gradients", eq.
+ * shiftrule), as an experiment would measure it: for every parametrised gate occurrence, the
+ * energies with that gate's angle moved by +pi/2 and by -pi/2 give (E+ - E-) / 2, added to the
+ * gradient of its parameter (a parameter shared by several gates gets the sum over its gates).
+ * Exact for rotations exp(-i theta G / 2) with G reflexive and for phase shifts; for controlled
+ * rotations it is the rule's value, not the derivative. All 2K + 1 circuits (K occurrences, plus
+ * the unshifted one) run as one register of n + s qubits whose top s bits select the circuit
+ * (in chunks when it would exceed a quarter of the free device memory): one forward sweep
+ * through the fused passes, one expectation pass with a sum per circuit. s is the input state
+ * (batch 1, unchanged); energy[0] receives the unshifted energy, grad[p] the gradients.
+ * Synchronises. */
+int yao_shift_grad(const yao_state* s, const yao_circuit* c, const double* params, const yao_pauli_sum* h,
+                   double* energy, double* grad);
+
 /* Time evolution (f3) --------------------------------------------------------------------- */
 
 /* psi_b <- exp(-i H t) psi_b for every slot (time_evolve of Sec. "Matrix Representation"), by

@@ -75,6 +75,7 @@ _SIGS = {
     "yao_qft": [P, P, I, I],
     "yao_probs": [P, P, I, P],
     "yao_time_evolve": [P, P, D, D, I, P],
+    "yao_shift_grad": [P, P, P, P, P, P],
     "yao_measure": [P, P, I, I, P, P],
     "yao_measure_collapse": [P, P, I, P, P, P],
     "yao_profile_enable": [I],
@@ -344,6 +345,15 @@ def qft(state: State, locs, inverse=False):
     """QFT (or its inverse) on the qubits locs, in place."""
     l = _i32(locs)
     _check(lib().yao_qft(state.h, _ptr(l), len(l), int(bool(inverse))))
+
+
+def shift_grad(state: State, circ: Circuit, params, H: PauliSum):
+    """(energy, grad[P]) by the shift rule over every gate occurrence, one batched register."""
+    p = _params(params)
+    e = np.zeros(1)
+    g = np.zeros(max(1, circ.nparams))
+    _check(lib().yao_shift_grad(state.h, circ.h, _ptr(p), H.h, _ptr(e), _ptr(g)))
+    return e[0], g[:circ.nparams]
 
 
 def time_evolve(state: State, H: PauliSum, t: float, tol: float = 0.0, krylov_dim: int = 0) -> int:

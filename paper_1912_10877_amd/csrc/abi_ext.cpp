@@ -125,6 +125,21 @@ int check_uniforms(const double* u, size_t count)
 
 extern "C" {
 
+int yao_shift_grad(const yao_state* s, const yao_circuit* c, const double* params, const yao_pauli_sum* h,
+                   double* energy, double* grad)
+{
+    YAO_TRY(check_state(s));
+    if (!c || !h) return set_error(YAO_EINVAL, "circuit or observable is NULL");
+    if (c->n != s->n || h->n != s->n) return set_error(YAO_EINVAL, "qubit counts of state, circuit, observable differ");
+    if (s->batch != 1) return set_error(YAO_EINVAL, "the shift-rule gradient takes a batch-1 state, got %d", s->batch);
+    if (c->nparams > 0 && (!params || !grad)) return set_error(YAO_EINVAL, "params or grad is NULL");
+    if (!energy) return set_error(YAO_EINVAL, "energy is NULL");
+    for (int p = 0; p < c->nparams; ++p)
+        if (!std::isfinite(params[p])) return set_error(YAO_EINVAL, "params[%d] is not finite", p);
+    YAO_TRY(ensure_device());
+    return shift_grad(s, c, params, const_cast<yao_pauli_sum*>(h), energy, grad);
+}
+
 int yao_time_evolve(yao_state* s, const yao_pauli_sum* h, double t, double tol, int krylov_dim, int* nsteps)
 {
     YAO_TRY(check_state(s));

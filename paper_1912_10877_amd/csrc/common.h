@@ -85,6 +85,10 @@ inline BatchGeom make_batch_geom(int B)
 // ------------------------------------------------------------------------------------------
 // Host-side objects behind the opaque handles of the C ABI.
 // ------------------------------------------------------------------------------------------
+// Controls a gate record holds: the C ABI takes up to 8; the shifted-circuit register of the
+// faithful gradient adds one control per slot bit.
+constexpr int kGateMaxCtrl = 32;
+
 struct GateRec {
     int kind;             // enum yao_gate
     int param;            // -1: fixed
@@ -92,8 +96,8 @@ struct GateRec {
     int k;
     int locs[8];
     int nctrl;
-    int ctrls[8];
-    int cvals[8];
+    int ctrls[kGateMaxCtrl];
+    int cvals[kGateMaxCtrl];
     std::vector<double> G;  // 2 * 4^k doubles for ROT / DENSE
 };
 

@@ -245,7 +245,7 @@ int build_program(const Plan& P, const yao_circuit* c, const double* params, boo
                     // The gate as a 16 x 16 matrix on the group's register bits (index bit j <->
                     // tile bit gd.rpos[j]) with its controls on those bits folded in, stored in
                     // the state's precision: rows of re[16] then im[16].
-                    int tp[kMaxDenseK], cpos[8];
+                    int tp[kMaxDenseK], cpos[kGateMaxCtrl];
                     for (int j = 0; j < g.k; ++j) {
                         tp[j] = -1;
                         for (int r = 0; r < kRegBitsFwd; ++r)
@@ -455,7 +455,7 @@ int launch_forward_passes(const Plan& P, const Program& prog, const DevProgram& 
             const GateRec& g = c->gates[P.ops[pass.standalone].gate];
             HostMat U;
             U.k = g.k;
-            int locs[8], ctrls[8];
+            int locs[8], ctrls[kGateMaxCtrl];
             layout_qubits(pass, g, locs, ctrls);
             YAO_TRY(launch_gate(data, dtype, n, B, U, locs, make_ctrl(g.nctrl, ctrls, g.cvals),
                                 d.mats + prog.pass_mat[p]));
@@ -483,7 +483,7 @@ int launch_backward_passes(const Plan& P, const Program& prog, const DevProgram&
             HostMat Ud, M;
             Ud.k = M.k = g.k;
             const int slot = prog.slot_of_gate[gi];
-            int locs[8], ctrls[8];
+            int locs[8], ctrls[kGateMaxCtrl];
             layout_qubits(pass, g, locs, ctrls);
             YAO_TRY(launch_adjoint_step_strided(psi, lam, lam_dtype, n, B, Ud, slot >= 0 ? &M : nullptr, locs,
                                                 make_ctrl(g.nctrl, ctrls, g.cvals), d.mats + prog.pass_mat[p],

@@ -109,7 +109,7 @@ std::vector<FusedPart> partition(const yao_circuit* c, int width)
 void apply_left(HostMat& M, const GateRec& g, const HostMat& U, const std::vector<int>& qs)
 {
     const int D = M.dim(), du = U.dim();
-    int tp[8], cp[8];
+    int tp[8], cp[kGateMaxCtrl];
     uint32_t tmask = 0, cmask = 0, cval = 0;
     for (int j = 0; j < g.k; ++j) {
         tp[j] = position(qs, g.locs[j]);

@@ -1818,6 +1818,12 @@ bool obs_passes_ok(const yao_pauli_sum* h, int n, int B, int dtype)
     return P && P->ok;
 }
 
+int obs_tile_qubits(const yao_pauli_sum* h, int n, int B, int dtype)
+{
+    const ObsPlan* P = obs_plan(h, n, B, dtype);
+    return P && P->ok ? P->t - P->c : 0;
+}
+
 size_t obs_partial_doubles(const yao_pauli_sum* h, int n, int B, int dtype)
 {
     const ObsPlan* P = obs_plan(h, n, B, dtype);

@@ -187,19 +187,26 @@ __global__ __launch_bounds__(kMThreads) void k_collapse(vec2_t<R>* __restrict__ 
                                                         uint64_t mask, const uint64_t* __restrict__ dep,
                                                         const double* __restrict__ scale)
 {
-    const uint64_t e = (uint64_t)blockIdx.x * kMThreads + threadIdx.x;
-    if (e >= elems) return;
-    const uint64_t i = e / B, b = e - i * B;
-    vec2_t<R> a = psi[e];
-    if ((i & mask) == dep[b]) {
-        const R s = (R)scale[b];
-        a.x *= s;
-        a.y *= s;
-    } else {
-        a.x = 0;
-        a.y = 0;
+    for (uint64_t e = (uint64_t)blockIdx.x * kMThreads + threadIdx.x; e < elems; e += (uint64_t)gridDim.x * kMThreads) {
+        const uint64_t i = e / B, b = e - i * B;
+        vec2_t<R> a = psi[e];
+        if ((i & mask) == dep[b]) {
+            const R s = (R)scale[b];
+            a.x *= s;
+            a.y *= s;
+        } else {
+            a.x = 0;
+            a.y = 0;
+        }
+        psi[e] = a;
     }
-    psi[e] = a;
+}
+
+// Blocks of a grid-stride elementwise launch over `count` items.
+unsigned grid_blocks(uint64_t count)
+{
+    const uint64_t nb = (count + kMThreads - 1) / kMThreads;
+    return (unsigned)(nb < 65536 ? nb : 65536);
 }
 
 bool locs_are_low(const int* locs, int k)
@@ -305,11 +312,11 @@ int launch_collapse(yao_state* s, const double* probs, const int* locs_dev, cons
     const uint64_t elems = s->elems();
     const int pi = prof_begin(YAO_KF_MEASURE);
     if (s->dtype == YAO_C64)
-        k_collapse<float><<<(unsigned)((elems + kMThreads - 1) / kMThreads), kMThreads, 0, stream()>>>(
-            (float2*)s->data, elems, B, mask, dep, scale);
+        k_collapse<float><<<grid_blocks(elems), kMThreads, 0, stream()>>>((float2*)s->data, elems, B, mask, dep,
+                                                                           scale);
     else
-        k_collapse<double><<<(unsigned)((elems + kMThreads - 1) / kMThreads), kMThreads, 0, stream()>>>(
-            (double2*)s->data, elems, B, mask, dep, scale);
+        k_collapse<double><<<grid_blocks(elems), kMThreads, 0, stream()>>>((double2*)s->data, elems, B, mask, dep,
+                                                                            scale);
     prof_end(pi, 2.0 * (double)s->bytes(), 2.0 * (double)elems);
     YAO_HIP(hipGetLastError());
     return 0;

@@ -10,6 +10,7 @@
 // tolerance (the Krylov space does not depend on tau), and substeps repeat until t is covered.
 // Every vector operation stays on the device with per-slot coefficients in device memory; the
 // host waits once per substep, for the alphas and betas.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -112,16 +113,16 @@ __global__ __launch_bounds__(kKThreads) void k_normalize(vec2_t<R>* __restrict__
                                                          const double* __restrict__ sumsq, double* __restrict__ beta,
                                                          uint64_t elems, int B)
 {
-    const uint64_t e = (uint64_t)blockIdx.x * kKThreads + threadIdx.x;
-    if (e >= elems) return;
-    const int b = (int)(e % (uint64_t)B);
-    const double nrm = sqrt(sumsq[b]);
-    const R inv = nrm > 1e-300 ? (R)(1.0 / nrm) : R(0);
-    vec2_t<R> x = in[e];
-    x.x *= inv;
-    x.y *= inv;
-    out[e] = x;
-    if (e < (uint64_t)B) beta[b] = nrm;
+    for (uint64_t e = (uint64_t)blockIdx.x * kKThreads + threadIdx.x; e < elems; e += (uint64_t)gridDim.x * kKThreads) {
+        const int b = (int)(e % (uint64_t)B);
+        const double nrm = sqrt(sumsq[b]);
+        const R inv = nrm > 1e-300 ? (R)(1.0 / nrm) : R(0);
+        vec2_t<R> x = in[e];
+        x.x *= inv;
+        x.y *= inv;
+        out[e] = x;
+        if (e < (uint64_t)B) beta[b] = nrm;
+    }
 }
 
 // psi = sum_j y[j][b] V_j for the m Krylov vectors (stride elements apart).
@@ -130,20 +131,20 @@ __global__ __launch_bounds__(kKThreads) void k_combine(vec2_t<R>* __restrict__ p
                                                        uint64_t stride, int m, const double2* __restrict__ y,
                                                        uint64_t elems, int B)
 {
-    const uint64_t e = (uint64_t)blockIdx.x * kKThreads + threadIdx.x;
-    if (e >= elems) return;
-    const int b = (int)(e % (uint64_t)B);
-    double re = 0, im = 0;
-    for (int j = 0; j < m; ++j) {
-        const vec2_t<R> v = V[(uint64_t)j * stride + e];
-        const double2 c = y[(uint64_t)j * B + b];
-        re += c.x * v.x - c.y * v.y;
-        im += c.x * v.y + c.y * v.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * kKThreads + threadIdx.x; e < elems; e += (uint64_t)gridDim.x * kKThreads) {
+        const int b = (int)(e % (uint64_t)B);
+        double re = 0, im = 0;
+        for (int j = 0; j < m; ++j) {
+            const vec2_t<R> v = V[(uint64_t)j * stride + e];
+            const double2 c = y[(uint64_t)j * B + b];
+            re += c.x * v.x - c.y * v.y;
+            im += c.x * v.y + c.y * v.x;
+        }
+        vec2_t<R> o;
+        o.x = (R)re;
+        o.y = (R)im;
+        psi[e] = o;
     }
-    vec2_t<R> o;
-    o.x = (R)re;
-    o.y = (R)im;
-    psi[e] = o;
 }
 
 using cplx = std::complex<double>;
@@ -212,7 +213,7 @@ int lanczos_substep(void* psi, int n, int B, int dtype, const yao_pauli_sum* h, 
     double2* ydev = (double2*)(sums + (size_t)B + 8);
     hipStream_t st = stream();
     dim3 grid(nbx, sg.nchunks);
-    const unsigned eb = (unsigned)((elems + kKThreads - 1) / kKThreads);
+    const unsigned eb = (unsigned)std::min<uint64_t>((elems + kKThreads - 1) / kKThreads, 65536);
     const int pi = prof_begin(YAO_KF_KRYLOV);
     k_norm2<R><<<grid, kKThreads, 0, st>>>((const V*)psi, rows, B, sg.logBc, part);
     YAO_TRY(launch_row_sums(part, B, nbx, sums));

@@ -79,7 +79,7 @@ int run_passes(const Plan& P, const Program& prog, const yao_circuit* c, const d
             const GateRec& g = c->gates[P.ops[pass.standalone].gate];
             HostMat U;
             if (!gate_matrix(g, gate_theta(g, params), U)) return set_error(YAO_EINVAL, "bad gate");
-            int locs[8], ctrls[8];
+            int locs[8], ctrls[kGateMaxCtrl];
             for (int j = 0; j < g.k; ++j) locs[j] = pass.phys.empty() ? g.locs[j] : pass.phys[g.locs[j]];
             for (int m = 0; m < g.nctrl; ++m) ctrls[m] = pass.phys.empty() ? g.ctrls[m] : pass.phys[g.ctrls[m]];
             apply_host(s, n, g.k, locs, g.nctrl, ctrls, g.cvals, U, P.reverse);

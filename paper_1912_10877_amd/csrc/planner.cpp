@@ -1,10 +1,11 @@
 // Host planner of the fused tile passes.
 //
 // Gates are taken in order. A gate may join a pass when its targets lie in the pass's tile
-// and it shares no qubit (target or control) with a gate that was deferred earlier in this
-// scan -- so moving it ahead of those gates cannot change the result, since operators on
-// disjoint qubits commute. The same rule, with 3 or 4 register bits in place of the tile,
-// splits a pass into register groups.
+// and neither its targets touch a qubit of a gate deferred earlier in this scan nor its
+// controls touch such a gate's targets -- so moving it ahead of those gates cannot change the
+// result: two controlled gates that share only control qubits are block diagonal in those
+// qubits and act on disjoint targets, so they commute like gates on disjoint qubits. The same
+// rule, with 3 or 4 register bits in place of the tile, splits a pass into register groups.
 //
 // Tiles are grown one qubit at a time, each time adding the qubit that lets the pass take the
 // most gates. On a layered circuit this alternates between overlapping windows whose gates
@@ -67,15 +68,16 @@ uint64_t bit(int q)
 int take_ops(const Plan& P, const yao_circuit* circ, const std::vector<int>& remaining, uint64_t T, int maxk,
              bool dense_ok, int max_ops, uint64_t all, std::vector<int>* sel, std::vector<int>* rest)
 {
-    uint64_t blocked = 0;
+    uint64_t blocked = 0, blocked_t = 0;  // qubits / targets of the deferred ops
     int nsel = 0, ndense = 0;
     for (int oi : remaining) {
         const HostOp& op = P.ops[oi];
         const int k = circ->gates[op.gate].k;
         const bool dense = dense_ok && k > 1;
-        if ((op.qmask & blocked) || (op.tmask & ~T) || k > maxk || nsel >= max_ops ||
+        if ((op.tmask & blocked) || (op.qmask & blocked_t) || (op.tmask & ~T) || k > maxk || nsel >= max_ops ||
             (dense && ndense >= kMaxPassDense)) {
             blocked |= op.qmask;
+            blocked_t |= op.tmask;
             if (rest) rest->push_back(oi);
             else if ((blocked & all) == all) break;
             continue;
@@ -344,7 +346,7 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
         std::vector<int> prem = taken[k];
         while (!prem.empty()) {
             HostGroup grp;
-            uint64_t R = 0, gblocked = 0;
+            uint64_t R = 0, gblocked = 0, gblocked_t = 0;
             std::vector<int> gsel, grest;
             bool lds_first = circ->gates[P.ops[prem[0]].gate].k > 1;
             if (lds_first && dense_ok) {
@@ -383,8 +385,9 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
                 const bool grad = reverse && is_param_kind(gr.kind) && gr.param >= 0;
                 uint64_t rb = 0;
                 for (int j = 0; j < k1; ++j) rb |= bit(tile_bit(gr.locs[j]));
-                if ((op.qmask & gblocked) || k1 > 1 || (grad && nslot >= max_slots)) {
+                if ((op.tmask & gblocked) || (op.qmask & gblocked_t) || k1 > 1 || (grad && nslot >= max_slots)) {
                     gblocked |= op.qmask;
+                    gblocked_t |= op.tmask;
                     grest.push_back(oi);
                     continue;
                 }
@@ -394,6 +397,7 @@ Plan make_plan(const yao_circuit* circ, int g0, int g1, int B, int t, int cbits,
                     nslot += grad ? 1 : 0;
                 } else {
                     gblocked |= op.qmask;
+                    gblocked_t |= op.tmask;
                     grest.push_back(oi);
                 }
             }

@@ -116,6 +116,8 @@ size_t hpsi_partial_doubles(const yao_pauli_sum* h, int n, int B, int dtype);
 // energy partials partial[b * W + column].
 bool obs_passes_ok(const yao_pauli_sum* h, int n, int B, int dtype);
 size_t obs_partial_doubles(const yao_pauli_sum* h, int n, int B, int dtype);
+// Qubits of each observable pass's tile (the non-tile qubits index the tiles, ascending).
+int obs_tile_qubits(const yao_pauli_sum* h, int n, int B, int dtype);
 int launch_obs_passes(const void* psi, int dtype, void* out, int out_dtype, int n, int B, const yao_pauli_sum* h,
                       double* partial, int* W);
 void drop_obs_plans(const yao_pauli_sum* h);
@@ -172,6 +174,10 @@ int launch_permute(const void* in, void* out, int dtype, int n, int B, const int
 int launch_qft(void* data, int dtype, int n, int B, const int* locs, int k, bool inverse);
 int qft_passes(int dtype, int n, int B, const int* locs, int k);
 
+// Faithful gradient by the shift rule, every shifted circuit in one register (shift.hip):
+// energy (host, 1 value) and grad (host, c->nparams values) of the batch-1 state st.
+int shift_grad(const yao_state* st, const yao_circuit* c, const double* params, yao_pauli_sum* h, double* energy,
+               double* grad);
 // psi <- exp(-i H t) psi per slot by the Lanczos method (krylov.hip); nsteps: substeps taken.
 int time_evolve(yao_state* s, yao_pauli_sum* h, double t, double tol, int krylov_dim, int* nsteps);
 

@@ -51,3 +51,31 @@ def test_layout_planner_beats_one_layer_per_pass():
         err, npass = yb.plan_selfcheck(c, w.angles(3, circ.nparams), 0, reverse, 0)
         assert err < 1e-11
         assert npass <= 8, npass
+
+
+@pytest.mark.parametrize("reverse", [False, True])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_gates_sharing_only_controls_reorder_correctly(seed, reverse):
+    """Rotations on low qubits controlled by a shared set of high qubits (with different control
+    values, the shape of the shifted-circuit register of the faithful gradient), mixed with
+    CNOTs whose targets are those control qubits: the planner lets gates that share only
+    control qubits pass each other, but never past a gate that targets one of them."""
+    rng = np.random.default_rng(seed)
+    n, hi = 16, [12, 13, 14, 15]
+    gates, p = [], 0
+    for layer in range(6):
+        for q in range(12):
+            gates.append(w.Gate("Rx", (q,), param=p))
+            p += 1
+            if rng.random() < 0.5:
+                cv = tuple(int(v) for v in rng.integers(0, 2, len(hi)))
+                gates.append(w.Gate(["Rx", "Ry", "Rz"][int(rng.integers(3))], (q,), ctrls=tuple(hi), cvals=cv,
+                                    theta=float(rng.uniform(0, 6.3))))
+        for q in range(11):
+            gates.append(w.Gate("X", (q + 1,), ctrls=(q,)))
+        gates.append(w.Gate("X", (hi[layer % 4],), ctrls=(int(rng.integers(12)),)))
+    circ = w.Circuit(n, gates, p)
+    c = yb.Circuit.from_workload(circ)
+    for tq in (0, 6):
+        err, npass = yb.plan_selfcheck(c, w.angles(seed, p), 1, reverse, tq)
+        assert err < 1e-11, (tq, err, npass)
