@@ -544,6 +544,7 @@ int record(Cache& C)
     YAO_HIP(hipStreamSynchronize(cs));
     YAO_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     prof_suspend(true);
+    set_recording(true);
     int rc = 0;
     do {
         if (hipEventRecord(g_fork, cs) != hipSuccess) {
@@ -598,6 +599,7 @@ int record(Cache& C)
         }
     } while (0);
     prof_suspend(false);
+    set_recording(false);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &graph);
     if (rc || e != hipSuccess) {

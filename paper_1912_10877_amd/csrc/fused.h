@@ -184,6 +184,21 @@ struct DevProgram {
     PGroupDesc* groups;
     double* mats;
 };
+// One circuit of a launch over several circuits of one structure (grid z): its state (psi),
+// adjoint state or H psi output (lam), program records (ops: the program's first record; the
+// pass's offset is added by the kernel) and partial sums.
+struct ZSlot {
+    void* psi;
+    void* lam;
+    const POp* ops;
+    double* partial;
+};
+// While set (nz > 0), pass and observable launches run over the nz circuits of zs (device
+// memory) instead of their own pointers; the rest of a launch (plan, groups, matrices, tiles)
+// is shared. launch_hpsi_dev then also sums the energies of all nz circuits (partials nz * B
+// rows apart by the observable's partial size, energies to consecutive entries).
+void set_zbatch(const ZSlot* zs, int nz);
+int zbatch_count();
 // lam_bytes: bytes per element of the adjoint state (reverse plans size their register groups'
 // gradient buffers by it).
 const Plan& get_plan(const yao_circuit* c, int g0, int g1, int B, int t, int cb, int L, bool reverse,

@@ -24,6 +24,25 @@
 namespace yao {
 
 namespace {
+struct ZBatch {
+    const ZSlot* zs = nullptr;
+    int nz = 0;
+};
+ZBatch g_zbatch;
+}  // namespace
+
+void set_zbatch(const ZSlot* zs, int nz)
+{
+    g_zbatch.zs = nz > 0 ? zs : nullptr;
+    g_zbatch.nz = nz > 0 ? nz : 0;
+}
+
+int zbatch_count()
+{
+    return g_zbatch.zs ? g_zbatch.nz : 1;
+}
+
+namespace {
 
 struct PassArgs {
     void* psi;
@@ -47,7 +66,29 @@ struct PassArgs {
     int ssrc[kMaxTileBits];
     uint32_t sreg[1 << kMaxRegBits];
     int mslots;             // reverse passes: gradient-carrying ops per register group (at most)
+    // Launches over several circuits of one structure (grid z): circuit z's state, adjoint
+    // state, records (ops: program base, plus op_first) and partial sums; null: one circuit.
+    const ZSlot* zs;
+    int op_first;
 };
+
+// The per-circuit pointers of a launch (the circuit's own, or its z slot's).
+__device__ __forceinline__ void* z_psi(const PassArgs& a)
+{
+    return a.zs ? a.zs[blockIdx.z].psi : a.psi;
+}
+__device__ __forceinline__ void* z_lam(const PassArgs& a)
+{
+    return a.zs ? a.zs[blockIdx.z].lam : a.lam;
+}
+__device__ __forceinline__ const POp* z_ops(const PassArgs& a)
+{
+    return a.zs ? a.zs[blockIdx.z].ops + a.op_first : a.ops;
+}
+__device__ __forceinline__ double* z_partial(const PassArgs& a, double* p)
+{
+    return a.zs ? a.zs[blockIdx.z].partial : p;
+}
 
 __device__ __forceinline__ uint32_t swz(uint32_t e)
 {
@@ -839,10 +880,10 @@ __global__ __launch_bounds__(512, sizeof(RP) == 4 ? 3 : 1) void k_pass_fwd(PassA
     // LDS: tile | dense block matrices (2 * 256 RP each), sized for this pass.
     VP* lp = (VP*)smem;
     uint4* ldm = (uint4*)(smem + (sizeof(VP) << t));
-    const YAO_CONST POp* gops = cptr(a.ops);
+    const YAO_CONST POp* gops = cptr(z_ops(a));
     const YAO_CONST PGroupDesc* ggrp = cptr(a.groups);
     const TileCtx tc = tile_ctx<RB>(a, th);
-    VP* gp = (VP*)a.psi;
+    VP* gp = (VP*)z_psi(a);
     // Every load is in bounds (slots past B read the last slot and are never stored), so all
     // of them are issued before the first wait.
     {
@@ -1113,8 +1154,8 @@ __global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
     VL* ll = (VL*)(smem + ((size_t)16 << t));
     double* red0 = (double*)(smem + ((size_t)(16 + sizeof(VL)) << t));
     const TileCtx tc = tile_ctx<RB>(a, th);
-    double2* gp = (double2*)a.psi;
-    VL* gl = (VL*)a.lam;
+    double2* gp = (double2*)z_psi(a);
+    VL* gl = (VL*)z_lam(a);
     {
         double2 v[N];
         VL w[N];
@@ -1133,8 +1174,8 @@ __global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
     }
     __syncthreads();
 
-    const GradOut go{a.gpartial, a.B, a.pstride, (int)blockIdx.x, (int)blockIdx.y << c};
-    const double2 ph = reverse_groups<RL, C0>(lp, ll, red0, cptr(a.ops), cptr(a.groups), a.groups, a.ngroups,
+    const GradOut go{z_partial(a, a.gpartial), a.B, a.pstride, (int)blockIdx.x, (int)blockIdx.y << c};
+    const double2 ph = reverse_groups<RL, C0>(lp, ll, red0, cptr(z_ops(a)), cptr(a.groups), a.groups, a.ngroups,
                                               a.mats, tc.base, t, c, nthr, th, a.mslots, go);
 
     if (tc.bvalid) {
@@ -1326,7 +1367,7 @@ __global__ __launch_bounds__(512) void k_obs_pass(PassArgs a, const ObsGroupT* _
     VP* lp = (VP*)smem;
     double* red = (double*)(smem + (sizeof(VP) << t));
     const TileCtx tc = tile_ctx<RB>(a, th);
-    const VP* gp = (const VP*)a.psi;
+    const VP* gp = (const VP*)z_psi(a);
     {
         VP v[N];
 #pragma unroll
@@ -1337,7 +1378,8 @@ __global__ __launch_bounds__(512) void k_obs_pass(PassArgs a, const ObsGroupT* _
     __syncthreads();
     const YAO_CONST ObsGroupT* gq = cptr(groups);
     const YAO_CONST ObsTermT* tq = cptr(terms);
-    VO* go = (VO*)a.lam;
+    VO* go = (VO*)z_lam(a);
+    partial = z_partial(a, partial);
     // Table entries are read once per thread (scalar loads) and applied to the thread's 16
     // elements: group by group, term by term.
     double orr[N], oi[N];
@@ -1642,13 +1684,16 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
     a.ngroups = ngroups;
     a.nops = nops;
     a.mslots = mslots;
+    a.zs = g_zbatch.zs;
+    a.op_first = op_first;
     tile_args(a, n, B, c, t, tile_qubits, bwd ? kRegBitsBwd : kRegBitsFwd, store_src);
     a.pstride = pstride > a.ntiles ? pstride : a.ntiles;
     const int Bc = 1 << c;
     const int RBk = bwd ? kRegBitsBwd : kRegBitsFwd;
     // The kernels are compiled for at most 512 threads per block (one tile, 2^(t - RB) threads).
     if (t - RBk < 0 || t - RBk > 9) return set_error(YAO_EINVAL, "tile of 2^%d does not fit 1 .. 512 threads", t);
-    dim3 grid(a.ntiles, (B + Bc - 1) / Bc);
+    const int nz = g_zbatch.zs ? g_zbatch.nz : 1;
+    dim3 grid(a.ntiles, (B + Bc - 1) / Bc, nz);
     dim3 block(1 << (t - RBk));
     const int pb = bwd ? 16 : (psi_dtype == YAO_C64 ? 8 : 16);
     const int lb = bwd ? (lam_dtype == YAO_C64 ? 8 : 16) : 0;
@@ -1683,7 +1728,7 @@ int launch_pass(bool bwd, int psi_dtype, int lam_dtype, void* psi, void* lam, co
             }
         }
     }
-    prof_end(pi, 2.0 * (double)(uint64_t(1) << n) * B * (pb + lb), flops);
+    prof_end(pi, 2.0 * (double)(uint64_t(1) << n) * B * (pb + lb) * nz, flops * nz);
     YAO_HIP(hipGetLastError());
     return 0;
 }
@@ -1844,7 +1889,7 @@ int launch_obs_passes(const void* psi, int dtype, void* out, int out_dtype, int 
     const int ntiles = 1 << (n - (t - c));
     *W = (int)P->passes.size() * ntiles;
     const int Bc = 1 << c;
-    const dim3 grid(ntiles, (B + Bc - 1) / Bc);
+    const dim3 grid(ntiles, (B + Bc - 1) / Bc, g_zbatch.zs ? g_zbatch.nz : 1);
     const size_t lds = ((size_t)(dtype == YAO_C64 ? 8 : 16) << t) + sizeof(double) * (size_t)grad_entries(nthr, c);
     for (size_t p = 0; p < P->passes.size(); ++p) {
         const ObsPass& ps = P->passes[p];
@@ -1852,6 +1897,7 @@ int launch_obs_passes(const void* psi, int dtype, void* out, int out_dtype, int 
         memset(&a, 0, sizeof(a));
         a.psi = const_cast<void*>(psi);
         a.lam = out;
+        a.zs = g_zbatch.zs;
         tile_args(a, n, B, c, t, ps.tile_qubits, kObsRegBits);
         const int acc = p > 0 ? 1 : 0, col = (int)p * ntiles;
         if (!out) {

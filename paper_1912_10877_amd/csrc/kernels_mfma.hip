@@ -3,115 +3,136 @@
 // A K-qubit gate maps each group of D = 2^K amplitudes (the indices that differ only in the
 // target bits) through a D x D complex matrix. Taking 32 groups as the columns of a
 // 2D x 32 real matrix [Re a; Im a], the update is one real GEMM with the 2D x 2D matrix
-// [[Re U, -Im U], [Im U, Re U]]. Each wave computes its 32 columns with
-// v_mfma_f32_16x16x4f32: the gate matrix stays in the A-operand registers, the amplitudes
-// of each lane's column are gathered once and fed as B operands, and the 16x16 accumulator
-// tiles hold the real and imaginary halves of each output amplitude in the same lane.
+// [[Re U, -Im U], [Im U, Re U]], which each wave computes with v_mfma_f32_16x16x4f32: the gate
+// matrix stays in the A-operand registers, each lane's column is read once as B operands, and
+// the 16x16 accumulator tiles hold the real and imaginary halves of each output amplitude in the
+// same lane.
+//
+// The amplitudes move through LDS: a workgroup loads a tile of 2^m index rows (the K target
+// bits and the lowest other bits, so every tile row run is contiguous in memory whatever the
+// targets), the waves run their columns out of LDS, and the tile is stored back the same way.
+#include <algorithm>
+#include <vector>
+
 #include "runtime.h"
 
 namespace yao {
 
 namespace {
 
-template <int K> struct MfmaGeom {
-    uint64_t off[1 << K];  // index offset of member s of a group
-    int sorted[K];         // target bits ascending, for building group bases
+constexpr int kMfmaTileBits = 12;  // 2^12 complex64 rows: 32 KiB of LDS per batch slot
+
+// Per-launch tables (the same for every workgroup).
+struct MfmaTables {
+    uint64_t in_lo[64], in_hi[64];   // index bits of tile row r: in_lo[r & 63] | in_hi[r >> 6]
+    uint32_t col_lo[64], col_hi[64]; // tile row of column (group) g: col_lo[g & 63] | col_hi[g >> 6]
+    uint32_t mem[32];                // tile-row offset of member s of a group
 };
 
-template <int K> __device__ __forceinline__ uint64_t mfma_group_base(uint64_t j, const MfmaGeom<K>& g)
-{
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-        const uint64_t lo = j & ((uint64_t(1) << g.sorted[t]) - 1);
-        j = ((j >> g.sorted[t]) << (g.sorted[t] + 1)) | lo;
-    }
-    return j;
-}
+// Passed by value: a launch recorded into a graph keeps its own copy of the tables.
+struct MfmaArgs {
+    MfmaTables tab;
+    uint64_t ntiles;
+    int m, K, nrest, B;
+    uint64_t cmask, cval;
+    int rpos[40];  // index bit of block index bit j
+};
+
+static_assert(sizeof(MfmaArgs) + 16 <= 4096, "kernel arguments must fit the 4 KiB argument segment");
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// LDS row of tile row r: bits 5..9 XORed into bits 0..4. Tile loads and stores run along
+// consecutive rows (low bits varying), a wave's 16 columns along the column bits, which sit
+// above the targets when the targets are low qubits; the swizzle spreads both over the banks.
+__device__ __forceinline__ int swz5(int r)
+{
+    return r ^ ((r >> 5) & 31);
+}
 
 // Lane layout of v_mfma_f32_16x16x4f32 (one block): A[i][k] from lane i + 16 k, B[k][j]
 // from lane j + 16 k, D[4 (l / 16) + v][l % 16] in accumulator register v of lane l.
 template <int K>
-__global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, uint64_t ngroups, uint32_t B,
-                                                    MfmaGeom<K> gg, uint64_t cmask, uint64_t cval,
-                                                    const float* __restrict__ M)
+__global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, MfmaArgs a, const float* __restrict__ M)
 {
     constexpr int D = 1 << K, RD = 2 * D, RT = RD / 16, KC = RD / 4, NA = D / 4;
-    const int lane = threadIdx.x & 63;
-    const uint64_t wave = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-    const uint64_t col0 = wave * 32;
-    if (col0 >= ngroups) return;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    MfmaTables* t = reinterpret_cast<MfmaTables*>(lds_raw);
+    float2* tile = reinterpret_cast<float2*>(lds_raw + sizeof(MfmaTables));
+    {
+        const uint32_t* g = reinterpret_cast<const uint32_t*>(&a.tab);
+        uint32_t* d = reinterpret_cast<uint32_t*>(t);
+        for (int i = threadIdx.x; i < (int)(sizeof(MfmaTables) / 4); i += 256) d[i] = g[i];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, cl = lane & 15;
-    float a[RT][KC];
+    float am[RT][KC];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) a[rt][kc] = M[(16 * rt + cl) * RD + 4 * kc + q];
-
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-        const uint64_t g = col0 + 16 * ct + cl;
-        const bool valid = g < ngroups;
-        const uint64_t j = valid ? g / B : 0;
-        const uint64_t b = valid ? g % B : 0;
-        const uint64_t base = mfma_group_base<K>(j, gg);
-        const bool on = valid && ((base & cmask) == cval);
-        float2 amp[NA];
-#pragma unroll
-        for (int m = 0; m < NA; ++m) {
-            amp[m] = make_float2(0.f, 0.f);
-            if (valid) amp[m] = psi[(base + gg.off[q + 4 * m]) * B + b];
+        for (int kc = 0; kc < KC; ++kc) am[rt][kc] = M[(16 * rt + cl) * RD + 4 * kc + q];
+    const int B = a.B;
+    const int rows = 1 << a.m;
+    const int E = rows * B;
+    const int ncols = (rows >> K) * B;  // (group, slot) columns of a tile
+    // Workgroups loop over tiles, so the matrix fragments above are read once per workgroup.
+    for (uint64_t tix = blockIdx.x; tix < a.ntiles; tix += gridDim.x) {
+        uint64_t base = 0;
+        for (int j = 0; j < a.nrest; ++j) base |= ((tix >> j) & 1) << a.rpos[j];
+        __syncthreads();
+        for (int e = threadIdx.x; e < E; e += 256) {
+            const int row = B == 1 ? e : e / B, b = e - row * B;
+            tile[swz5(row) * B + b] = psi[(base | t->in_lo[row & 63] | t->in_hi[row >> 6]) * B + b];
         }
-        v4f acc[RT];
+        __syncthreads();
+        for (int c0 = wave * 32; c0 < ncols; c0 += 4 * 32) {
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+            for (int ct = 0; ct < 2; ++ct) {
+                const int col = c0 + 16 * ct + cl;
+                const bool valid = col < ncols;
+                const int g = !valid ? 0 : (B == 1 ? col : col / B), b = valid ? col - g * B : 0;
+                const int r0 = (int)(t->col_lo[g & 63] | t->col_hi[g >> 6]);
+                const uint64_t idx0 = base | t->in_lo[r0 & 63] | t->in_hi[r0 >> 6];
+                const bool on = valid && ((idx0 & a.cmask) == a.cval);
+                float2 amp[NA];
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            const int m = kc % NA;
-            const float bv = (kc / NA) == 0 ? amp[m].x : amp[m].y;
+                for (int m = 0; m < NA; ++m)
+                    amp[m] = valid ? tile[swz5(r0 | t->mem[q + 4 * m]) * B + b] : make_float2(0.f, 0.f);
+                v4f acc[RT];
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][kc], bv, acc[rt], 0, 0, 0);
-        }
-        if (on) {
+                for (int rt = 0; rt < RT; ++rt) acc[rt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int rt = 0; rt < RT / 2; ++rt)
+                for (int kc = 0; kc < KC; ++kc) {
+                    const int m = kc % NA;
+                    const float bv = (kc / NA) == 0 ? amp[m].x : amp[m].y;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int s = 16 * rt + 4 * q + v;
-                    psi[(base + gg.off[s]) * B + b] = make_float2(acc[rt][v], acc[rt + RT / 2][v]);
+                    for (int rt = 0; rt < RT; ++rt) acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[rt][kc], bv, acc[rt], 0, 0, 0);
                 }
+                if (on) {
+#pragma unroll
+                    for (int rt = 0; rt < RT / 2; ++rt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int s = 16 * rt + 4 * q + v;
+                            tile[swz5(r0 | t->mem[s]) * B + b] = make_float2(acc[rt][v], acc[rt + RT / 2][v]);
+                        }
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < E; e += 256) {
+            const int row = B == 1 ? e : e / B, b = e - row * B;
+            psi[(base | t->in_lo[row & 63] | t->in_hi[row >> 6]) * B + b] = tile[swz5(row) * B + b];
         }
     }
-}
-
-template <int K> MfmaGeom<K> mfma_geom(const int* locs)
-{
-    MfmaGeom<K> g;
-    for (int s = 0; s < (1 << K); ++s) {
-        uint64_t o = 0;
-        for (int j = 0; j < K; ++j)
-            if ((s >> j) & 1) o |= uint64_t(1) << locs[j];
-        g.off[s] = o;
-    }
-    int tmp[K];
-    for (int j = 0; j < K; ++j) tmp[j] = locs[j];
-    for (int x = 0; x < K; ++x)
-        for (int y = x + 1; y < K; ++y)
-            if (tmp[y] < tmp[x]) {
-                int t = tmp[x];
-                tmp[x] = tmp[y];
-                tmp[y] = t;
-            }
-    for (int j = 0; j < K; ++j) g.sorted[j] = tmp[j];
-    return g;
 }
 
 }  // namespace
 
 bool mfma_supported(int k, int n, int B)
 {
-    return (k == 4 || k == 5) && ((uint64_t(1) << (n - k)) * (uint64_t)B) < (uint64_t(1) << 40) && B < (1 << 30);
+    // A tile holds at least the 2^k members x B slots of a group (<= 64 KiB of LDS).
+    return (k == 4 || k == 5) && n >= k && n - kMfmaTileBits < 31 && ((size_t)B << k) <= 8192;
 }
 
 // Real form [[Ur, -Ui], [Ui, Ur]] of U in FP32, row-major 2D x 2D: the operand the kernel reads.
@@ -140,16 +161,64 @@ int launch_dense_mfma(float2* psi, int n, int B, const HostMat& U, const int* lo
         dm = (const float*)ring_upload(h.data(), h.size() * sizeof(float));
         if (!dm) return YAO_ENOMEM;
     }
-    const uint64_t ngroups = (uint64_t(1) << (n - k)) * (uint64_t)B;
-    const uint64_t waves = (ngroups + 31) / 32;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
-    const double elems = (double)(uint64_t(1) << n) * B / double(uint64_t(1) << __builtin_popcountll(c.mask));
+    // Tile bits: the targets and the lowest other index bits, up to 2^12 rows (fewer rows for
+    // wide batches: the tile holds 2^m rows x B slots within 32 KiB).
+    int mmax = kMfmaTileBits;
+    while (mmax > k && ((size_t)B << mmax) * 8 > (size_t)32 * 1024) --mmax;
+    uint64_t mask = 0;
+    for (int j = 0; j < k; ++j) mask |= uint64_t(1) << locs[j];
+    for (int b = 0; b < n && __builtin_popcountll(mask) < std::min(n, mmax); ++b) mask |= uint64_t(1) << b;
+    MfmaArgs a;
+    memset(&a, 0, sizeof(a));
+    a.K = k;
+    a.B = B;
+    a.cmask = c.mask;
+    a.cval = c.val;
+    std::vector<int> tpos;
+    for (int b = 0; b < n; ++b) ((mask >> b) & 1 ? tpos.push_back(b) : (void)(a.rpos[a.nrest++] = b));
+    a.m = (int)tpos.size();
+    MfmaTables& tab = a.tab;
+    for (int h = 0; h < 64; ++h)
+        for (int j = 0; j < 6; ++j) {
+            if (!((h >> j) & 1)) continue;
+            if (j < a.m) tab.in_lo[h] |= uint64_t(1) << tpos[j];
+            if (j + 6 < a.m) tab.in_hi[h] |= uint64_t(1) << tpos[j + 6];
+        }
+    // Row bits of the targets (member bits) and of the other tile bits (column bits).
+    int trow[8], nt = 0, crow[kMfmaTileBits], nc = 0;
+    for (int r = 0; r < a.m; ++r) {
+        bool tgt = false;
+        for (int j = 0; j < k; ++j) tgt |= tpos[r] == locs[j];
+        if (tgt) continue;
+        crow[nc++] = r;
+    }
+    for (int j = 0; j < k; ++j)
+        for (int r = 0; r < a.m; ++r)
+            if (tpos[r] == locs[j]) trow[nt++] = r;
+    for (int s = 0; s < D; ++s) {
+        uint32_t o = 0;
+        for (int j = 0; j < k; ++j)
+            if ((s >> j) & 1) o |= 1u << trow[j];
+        tab.mem[s] = o;
+    }
+    for (int h = 0; h < 64; ++h)
+        for (int j = 0; j < 6; ++j) {
+            if (!((h >> j) & 1)) continue;
+            if (j < nc) tab.col_lo[h] |= 1u << crow[j];
+            if (j + 6 < nc) tab.col_hi[h] |= 1u << crow[j + 6];
+        }
+    a.ntiles = uint64_t(1) << a.nrest;
+    // About eight workgroups per CU, each looping over tiles.
+    const uint64_t blocks = std::min<uint64_t>(a.ntiles, 2048);
+    const size_t lds = sizeof(MfmaTables) + ((size_t)B << a.m) * 8;
+    const double elems = (double)(uint64_t(1) << n) * B;
     const int pi = prof_begin(YAO_KF_MFMA);
-    if (k == 4)
-        k_dense_mfma<4><<<blocks, 256, 0, stream()>>>(psi, ngroups, (uint32_t)B, mfma_geom<4>(locs), c.mask, c.val, dm);
-    else
-        k_dense_mfma<5><<<blocks, 256, 0, stream()>>>(psi, ngroups, (uint32_t)B, mfma_geom<5>(locs), c.mask, c.val, dm);
-    prof_end(pi, 2.0 * 8.0 * elems, 8.0 * D * (double)(uint64_t(1) << n) * B);
+    if (k == 4) k_dense_mfma<4><<<(unsigned)blocks, 256, lds, stream()>>>(psi, a, dm);
+    else k_dense_mfma<5><<<(unsigned)blocks, 256, lds, stream()>>>(psi, a, dm);
+    // Algorithmic work: one read and one write of every element; 8 D real flops per element
+    // (for the elements whose controls pass).
+    const double on = elems / double(uint64_t(1) << __builtin_popcountll(c.mask));
+    prof_end(pi, 2.0 * 8.0 * elems, 8.0 * D * on);
     YAO_HIP(hipGetLastError());
     return 0;
 }

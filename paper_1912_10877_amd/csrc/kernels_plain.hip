@@ -4,9 +4,11 @@
 // Every kernel walks the state with the batch innermost, so consecutive lanes touch
 // consecutive addresses: for a single state (B = 1) the lanes run along the low bits of the
 // pair index, for a batch they run along the batch slots of one amplitude row.
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 
+#include "fused.h"
 #include "runtime.h"
 
 namespace yao {
@@ -30,6 +32,26 @@ __global__ __launch_bounds__(kThreads) void k_fill_basis(vec2_t<R>* __restrict__
     uint64_t e = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     if (e >= elems) return;
     psi[e] = mk<R>(e < (uint64_t)B ? R(1) : R(0), R(0));
+}
+
+// |0...0> in each of a list of single-slot states (blockIdx.y selects the state).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_fill_basis_z(vec2_t<R>* const* __restrict__ ptrs, uint64_t elems)
+{
+    vec2_t<R>* psi = ptrs[blockIdx.y];
+    for (uint64_t e = (uint64_t)blockIdx.x * kThreads + threadIdx.x; e < elems; e += (uint64_t)gridDim.x * kThreads)
+        psi[e] = mk<R>(e == 0 ? R(1) : R(0), R(0));
+}
+
+// dst[y * elems + e] = src_y[e] widened to complex128 (blockIdx.y selects the state).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_convert_z(const vec2_t<R>* const* __restrict__ src,
+                                                        double2* __restrict__ dst, uint64_t elems)
+{
+    const vec2_t<R>* a = src[blockIdx.y];
+    double2* d = dst + (uint64_t)blockIdx.y * elems;
+    for (uint64_t e = (uint64_t)blockIdx.x * kThreads + threadIdx.x; e < elems; e += (uint64_t)gridDim.x * kThreads)
+        d[e] = make_double2((double)a[e].x, (double)a[e].y);
 }
 
 // -------------------------------------------------------------------------------- 1-qubit gate
@@ -485,6 +507,26 @@ int launch_fill_basis(void* data, int dtype, int n, int B)
     return 0;
 }
 
+int launch_fill_basis_z(void* const* ptrs, int nz, int dtype, int n)
+{
+    const uint64_t elems = uint64_t(1) << n;
+    const dim3 grid((unsigned)std::min<uint64_t>((elems + kThreads - 1) / kThreads, 4096), nz);
+    if (dtype == YAO_C64) k_fill_basis_z<float><<<grid, kThreads, 0, stream()>>>((float2* const*)ptrs, elems);
+    else k_fill_basis_z<double><<<grid, kThreads, 0, stream()>>>((double2* const*)ptrs, elems);
+    YAO_HIP(hipGetLastError());
+    return 0;
+}
+
+int launch_convert_z(const void* const* src, int nz, int dtype, double* dst, int n)
+{
+    const uint64_t elems = uint64_t(1) << n;
+    const dim3 grid((unsigned)std::min<uint64_t>((elems + kThreads - 1) / kThreads, 4096), nz);
+    if (dtype == YAO_C64) k_convert_z<float><<<grid, kThreads, 0, stream()>>>((const float2* const*)src, (double2*)dst, elems);
+    else k_convert_z<double><<<grid, kThreads, 0, stream()>>>((const double2* const*)src, (double2*)dst, elems);
+    YAO_HIP(hipGetLastError());
+    return 0;
+}
+
 int launch_reset(yao_state* s)
 {
     return launch_fill_basis(s->data, s->dtype, s->n, s->batch);
@@ -700,8 +742,10 @@ int launch_hpsi_dev(const void* data, int dtype, void* out, int out_dtype, int n
     if (obs_passes_ok(h, n, B, dtype)) {
         int W = 0;
         YAO_TRY(launch_obs_passes(data, dtype, out, out_dtype, n, B, h, partial, &W));
-        return launch_row_sums(partial, B, W, energy_dev);
+        // Over several circuits at once, their partial rows follow each other.
+        return launch_row_sums(partial, B * zbatch_count(), W, energy_dev);
     }
+    if (zbatch_count() > 1) return set_error(YAO_EINVAL, "observable outside the tile passes in a batched launch");
     if (!h->d_groups) return set_error(YAO_EINVAL, "observable tables not uploaded");
     BatchGeom bg = make_batch_geom(B);
     const uint64_t rows = uint64_t(1) << n;

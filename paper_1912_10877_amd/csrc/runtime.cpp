@@ -152,9 +152,20 @@ static constexpr size_t kRingSlot = 64 * 1024;
 static constexpr int kRingSlots = 256;
 static char* g_ring = nullptr;
 static int g_ring_next = 0;
+static bool g_recording = false;
+
+void set_recording(bool on)
+{
+    g_recording = on;
+}
 
 void* ring_upload(const void* host, size_t bytes)
 {
+    if (g_recording) {
+        // A captured copy would keep the host address and read it again at every replay.
+        set_error(YAO_EINVAL, "ring upload while a graph is being recorded");
+        return nullptr;
+    }
     if (bytes > kRingSlot) {
         set_error(YAO_EINVAL, "ring upload of %zu bytes exceeds the slot size", bytes);
         return nullptr;

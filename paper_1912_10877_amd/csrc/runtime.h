@@ -54,7 +54,10 @@ void* pinned(int slot, size_t bytes);
 // Copy a small host block (<= 64 KiB) into the next slot of a device ring and return the slot.
 // The copy is queued on the current stream, so kernels queued after it see the data; slots
 // are reused round-robin after 256 uploads.
+// Refused (YAO_EINVAL) while set_recording(true) is in force: launches recorded into a graph
+// take their constants by value or from buffers that the graph owns.
 void* ring_upload(const void* host, size_t bytes);
+void set_recording(bool on);
 // Copy a host block into workspace slot `slot` (grown as needed), ordered on the stream.
 void* upload_to(int slot, const void* host, size_t bytes);
 
@@ -93,6 +96,10 @@ struct CtrlSpec {
 CtrlSpec make_ctrl(int nctrl, const int* ctrls, const int* cvals);
 
 int launch_reset(yao_state* s);
+// |0...0> into nz single-slot states of n qubits (device array of their data pointers), and
+// those states widened to complex128 into dst (nz consecutive blocks of 2^n elements).
+int launch_fill_basis_z(void* const* ptrs, int nz, int dtype, int n);
+int launch_convert_z(const void* const* src, int nz, int dtype, double* dst, int n);
 int launch_fill_basis(void* data, int dtype, int n, int B);
 // One gate on a state of either precision (per-gate form).
 // k >= 2 matrices come from dev_mat (re block then im block, rounded to the state's real

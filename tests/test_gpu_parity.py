@@ -81,6 +81,28 @@ def test_dense_k_qubit_gate(dtype, k):
     assert np.abs(s.download() - want).max() <= amp_tol(dtype, 2 ** k)
 
 
+@pytest.mark.parametrize("n,B,k,nctrl,seed", [(5, 1, 5, 0, 1), (6, 3, 4, 1, 2), (12, 1, 5, 2, 3), (14, 2, 4, 0, 4),
+                                              (10, 64, 5, 1, 5), (13, 100, 4, 2, 6), (16, 1, 5, 1, 7)])
+def test_dense_blocks_on_matrix_cores(n, B, k, nctrl, seed):
+    """4- and 5-qubit matrices on complex64 states (the FP32 matrix-core kernel, tiles staged in
+    LDS): targets on low and high bits, controls of either value, batches up to 100 slots."""
+    rng = np.random.default_rng(seed)
+    U = w.random_unitary(1 << k, rng)
+    perm = [int(x) for x in rng.permutation(n)]
+    locs = perm[:k]
+    if seed % 2:
+        locs = [0] + [q for q in locs if q != 0][:k - 1]
+    rest = [q for q in range(n) if q not in locs]
+    ctrl = rest[:nctrl]
+    cv = [int(v) for v in rng.integers(0, 2, nctrl)]
+    psi0 = w.random_state(n, B, seed)
+    s = yb.State(n, B, 0)
+    s.upload(psi0)
+    s.apply(U, locs, ctrl, cv)
+    want = oracle.apply_matrix(psi0, n, U, locs, ctrl, cv)
+    assert np.abs(s.download() - want).max() <= amp_tol(0, 2 ** k)
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_state_create_is_zero_state_and_upload_roundtrip(dtype):
     s = yb.State(5, 3, dtype)
