@@ -345,7 +345,7 @@ def profile_family(yb, fam):
 
 
 CASES = ("step20", "step20_b64", "rx25_c128", "rx25_c64", "fwd25_c128", "fwd25_c64", "w5mfma30_c64",
-         "qft25_c128", "perm25_c128", "measure24_c128", "copy1g")
+         "qft25_c128", "perm25_c128", "measure24_c128", "copy1g", "c4batch")
 
 
 def run_case(name, reps):
@@ -419,6 +419,18 @@ def run_case(name, reps):
         yb.forward(s, yb.Circuit.from_workload(c), w.angles(3, c.nparams))
         u = np.random.default_rng(0).random((1, 1 << 20))
         f = lambda: yb.measure(s, list(range(24)), u)
+    elif name == "c4batch":
+        # The 1024-circuit uneven batch (complex64), replayed: a kernel trace counts the
+        # launches of one replay (from one k_bind_jobs dispatch to the next).
+        spec = w.hetero_batch_spec(1024)
+        states, circs, hams, params = [], [], [], []
+        for n, d, seed in spec:
+            c = w.hea_circuit(n, d)
+            states.append(yb.State(n, 1, yb.C64))
+            circs.append(yb.Circuit.from_workload(c))
+            hams.append(yb.PauliSum.from_workload(w.heisenberg(n)))
+            params.append(w.angles(seed, c.nparams))
+        f = lambda: yb.batch_run(states, circs, params, hams)
     else:
         raise SystemExit(f"unknown case {name}; cases: {', '.join(CASES)}")
     f()

@@ -67,6 +67,20 @@ struct Item {
     int W = 0;                    // partial-sum row stride of the reverse passes
     size_t out_e = 0, out_g = 0;  // positions in the output block
     double cost = 0;
+    int unit = -1;  // recording unit (see Unit)
+};
+
+// Circuits recorded together. A z unit holds circuits of one structure (the same gates, the
+// same observable, the same state shape) whose programs are bound on the device: every launch
+// of the unit runs over all of them at once (grid z), each with its own state, records and
+// scratch slice. Any other circuit is a unit of its own, recorded launch by launch.
+struct Unit {
+    int first = 0, count = 0;  // its items: C.items[first .. first + count)
+    bool z = false;
+    int bank = 0, phase = 0;
+    double cost = 0;
+    size_t zf = 0, zo = 0, zb = 0;  // its slot tables in C.d_zs (forward, H psi, reverse)
+    size_t sp = 0;                  // its state pointers in C.d_ptrs
 };
 
 using Key = std::vector<std::tuple<const yao_circuit*, uint64_t, const yao_state*, const yao_pauli_sum*, int>>;
@@ -100,6 +114,9 @@ struct Cache {
     std::vector<SmallLaunch> small_launches;
     BindJob* d_jobs = nullptr;
     int njobs = 0, max_nb = 0;
+    std::vector<Unit> units;  // recording order
+    ZSlot* d_zs = nullptr;
+    void** d_ptrs = nullptr;
 };
 
 Cache* g_cache = nullptr;
@@ -119,6 +136,8 @@ void free_cache(Cache* c)
     if (c->d_params) (void)hipFree(c->d_params);
     if (c->d_small) (void)hipFree(c->d_small);
     if (c->d_jobs) (void)hipFree(c->d_jobs);
+    if (c->d_zs) (void)hipFree(c->d_zs);
+    if (c->d_ptrs) (void)hipFree(c->d_ptrs);
     if (c->h_params) (void)hipHostFree(c->h_params);
     for (int b = 0; b < kBanks; ++b) {
         if (c->psi64[b]) (void)hipFree(c->psi64[b]);
@@ -335,6 +354,51 @@ void pack_params(Cache& C, const double* const* params)
         if (it.c->nparams > 0) memcpy(C.h_params + it.poff, params[it.idx], sizeof(double) * (size_t)it.c->nparams);
 }
 
+bool same_gates(const yao_circuit* a, const yao_circuit* b)
+{
+    if (a == b) return true;
+    if (a->n != b->n || a->nparams != b->nparams || a->gates.size() != b->gates.size()) return false;
+    for (size_t i = 0; i < a->gates.size(); ++i) {
+        const GateRec &x = a->gates[i], &y = b->gates[i];
+        if (x.kind != y.kind || x.param != y.param || x.theta != y.theta || x.k != y.k || x.nctrl != y.nctrl ||
+            x.G != y.G)
+            return false;
+        for (int j = 0; j < x.k; ++j)
+            if (x.locs[j] != y.locs[j]) return false;
+        for (int m = 0; m < x.nctrl; ++m)
+            if (x.ctrls[m] != y.ctrls[m] || x.cvals[m] != y.cvals[m]) return false;
+    }
+    return true;
+}
+
+bool same_observable(const yao_pauli_sum* a, const yao_pauli_sum* b)
+{
+    return a == b || (a->n == b->n && a->coef == b->coef && a->x == b->x && a->z == b->z);
+}
+
+// A circuit can share launches with others of its structure: both programs bound on the
+// device (each circuit binds its own records), every pass a tile pass, H psi by tile passes.
+bool z_capable(const Item& it)
+{
+    if (it.small || !it.bf || (it.nslots && !it.bb)) return false;
+    for (const HostPass& p : it.fwd->passes)
+        if (p.standalone >= 0) return false;
+    if (it.nslots)
+        for (const HostPass& p : it.bwd->passes)
+            if (p.standalone >= 0) return false;
+    return obs_passes_ok(it.h, it.s->n, 1, it.s->dtype);
+}
+
+// Scratch of one circuit of a z unit: psi in FP64, lambda, reverse and H psi partial sums.
+size_t z_item_bytes(const Item& it)
+{
+    const size_t N = size_t(1) << it.s->n;
+    return (16 + it.s->elem_bytes()) * N +
+           sizeof(double) * ((size_t)std::max(1, it.nslots) * it.W + hpsi_partial_doubles(it.h, it.s->n, 1, it.s->dtype));
+}
+constexpr size_t kZUnitBytes = size_t(2) << 30;  // scratch of one z unit at most
+constexpr int kZUnitMax = 1024;                   // circuits of one z unit at most
+
 int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit* const* circs,
                 const double* const* params, yao_pauli_sum* const* h)
 {
@@ -415,39 +479,115 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
     for (Item& it : C.items)
         if (!it.small) it.W = reverse_stride(it.s->n, it.s->dtype, it.tune.tq_b);
 
-    // By phase, then largest circuits first, each on the least loaded stream of its phase.
-    std::stable_sort(C.items.begin(), C.items.end(), [](const Item& a, const Item& b) {
-        return a.phase != b.phase ? a.phase < b.phase : a.cost > b.cost;
+    // Units: circuits of one structure with bound programs together (z units), every other
+    // circuit alone; the small circuits stay outside the units.
+    std::vector<std::vector<int>> members;
+    std::vector<bool> zunit;
+    {
+        std::map<std::pair<int, int>, std::vector<int>> open;  // (n, dtype) -> z units
+        for (int i = 0; i < (int)C.items.size(); ++i) {
+            const Item& it = C.items[i];
+            if (it.small) continue;
+            if (!z_capable(it)) {
+                members.push_back({i});
+                zunit.push_back(false);
+                continue;
+            }
+            std::vector<int>& cand = open[std::make_pair(it.s->n, it.s->dtype)];
+            int u = -1;
+            for (int v : cand) {
+                const Item& lead = C.items[members[v][0]];
+                if ((int)members[v].size() < kZUnitMax &&
+                    z_item_bytes(lead) * (members[v].size() + 1) <= kZUnitBytes && lead.W == it.W &&
+                    lead.nslots == it.nslots && same_gates(lead.c, it.c) && same_observable(lead.h, it.h)) {
+                    u = v;
+                    break;
+                }
+            }
+            if (u < 0) {
+                u = (int)members.size();
+                members.emplace_back();
+                zunit.push_back(true);
+                cand.push_back(u);
+            }
+            members[u].push_back(i);
+        }
+    }
+    // By phase, then largest units first, each on the least loaded stream of its phase; the
+    // items are reordered so that each unit's circuits follow each other (their energies and
+    // gradient sums then sit in consecutive output entries).
+    std::vector<int> order(members.size());
+    std::vector<double> ucost(members.size(), 0.0);
+    for (size_t u = 0; u < members.size(); ++u) {
+        order[u] = (int)u;
+        for (int i : members[u]) ucost[u] += C.items[i].cost;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int pa = C.items[members[a][0]].phase, pb = C.items[members[b][0]].phase;
+        return pa != pb ? pa < pb : ucost[a] > ucost[b];
     });
+    {
+        std::vector<Item> sorted;
+        sorted.reserve(C.items.size());
+        for (const Item& it : C.items)
+            if (it.small) sorted.push_back(it);
+        for (int u : order) {
+            Unit U;
+            U.first = (int)sorted.size();
+            U.count = (int)members[u].size();
+            U.z = zunit[u];
+            U.phase = C.items[members[u][0]].phase;
+            U.cost = ucost[u];
+            for (int i : members[u]) {
+                sorted.push_back(C.items[i]);
+                sorted.back().unit = (int)C.units.size();
+            }
+            C.units.push_back(U);
+        }
+        C.items.swap(sorted);
+    }
     double load[kBanks] = {};
     int cur_phase = -1;
     size_t psi_b[kBanks] = {}, lam_b[kBanks] = {}, gp_b[kBanks] = {}, hp_b[kBanks] = {};
-    size_t nout = 0, off = 0;
+    size_t nout = 0, off = 0, nzs = 0, nptr = 0;
     for (Item& it : C.items) {
-        if (it.small) {
-            it.out_e = nout++;
-            it.off_f = it.off_b = off;
-            continue;
-        }
-        if (it.phase != cur_phase) {
-            cur_phase = it.phase;
+        if (!it.small) continue;
+        it.out_e = nout++;
+        it.off_f = it.off_b = off;
+    }
+    for (Unit& U : C.units) {
+        if (U.phase != cur_phase) {
+            cur_phase = U.phase;
             for (double& l : load) l = 0;
         }
         int best = 0;
         for (int b = 1; b < kBanks; ++b)
             if (load[b] < load[best]) best = b;
-        it.bank = best;
-        load[best] += it.cost;
-        const size_t N = size_t(1) << it.s->n;
-        psi_b[best] = std::max(psi_b[best], 16 * N);
-        lam_b[best] = std::max(lam_b[best], it.s->elem_bytes() * N);
-        gp_b[best] = std::max(gp_b[best], sizeof(double) * (size_t)std::max(1, it.nslots) * it.W);
-        hp_b[best] = std::max(hp_b[best], sizeof(double) * hpsi_partial_doubles(it.h, it.s->n, 1, it.s->dtype));
-        it.out_e = nout++;
-        it.off_f = off;
-        off += it.bytes_f;
-        it.off_b = off;
-        off += it.bytes_b;
+        U.bank = best;
+        load[best] += U.cost;
+        const Item& lead = C.items[U.first];
+        const size_t N = size_t(1) << lead.s->n, nz = (size_t)U.count;
+        psi_b[best] = std::max(psi_b[best], nz * 16 * N);
+        lam_b[best] = std::max(lam_b[best], nz * lead.s->elem_bytes() * N);
+        gp_b[best] = std::max(gp_b[best], nz * sizeof(double) * (size_t)std::max(1, lead.nslots) * lead.W);
+        hp_b[best] = std::max(hp_b[best], nz * sizeof(double) * hpsi_partial_doubles(lead.h, lead.s->n, 1, lead.s->dtype));
+        if (U.z) {
+            U.zf = nzs;
+            U.zo = nzs + nz;
+            U.zb = nzs + 2 * nz;
+            nzs += 3 * nz;
+            U.sp = nptr;
+            nptr += nz;
+        }
+        for (int j = 0; j < U.count; ++j) {
+            Item& it = C.items[U.first + j];
+            it.bank = best;
+            it.out_e = nout++;
+            it.off_f = off;
+            off += it.bytes_f;
+            it.off_b = off;
+            off += it.bytes_b;
+        }
     }
     for (Item& it : C.items) {
         it.out_g = nout;
@@ -471,6 +611,32 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
         YAO_TRY(dev_alloc((void**)&C.hpart[b], hp_b[b]));
     }
     pack_all(C);
+    // Slot tables of the z units: each circuit's state, its slice of the unit's scratch (at
+    // the bank's buffers) and its bound records.
+    if (nzs) {
+        std::vector<ZSlot> zs(nzs);
+        std::vector<void*> ptrs(nptr);
+        for (const Unit& U : C.units) {
+            if (!U.z) continue;
+            const Item& lead = C.items[U.first];
+            const size_t N = size_t(1) << lead.s->n, es = lead.s->elem_bytes();
+            const size_t wo = hpsi_partial_doubles(lead.h, lead.s->n, 1, lead.s->dtype);
+            const size_t wg = (size_t)std::max(1, lead.nslots) * lead.W;
+            for (int j = 0; j < U.count; ++j) {
+                const Item& it = C.items[U.first + j];
+                void* lam = (char*)C.lam[U.bank] + (size_t)j * es * N;
+                ptrs[U.sp + j] = it.s->data;
+                zs[U.zf + j] = ZSlot{it.s->data, nullptr, it.bf->d.ops, nullptr};
+                zs[U.zo + j] = ZSlot{it.s->data, lam, nullptr, C.hpart[U.bank] + (size_t)j * wo};
+                zs[U.zb + j] = ZSlot{C.psi64[U.bank] + (size_t)j * 2 * N, lam, it.nslots ? it.bb->d.ops : nullptr,
+                                     C.gpart[U.bank] + (size_t)j * wg};
+            }
+        }
+        YAO_TRY(dev_alloc((void**)&C.d_zs, sizeof(ZSlot) * nzs));
+        YAO_TRY(dev_alloc((void**)&C.d_ptrs, sizeof(void*) * nptr));
+        YAO_HIP(hipMemcpy(C.d_zs, zs.data(), sizeof(ZSlot) * nzs, hipMemcpyHostToDevice));
+        YAO_HIP(hipMemcpy(C.d_ptrs, ptrs.data(), sizeof(void*) * nptr, hipMemcpyHostToDevice));
+    }
     // Descriptors and bind jobs of the small circuits, by qubit count.
     {
         std::vector<const Item*> sm;
@@ -509,6 +675,19 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
                 C.max_nb = std::max(C.max_nb, nb);
             }
         }
+        // The z units' circuits bind here too: one launch binds every such program.
+        for (const Unit& U : C.units) {
+            if (!U.z) continue;
+            for (int j = 0; j < U.count; ++j) {
+                const Item& it = C.items[U.first + j];
+                for (const BoundProgram* b : {it.bf, it.nslots ? it.bb : nullptr}) {
+                    const int nb = b ? (int)b->prog.binds.size() : 0;
+                    if (nb == 0) continue;
+                    jobs.push_back(BindJob{b->d.ops, b->dbinds, b->dfacs, C.d_params + it.poff, nb, 0});
+                    C.max_nb = std::max(C.max_nb, nb);
+                }
+            }
+        }
         if (!hs.empty()) {
             YAO_TRY(dev_alloc((void**)&C.d_small, sizeof(SmallCircuit) * hs.size()));
             YAO_HIP(hipMemcpy(C.d_small, hs.data(), sizeof(SmallCircuit) * hs.size(), hipMemcpyHostToDevice));
@@ -537,6 +716,54 @@ int build_cache(Cache& C, int ncirc, yao_state* const* states, const yao_circuit
     return 0;
 }
 
+// Restores single-circuit launches when a z unit's recording ends (also on errors).
+struct ZBatchScope {
+    ZBatchScope(const ZSlot* zs, int nz) { set_zbatch(zs, nz); }
+    ~ZBatchScope() { set_zbatch(nullptr, 0); }
+};
+
+// One z unit: every launch runs over the unit's nz circuits (grid z); the leader's plans and
+// programs give the shared part of each launch.
+int record_z_unit(Cache& C, const Unit& U)
+{
+    const Item& it = C.items[U.first];
+    const int n = it.s->n, dt = it.s->dtype, bk = U.bank, nz = U.count;
+    YAO_TRY(launch_fill_basis_z(C.d_ptrs + U.sp, nz, dt, n));
+    {
+        ZBatchScope z(C.d_zs + U.zf, nz);
+        YAO_TRY(launch_forward_passes(*it.fwd, fwd_prog(it), it.df, it.s->data, dt, n, 1, it.fc, nullptr));
+    }
+    {
+        ZBatchScope z(C.d_zs + U.zo, nz);
+        YAO_TRY(launch_hpsi_dev(it.s->data, dt, C.lam[bk], dt, n, 1, it.h, C.hpart[bk], C.d_out + it.out_e));
+    }
+    if (it.nslots == 0) return 0;
+    YAO_TRY(launch_convert_z(C.d_ptrs + U.sp, nz, dt, C.psi64[bk], n));
+    YAO_TRY(launch_fill(C.gpart[bk], (size_t)nz * it.nslots * it.W, 0.0));
+    {
+        ZBatchScope z(C.d_zs + U.zb, nz);
+        YAO_TRY(launch_backward_passes(*it.bwd, bwd_prog(it), it.db, it.c, nullptr, C.psi64[bk], C.lam[bk], dt, n, 1,
+                                       C.gpart[bk], it.W));
+    }
+    return launch_row_sums(C.gpart[bk], nz * it.nslots, it.W, C.d_out + it.out_g);
+}
+
+int record_item(Cache& C, Item& it)
+{
+    const int n = it.s->n, dt = it.s->dtype, bk = it.bank;
+    YAO_TRY(launch_fill_basis(it.s->data, dt, n, 1));
+    if (it.bf) YAO_TRY(bind_program(it.bf, C.d_params + it.poff));
+    YAO_TRY(launch_forward_passes(*it.fwd, fwd_prog(it), it.df, it.s->data, dt, n, 1, it.fc, nullptr));
+    YAO_TRY(launch_hpsi_dev(it.s->data, dt, C.lam[bk], dt, n, 1, it.h, C.hpart[bk], C.d_out + it.out_e));
+    if (it.nslots == 0) return 0;
+    YAO_TRY(launch_convert(it.s->data, dt, C.psi64[bk], YAO_C128, size_t(1) << n));
+    YAO_TRY(launch_fill(C.gpart[bk], (size_t)it.nslots * it.W, 0.0));
+    if (it.bb) YAO_TRY(bind_program(it.bb, C.d_params + it.poff));
+    YAO_TRY(launch_backward_passes(*it.bwd, bwd_prog(it), it.db, it.c, nullptr, C.psi64[bk], C.lam[bk], dt, n, 1,
+                                   C.gpart[bk], it.W));
+    return launch_row_sums(C.gpart[bk], it.nslots, it.W, C.d_out + it.out_g);
+}
+
 int record(Cache& C)
 {
     YAO_TRY(prepare_pass_kernels());
@@ -547,6 +774,10 @@ int record(Cache& C)
     set_recording(true);
     int rc = 0;
     do {
+        // One launch binds the programs of the small circuits and of the z units, before
+        // any stream starts.
+        set_stream(cs);
+        if ((rc = launch_bind_jobs(C.d_jobs, C.njobs, C.max_nb))) break;
         if (hipEventRecord(g_fork, cs) != hipSuccess) {
             rc = set_error(YAO_EHIP, "fork record");
             break;
@@ -554,19 +785,15 @@ int record(Cache& C)
         for (int b = 0; b < kBanks && !rc; ++b)
             if (hipStreamWaitEvent(g_bank[b], g_fork, 0) != hipSuccess) rc = set_error(YAO_EHIP, "fork wait");
         if (rc) break;
-        // The small circuits first, alone: one bind launch and one launch per qubit count.
-        set_stream(cs);
-        if ((rc = launch_bind_jobs(C.d_jobs, C.njobs, C.max_nb))) break;
+        // The small circuits: one launch per qubit count.
         for (const Cache::SmallLaunch& l : C.small_launches)
             if ((rc = launch_small_circuits(C.d_small + l.first, l.count, l.n))) break;
         if (rc) break;
         int phase = -1;
-        for (Item& it : C.items) {
-            if (it.small) continue;
-            const int n = it.s->n, dt = it.s->dtype, bk = it.bank;
-            if (it.phase != phase) {
+        for (const Unit& U : C.units) {
+            if (U.phase != phase) {
                 // Every stream finishes the previous phase before any starts this one.
-                phase = it.phase;
+                phase = U.phase;
                 for (int b = 0; b < kBanks && !rc; ++b)
                     if (hipEventRecord(g_join[b], g_bank[b]) != hipSuccess || hipStreamWaitEvent(cs, g_join[b], 0) != hipSuccess)
                         rc = set_error(YAO_EHIP, "phase join");
@@ -575,20 +802,10 @@ int record(Cache& C)
                     if (hipStreamWaitEvent(g_bank[b], g_fork, 0) != hipSuccess) rc = set_error(YAO_EHIP, "phase fork wait");
                 if (rc) break;
             }
-            set_stream(g_bank[bk]);
-            if ((rc = launch_fill_basis(it.s->data, dt, n, 1))) break;
-            if (it.bf && (rc = bind_program(it.bf, C.d_params + it.poff))) break;
-            if ((rc = launch_forward_passes(*it.fwd, fwd_prog(it), it.df, it.s->data, dt, n, 1, it.fc, nullptr))) break;
-            if ((rc = launch_hpsi_dev(it.s->data, dt, C.lam[bk], dt, n, 1, it.h, C.hpart[bk], C.d_out + it.out_e)))
-                break;
-            if (it.nslots == 0) continue;
-            if ((rc = launch_convert(it.s->data, dt, C.psi64[bk], YAO_C128, size_t(1) << n))) break;
-            if ((rc = launch_fill(C.gpart[bk], (size_t)it.nslots * it.W, 0.0))) break;
-            if (it.bb && (rc = bind_program(it.bb, C.d_params + it.poff))) break;
-            if ((rc = launch_backward_passes(*it.bwd, bwd_prog(it), it.db, it.c, nullptr, C.psi64[bk], C.lam[bk], dt, n, 1,
-                                             C.gpart[bk], it.W)))
-                break;
-            if ((rc = launch_row_sums(C.gpart[bk], it.nslots, it.W, C.d_out + it.out_g))) break;
+            set_stream(g_bank[U.bank]);
+            if (U.z) rc = record_z_unit(C, U);
+            else rc = record_item(C, C.items[U.first]);
+            if (rc) break;
         }
         if (rc) break;
         for (int b = 0; b < kBanks; ++b) {

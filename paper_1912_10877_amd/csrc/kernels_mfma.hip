@@ -75,16 +75,43 @@ __global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, Mf
     const int rows = 1 << a.m;
     const int E = rows * B;
     const int ncols = (rows >> K) * B;  // (group, slot) columns of a tile
-    // Workgroups loop over tiles, so the matrix fragments above are read once per workgroup.
-    for (uint64_t tix = blockIdx.x; tix < a.ntiles; tix += gridDim.x) {
+    // Workgroups loop over tiles, so the matrix fragments above are read once per workgroup;
+    // the next tile's amplitudes are loaded into registers while the current one is computed
+    // and stored (a tile holds at most 4096 amplitudes: 16 per thread).
+    constexpr int kPer = 4096 / 256;
+    float2 pre[kPer];
+    auto tile_base = [&](uint64_t tix) {
         uint64_t base = 0;
         for (int j = 0; j < a.nrest; ++j) base |= ((tix >> j) & 1) << a.rpos[j];
+        return base;
+    };
+    auto gload = [&](uint64_t base) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            if (e < E) {
+                const int row = B == 1 ? e : e / B, b = e - row * B;
+                pre[i] = psi[(base | t->in_lo[row & 63] | t->in_hi[row >> 6]) * B + b];
+            }
+        }
+    };
+    if (blockIdx.x < a.ntiles) {
+        __syncthreads();  // the tables are in LDS
+        gload(tile_base(blockIdx.x));
+    }
+    for (uint64_t tix = blockIdx.x; tix < a.ntiles; tix += gridDim.x) {
+        const uint64_t base = tile_base(tix);
         __syncthreads();
-        for (int e = threadIdx.x; e < E; e += 256) {
-            const int row = B == 1 ? e : e / B, b = e - row * B;
-            tile[swz5(row) * B + b] = psi[(base | t->in_lo[row & 63] | t->in_hi[row >> 6]) * B + b];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            if (e < E) {
+                const int row = B == 1 ? e : e / B, b = e - row * B;
+                tile[swz5(row) * B + b] = pre[i];
+            }
         }
         __syncthreads();
+        if (tix + gridDim.x < a.ntiles) gload(tile_base(tix + gridDim.x));
         for (int c0 = wave * 32; c0 < ncols; c0 += 4 * 32) {
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
@@ -131,8 +158,9 @@ __global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, Mf
 
 bool mfma_supported(int k, int n, int B)
 {
-    // A tile holds at least the 2^k members x B slots of a group (<= 64 KiB of LDS).
-    return (k == 4 || k == 5) && n >= k && n - kMfmaTileBits < 31 && ((size_t)B << k) <= 8192;
+    // A tile holds at least the 2^k members x B slots of a group, at most 4096 amplitudes
+    // (32 KiB of LDS, 16 per thread in the prefetch registers).
+    return (k == 4 || k == 5) && n >= k && n - kMfmaTileBits < 31 && ((size_t)B << k) <= 4096;
 }
 
 // Real form [[Ur, -Ui], [Ui, Ur]] of U in FP32, row-major 2D x 2D: the operand the kernel reads.
@@ -208,6 +236,7 @@ int launch_dense_mfma(float2* psi, int n, int B, const HostMat& U, const int* lo
             if (j + 6 < nc) tab.col_hi[h] |= 1u << crow[j + 6];
         }
     a.ntiles = uint64_t(1) << a.nrest;
+    if (((size_t)B << a.m) > 4096) return set_error(YAO_EINVAL, "matrix-core tile of %zu amplitudes", (size_t)B << a.m);
     // About eight workgroups per CU, each looping over tiles.
     const uint64_t blocks = std::min<uint64_t>(a.ntiles, 2048);
     const size_t lds = sizeof(MfmaTables) + ((size_t)B << a.m) * 8;

@@ -181,6 +181,35 @@ def test_changed_circuit_is_recorded_anew():
     check(e, g, params, refs, 1)
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_same_structure_circuits_share_launches(dtype):
+    """Circuits of one structure (same gates, same observable, same state shape) run every
+    launch together over all of them, each with its own angles, state and scratch slice: five
+    13-qubit and three 14-qubit ansatz circuits, beside a 13-qubit one under another observable
+    and one with an extra gate (units of their own). Energies, gradients and output states
+    against the oracle, then a replay with new angles."""
+    base13, base14 = w.hea_circuit(13, 2), w.hea_circuit(14, 1)
+    extra = w.Circuit(13, list(base13.gates) + [w.Gate("Ry", (5,), param=3)], base13.nparams)
+    cases = [(base13, w.heisenberg(13))] * 5 + [(base14, w.heisenberg(14))] * 3
+    cases += [(base13, random_pauli_sum(13, 7, 7100)), (extra, w.heisenberg(13))]
+    states, circs, hams, params, refs = [], [], [], [], []
+    for i, (c, H) in enumerate(cases):
+        states.append(yb.State(c.n, 1, dtype))
+        circs.append(yb.Circuit.from_workload(c))
+        hams.append(yb.PauliSum.from_workload(H))
+        params.append(w.angles(7200 + i, c.nparams))
+        refs.append((c, H))
+    for rep in range(2):
+        if rep:
+            params = [w.angles(7300 + i, len(p)) for i, p in enumerate(params)]
+        e, g = yb.batch_run(states, circs, params, hams)
+        check(e, g, params, refs, dtype)
+        for i in (0, 4, 5, 7, 9):
+            c = refs[i][0]
+            ref = oracle.forward(c, params[i], w.zero_state(c.n))
+            assert np.abs(states[i].download() - ref).max() <= (1e-5 if dtype == 0 else 1e-11), i
+
+
 def test_circuit_without_parameters_and_observable_only():
     c = w.ghz_circuit(7)
     H = w.heisenberg(7)
