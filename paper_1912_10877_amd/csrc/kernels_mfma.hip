@@ -52,7 +52,9 @@ __device__ __forceinline__ int swz5(int r)
 
 // Lane layout of v_mfma_f32_16x16x4f32 (one block): A[i][k] from lane i + 16 k, B[k][j]
 // from lane j + 16 k, D[4 (l / 16) + v][l % 16] in accumulator register v of lane l.
-template <int K>
+// FULL: the tile holds exactly 4096 amplitudes, so every load and store loop has a fixed trip
+// count and the wait for the next tile's registers need not include the stores issued after them.
+template <int K, bool FULL>
 __global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, MfmaArgs a, const float* __restrict__ M)
 {
     constexpr int D = 1 << K, RD = 2 * D, RT = RD / 16, KC = RD / 4, NA = D / 4;
@@ -73,8 +75,8 @@ __global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, Mf
         for (int kc = 0; kc < KC; ++kc) am[rt][kc] = M[(16 * rt + cl) * RD + 4 * kc + q];
     const int B = a.B;
     const int rows = 1 << a.m;
-    const int E = rows * B;
-    const int ncols = (rows >> K) * B;  // (group, slot) columns of a tile
+    const int E = FULL ? 4096 : rows * B;
+    const int ncols = E >> K;  // (group, slot) columns of a tile
     // Workgroups loop over tiles, so the matrix fragments above are read once per workgroup;
     // the next tile's amplitudes are loaded into registers while the current one is computed
     // and stored (a tile holds at most 4096 amplitudes: 16 per thread).
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, Mf
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int e = threadIdx.x + 256 * i;
-            if (e < E) {
+            if (FULL || e < E) {
                 const int row = B == 1 ? e : e / B, b = e - row * B;
                 pre[i] = psi[(base | t->in_lo[row & 63] | t->in_hi[row >> 6]) * B + b];
             }
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, Mf
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int e = threadIdx.x + 256 * i;
-            if (e < E) {
+            if (FULL || e < E) {
                 const int row = B == 1 ? e : e / B, b = e - row * B;
                 tile[swz5(row) * B + b] = pre[i];
             }
@@ -147,10 +149,108 @@ __global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, Mf
             }
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < E; e += 256) {
-            const int row = B == 1 ? e : e / B, b = e - row * B;
-            psi[(base | t->in_lo[row & 63] | t->in_hi[row >> 6]) * B + b] = tile[swz5(row) * B + b];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            if (FULL || e < E) {
+                const int row = B == 1 ? e : e / B, b = e - row * B;
+                psi[(base | t->in_lo[row & 63] | t->in_hi[row >> 6]) * B + b] = tile[swz5(row) * B + b];
+            }
         }
+    }
+}
+
+// Single-slot states with full tiles (B = 1, 2^12 rows): element e = threadIdx.x + 256 i of a
+// tile is row e, so its address is base | in_lo[lane] | in_hi[wave + 4 i], a per-lane part fixed
+// for the whole launch and a wave-uniform one. Two LDS tiles alternate: while the waves multiply
+// one, the next tile's amplitudes (loaded into registers during the previous multiply) are
+// written into the other and the finished one is stored, so each wait for loads covers only
+// loads and stores issued a whole multiply earlier.
+template <int K>
+__global__ __launch_bounds__(256) void k_dense_mfma_b1(float2* __restrict__ psi, MfmaArgs a, const float* __restrict__ M)
+{
+    constexpr int D = 1 << K, RD = 2 * D, RT = RD / 16, KC = RD / 4, NA = D / 4;
+    constexpr int NBLK = (4096 >> K) / 64;  // 16-column blocks per wave
+    constexpr int kPer = 16;                // amplitudes per thread and tile
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float2* buf = reinterpret_cast<float2*>(lds_raw);  // two tiles of 4096 amplitudes
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int q = lane >> 4, cl = lane & 15;
+    float am[RT][KC];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) am[rt][kc] = M[(16 * rt + cl) * RD + 4 * kc + q];
+    const uint64_t lo = a.tab.in_lo[lane];
+    // Group columns of this lane (block wave + 4 j): first row, and the row bits that decide
+    // its controls; member offsets split into a per-lane part and a uniform part (the member
+    // table is linear in the member index bits).
+    int r0[NBLK];
+    uint64_t tctl[NBLK];
+#pragma unroll
+    for (int j = 0; j < NBLK; ++j) {
+        const int col = 16 * (wave + 4 * j) + cl;
+        r0[j] = (int)(a.tab.col_lo[col & 63] | a.tab.col_hi[col >> 6]);
+        tctl[j] = (a.tab.in_lo[r0[j] & 63] | a.tab.in_hi[r0[j] >> 6]) & a.cmask;
+    }
+    const int memq = (int)a.tab.mem[q], memq4 = (int)a.tab.mem[4 * q];
+    auto tile_base = [&](uint64_t tix) {
+        uint64_t base = 0;
+        for (int j = 0; j < a.nrest; ++j) base |= ((tix >> j) & 1) << a.rpos[j];
+        return base;
+    };
+    float2 pre[kPer];
+    auto gload = [&](uint64_t base) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) pre[i] = psi[base | lo | a.tab.in_hi[wave + 4 * i]];
+    };
+    auto lput = [&](float2* t) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) t[swz5(threadIdx.x + 256 * i)] = pre[i];
+    };
+    const uint64_t G = gridDim.x;
+    uint64_t tix = blockIdx.x;
+    gload(tile_base(tix));
+    lput(buf);
+    if (tix + G < a.ntiles) gload(tile_base(tix + G));
+    __syncthreads();
+    int cur = 0;
+    for (; tix < a.ntiles; tix += G) {
+        const uint64_t base = tile_base(tix);
+        float2* t = buf + cur * 4096;
+#pragma unroll
+        for (int j = 0; j < NBLK; ++j) {
+            const bool on = ((base & a.cmask) | tctl[j]) == a.cval;
+            float2 amp[NA];
+#pragma unroll
+            for (int m = 0; m < NA; ++m) amp[m] = t[swz5(r0[j] | memq | (int)a.tab.mem[4 * m])];
+            v4f acc[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) acc[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const int m = kc % NA;
+                const float bv = (kc / NA) == 0 ? amp[m].x : amp[m].y;
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[rt][kc], bv, acc[rt], 0, 0, 0);
+            }
+            if (on) {
+#pragma unroll
+                for (int rt = 0; rt < RT / 2; ++rt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        t[swz5(r0[j] | memq4 | (int)a.tab.mem[16 * rt + v])] = make_float2(acc[rt][v], acc[rt + RT / 2][v]);
+            }
+        }
+        __syncthreads();
+        const uint64_t nx = tix + G;
+        if (nx < a.ntiles) lput(buf + (cur ^ 1) * 4096);
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) psi[base | lo | a.tab.in_hi[wave + 4 * i]] = t[swz5(threadIdx.x + 256 * i)];
+        if (nx + G < a.ntiles) gload(tile_base(nx + G));
+        __syncthreads();
+        cur ^= 1;
     }
 }
 
@@ -242,8 +342,21 @@ int launch_dense_mfma(float2* psi, int n, int B, const HostMat& U, const int* lo
     const size_t lds = sizeof(MfmaTables) + ((size_t)B << a.m) * 8;
     const double elems = (double)(uint64_t(1) << n) * B;
     const int pi = prof_begin(YAO_KF_MFMA);
-    if (k == 4) k_dense_mfma<4><<<(unsigned)blocks, 256, lds, stream()>>>(psi, a, dm);
-    else k_dense_mfma<5><<<(unsigned)blocks, 256, lds, stream()>>>(psi, a, dm);
+    const bool full = ((size_t)B << a.m) == 4096;
+    if (B == 1 && full) {
+        // Two tiles of 32 KiB; two workgroups per CU.
+        const size_t lds2 = 2 * 4096 * sizeof(float2);
+        if (k == 4) {
+            YAO_HIP(hipFuncSetAttribute((const void*)k_dense_mfma_b1<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+            k_dense_mfma_b1<4><<<(unsigned)blocks, 256, lds2, stream()>>>(psi, a, dm);
+        } else {
+            YAO_HIP(hipFuncSetAttribute((const void*)k_dense_mfma_b1<5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+            k_dense_mfma_b1<5><<<(unsigned)blocks, 256, lds2, stream()>>>(psi, a, dm);
+        }
+    } else if (k == 4 && full) k_dense_mfma<4, true><<<(unsigned)blocks, 256, lds, stream()>>>(psi, a, dm);
+    else if (k == 4) k_dense_mfma<4, false><<<(unsigned)blocks, 256, lds, stream()>>>(psi, a, dm);
+    else if (full) k_dense_mfma<5, true><<<(unsigned)blocks, 256, lds, stream()>>>(psi, a, dm);
+    else k_dense_mfma<5, false><<<(unsigned)blocks, 256, lds, stream()>>>(psi, a, dm);
     // Algorithmic work: one read and one write of every element; 8 D real flops per element
     // (for the elements whose controls pass).
     const double on = elems / double(uint64_t(1) << __builtin_popcountll(c.mask));

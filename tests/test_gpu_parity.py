@@ -82,7 +82,8 @@ def test_dense_k_qubit_gate(dtype, k):
 
 
 @pytest.mark.parametrize("n,B,k,nctrl,seed", [(5, 1, 5, 0, 1), (6, 3, 4, 1, 2), (12, 1, 5, 2, 3), (14, 2, 4, 0, 4),
-                                              (10, 64, 5, 1, 5), (13, 100, 4, 2, 6), (16, 1, 5, 1, 7)])
+                                              (10, 64, 5, 1, 5), (13, 100, 4, 2, 6), (16, 1, 5, 1, 7),
+                                              (13, 1, 4, 1, 8), (15, 1, 4, 0, 9), (14, 1, 5, 3, 10)])
 def test_dense_blocks_on_matrix_cores(n, B, k, nctrl, seed):
     """4- and 5-qubit matrices on complex64 states (the FP32 matrix-core kernel, tiles staged in
     LDS): targets on low and high bits, controls of either value, batches up to 100 slots."""
