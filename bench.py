@@ -77,6 +77,9 @@ def parse():
     p.add_argument("--batch-steps", type=int, default=5)
     p.add_argument("--fuse-width", type=int, default=-1,
                    help="forward fusion width 0..5 with the autotuner off (-1: autotuned)")
+    p.add_argument("--jit", type=int, default=-1,
+                   help="run-time compiled passes after this many uses of a bound program (0: off; -1: the "
+                        "library default)")
     return p.parse_args()
 
 
@@ -462,6 +465,8 @@ def main():
     yb.use_torch_stream()
     if args.fuse_width >= 0:
         yb.set_options(autotune=0, fuse_width=args.fuse_width)
+    if args.jit >= 0:
+        yb.set_options(jit=args.jit)
     n, depth, B = args.qubits, args.depth, args.batch
     dtype = yb.C64 if args.dtype == "c64" else yb.C128
     mode = {"reversible": yb.GRAD_REVERSIBLE, "checkpoint": yb.GRAD_CHECKPOINT, "auto": yb.GRAD_AUTO}[args.mode]
@@ -576,7 +581,8 @@ def main():
                                f"{circ_w.nparams} params, periodic Heisenberg energy + all gradients, "
                                f"{args.mode} adjoint", "qubits": n, "depth": depth, "batch": B,
                    "params": circ_w.nparams, "gates": ngates, "grad_mode": args.mode,
-                   "forward_fusion": "autotuned" if args.fuse_width < 0 else args.fuse_width},
+                   "forward_fusion": "autotuned" if args.fuse_width < 0 else args.fuse_width,
+                   "jit": yb.get_options().jit},
         "energy": float(e[0]), "drift": drift,
         "plain_ms_per_step": plain_ms,
         "speedup_vs_plain": (plain_ms / ms_step) if plain_ms else None,

@@ -98,7 +98,16 @@ enum yao_grad_mode { YAO_GRAD_REVERSIBLE = 0, YAO_GRAD_CHECKPOINT = 1, YAO_GRAD_
  *                    on the device the first time it meets them; the state is restored after
  *                    the trials. Which candidate wins depends on timings, so results may
  *                    differ in the last bits between processes. 0: fuse_width and
- *                    tile_qubits are taken as given. */
+ *                    tile_qubits are taken as given.
+ *   jit              0: off. N >= 1 (default 3): when a device-bound program (a circuit
+ *                    whose matrices are bound from the parameters on the device) runs its
+ *                    N-th forward sweep on a single-slot state, its passes are compiled at run
+ *                    time (hipRTC) into straight-line kernels that read the same op records,
+ *                    so later parameter changes need no recompile. Passes outside the
+ *                    compiled form (batched states, LDS-applied ops, dense blocks, tiles over
+ *                    64 KiB), autotuner trials and graph recording keep the generic kernels; a
+ *                    failed compile leaves the program on them. Compiling takes ~0.4 s per
+ *                    pass family of ~70 ops, once per program. */
 typedef struct {
     int plain;
     int tile_qubits;
@@ -107,6 +116,7 @@ typedef struct {
     double drift_tol;
     int mfma;
     int autotune;
+    int jit;
 } yao_options;
 
 /* Library ------------------------------------------------------------------------------ */
@@ -325,6 +335,16 @@ int yao_profile_read(int family, int* launches, double* total_ms, double* algo_b
  * At most 20 qubits; no GPU is used. */
 int yao_plan_selfcheck(const yao_circuit* c, const double* params, enum yao_dtype dt, int reverse, int tile_qubits,
                        double* max_err, int* npasses);
+/* Generates the run-time compiled forward passes (see yao_options.jit) of circuit c, held as a
+ * device-bound program of a single-slot state of dtype dt over tiles of tile_qubits qubits (0:
+ * default), and compiles them for gfx950 with hipRTC, without loading them (no GPU is used).
+ * *npasses receives the plan's pass count and *njit how many of them compile to straight-line
+ * kernels. Errors: YAO_EINVAL when c cannot be bound on the device or is too small for tile
+ * passes; YAO_EHIP with the compiler log when the generated source does not compile. */
+int yao_jit_selfcheck(const yao_circuit* c, enum yao_dtype dt, int tile_qubits, int* npasses, int* njit);
+/* Counters of the run-time compiled passes since the library was loaded: programs compiled,
+ * passes compiled, and launches of compiled passes. Any argument may be NULL. */
+int yao_jit_stats(long long* programs, long long* passes, long long* launches);
 
 #ifdef __cplusplus
 }

@@ -31,7 +31,7 @@ class YaoError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("plain", ctypes.c_int), ("tile_qubits", ctypes.c_int), ("fuse_width", ctypes.c_int),
                 ("checkpoint_every", ctypes.c_int), ("drift_tol", ctypes.c_double), ("mfma", ctypes.c_int),
-                ("autotune", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("jit", ctypes.c_int)]
 
 
 _lib = None
@@ -81,6 +81,8 @@ _SIGS = {
     "yao_profile_enable": [I],
     "yao_profile_read": [I, P, P, P, P],
     "yao_plan_selfcheck": [P, P, I, I, I, P, P],
+    "yao_jit_selfcheck": [P, I, I, P, P],
+    "yao_jit_stats": [P, P, P],
 }
 
 
@@ -428,3 +430,18 @@ def plan_selfcheck(circ: Circuit, params, dtype=0, reverse=False, tile_qubits=0)
     _check(lib().yao_plan_selfcheck(circ.h, _ptr(p), int(dtype), int(bool(reverse)), int(tile_qubits),
                                     ctypes.byref(err), ctypes.byref(npass)))
     return err.value, npass.value
+
+
+def jit_selfcheck(circ: Circuit, dtype=0, tile_qubits=0):
+    """Generate and compile (hipRTC, host only) the run-time forward passes of the circuit as
+    a device-bound program: returns (number of passes, number compiled to straight-line code)."""
+    npass, njit = ctypes.c_int(), ctypes.c_int()
+    _check(lib().yao_jit_selfcheck(circ.h, int(dtype), int(tile_qubits), ctypes.byref(npass), ctypes.byref(njit)))
+    return npass.value, njit.value
+
+
+def jit_stats():
+    """(programs compiled, passes compiled, launches of compiled passes) since the library loaded."""
+    a, b, c = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+    _check(lib().yao_jit_stats(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value

@@ -731,7 +731,7 @@ int record_z_unit(Cache& C, const Unit& U)
     YAO_TRY(launch_fill_basis_z(C.d_ptrs + U.sp, nz, dt, n));
     {
         ZBatchScope z(C.d_zs + U.zf, nz);
-        YAO_TRY(launch_forward_passes(*it.fwd, fwd_prog(it), it.df, it.s->data, dt, n, 1, it.fc, nullptr));
+        YAO_TRY(launch_forward_passes(*it.fwd, fwd_prog(it), it.df, it.s->data, dt, n, 1, it.fc, nullptr, it.bf));
     }
     {
         ZBatchScope z(C.d_zs + U.zo, nz);
@@ -753,7 +753,7 @@ int record_item(Cache& C, Item& it)
     const int n = it.s->n, dt = it.s->dtype, bk = it.bank;
     YAO_TRY(launch_fill_basis(it.s->data, dt, n, 1));
     if (it.bf) YAO_TRY(bind_program(it.bf, C.d_params + it.poff));
-    YAO_TRY(launch_forward_passes(*it.fwd, fwd_prog(it), it.df, it.s->data, dt, n, 1, it.fc, nullptr));
+    YAO_TRY(launch_forward_passes(*it.fwd, fwd_prog(it), it.df, it.s->data, dt, n, 1, it.fc, nullptr, it.bf));
     YAO_TRY(launch_hpsi_dev(it.s->data, dt, C.lam[bk], dt, n, 1, it.h, C.hpart[bk], C.d_out + it.out_e));
     if (it.nslots == 0) return 0;
     YAO_TRY(launch_convert(it.s->data, dt, C.psi64[bk], YAO_C128, size_t(1) << n));

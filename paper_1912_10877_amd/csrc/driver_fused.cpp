@@ -445,11 +445,18 @@ static void layout_qubits(const HostPass& pass, const GateRec& g, int* locs, int
 }
 
 int launch_forward_passes(const Plan& P, const Program& prog, const DevProgram& d, void* data, int dtype, int n, int B,
-                          const yao_circuit* c, const double* params)
+                          const yao_circuit* c, const double* params, const BoundProgram* bp)
 {
     if (!P.valid) return set_error(YAO_EINVAL, "pass plan could not restore the qubit layout");
+    const JitPasses* J = bp && &bp->prog == &prog ? jit_passes(bp, P, false, dtype, n, B) : nullptr;
     for (size_t p = 0; p < P.passes.size(); ++p) {
         const HostPass& pass = P.passes[p];
+        if (jit_has(J, (int)p)) {
+            const double N = (double)(uint64_t(1) << n) * B;
+            YAO_TRY(jit_launch_forward(J, (int)p, data, d.ops, prog.pass_op0[p], 2.0 * N * (dtype == YAO_C64 ? 8 : 16),
+                                       prog.pass_flops[p] * N));
+            continue;
+        }
         if (pass.standalone >= 0) {
             // The matrix is read from the program; the launch takes only its size from U.
             const GateRec& g = c->gates[P.ops[pass.standalone].gate];
@@ -507,6 +514,7 @@ static std::mutex g_bound_mu;
 
 static void free_bound(BoundProgram* b)
 {
+    jit_free(b->jit);
     if (b->dev) (void)hipFree(b->dev);
     if (b->dbinds) (void)hipFree(b->dbinds);
     if (b->dfacs) (void)hipFree(b->dfacs);
@@ -632,7 +640,7 @@ int forward_fused_range(void* data, int dtype, int n, int B, const yao_circuit* 
     const double* dp = c->nparams > 0 ? upload_params(params, c->nparams) : nullptr;
     if (c->nparams > 0 && !dp) return YAO_ENOMEM;
     YAO_TRY(bind_program(bp, dp));
-    return launch_forward_passes(P, bp->prog, bp->d, data, dtype, n, B, c, params);
+    return launch_forward_passes(P, bp->prog, bp->d, data, dtype, n, B, c, params, bp);
 }
 
 int forward_fused(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params)
@@ -658,7 +666,7 @@ int forward_sweep(void* data, int dtype, int n, int B, const yao_circuit* c, con
                 if (!dparams) return YAO_ENOMEM;
             }
             YAO_TRY(bind_program(bp, dparams));
-            return launch_forward_passes(P, bp->prog, bp->d, data, dtype, n, B, sc, nullptr);
+            return launch_forward_passes(P, bp->prog, bp->d, data, dtype, n, B, sc, nullptr, bp);
         }
     }
     // Host-built program for these parameters (dense fused blocks, or gates the device cannot bind).

@@ -198,6 +198,7 @@ struct ZSlot {
 // is shared. launch_hpsi_dev then also sums the energies of all nz circuits (partials nz * B
 // rows apart by the observable's partial size, energies to consecutive entries).
 void set_zbatch(const ZSlot* zs, int nz);
+const ZSlot* zbatch_slots();
 int zbatch_count();
 // lam_bytes: bytes per element of the adjoint state (reverse plans size their register groups'
 // gradient buffers by it).
@@ -217,9 +218,11 @@ int launch_bind(POp* ops, const BindRec* binds, int nbinds, const BindFac* facs,
 size_t program_blob_bytes(const Program& prog);
 void pack_program(const Program& prog, char* host, char* dev, DevProgram& d);
 // Launch the passes of a plan whose program is already in device memory (no host sync, no
-// copies: capturable in a graph).
+// copies: capturable in a graph). bp: the bound program prog belongs to, whose run-time
+// compiled passes (if any) are used.
+struct BoundProgram;
 int launch_forward_passes(const Plan& P, const Program& prog, const DevProgram& d, void* data, int dtype, int n, int B,
-                          const yao_circuit* c, const double* params);
+                          const yao_circuit* c, const double* params, const BoundProgram* bp = nullptr);
 int launch_backward_passes(const Plan& P, const Program& prog, const DevProgram& d, const yao_circuit* c,
                            const double* params, double* psi, void* lam, int lam_dtype, int n, int B, double* gpartial,
                            int W);
@@ -264,6 +267,7 @@ int launch_bind_jobs(const BindJob* jobs, int njobs, int max_nb);
 int launch_small_circuits(const SmallCircuit* items, int count, int n);
 constexpr int kSmallMaxQubits = 12;  // psi and lambda in FP64: 32 B x 2^12 = 128 KiB of LDS
 
+struct JitPasses;
 struct BoundProgram {
     const yao_circuit* circ = nullptr;
     Program prog;
@@ -272,7 +276,26 @@ struct BoundProgram {
     BindRec* dbinds = nullptr;
     BindFac* dfacs = nullptr;
     bool ok = false;  // false: the program needs the host for some matrix
+    // Run-time compiled passes (jit.cpp): uses so far, the module once compiled, and whether
+    // compiling failed (then the generic kernels for good).
+    mutable int uses = 0;
+    mutable JitPasses* jit = nullptr;
+    mutable bool jit_failed = false;
 };
+// The run-time compiled passes of a bound program (compiled on its options().jit-th use),
+// or nullptr. jit_has: pass p has a compiled kernel. jit_launch_forward runs it on psi with
+// the program's records (op_first: the pass's first record), over the current z batch.
+const JitPasses* jit_passes(const BoundProgram* bp, const Plan& P, bool bwd, int dtype, int n, int B);
+bool jit_has(const JitPasses* J, int p);
+int jit_launch_forward(const JitPasses* J, int p, void* psi, const POp* ops, int op_first, double bytes,
+                       double flops);
+void jit_free(JitPasses* J);
+void jit_stats(long long* programs, long long* passes, long long* launches);
+// Host only: generate and compile (no module load) the run-time forward passes of circuit c
+// as a bound program; *njit of *npasses passes are compiled.
+int jit_selfcheck(const yao_circuit* c, int dtype, int tile_qubits, int* npasses, int* njit);
+// Nested: while any suspension is active nothing is compiled (autotuner trials).
+void jit_suspend(bool on);
 const BoundProgram* bound_program(const Plan& P, const yao_circuit* c, bool bwd, int dtype,
                                   const std::vector<FusedPart>* parts, const yao_circuit* orig);
 const double* upload_params(const double* params, int nparams);

@@ -1,0 +1,412 @@
+// Run-time compiled pass kernels (hipRTC). The generic pass kernels read every op record at run
+// time and dispatch on its variant: per op, scalar loads, a compare tree, loop control and, at
+// the merge of the variants, register copies. With one wave per SIMD (a 20-qubit state gives
+// each CU one 2^12 tile) that scalar work is not hidden behind another wave's vector work. A
+// device-bound program's structure (which ops, on which register bits, under which controls)
+// is fixed; only its matrices change with the parameters, and they stay in the op records that
+// k_bind rewrites. So each pass of such a program can be emitted as straight-line code: the
+// tile mapping and the register-group layouts become constants, a SWAP on register bits whose
+// controls are register bits is a renaming of registers at compile time (no instructions),
+// and the matrix entries are read from the records at constant offsets.
+//
+// Supported: single-slot states (B = 1), passes whose groups are all register groups (no
+// LDS-applied k = 2, 3 ops and no dense blocks), LDS tiles of at most 64 KiB. Any other pass
+// of the program runs the generic kernel. A compile failure switches the program back to the
+// generic kernels for good.
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstddef>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "fused.h"
+
+namespace yao {
+
+namespace {
+
+std::string I(long long v)
+{
+    return std::to_string(v);
+}
+std::string U(unsigned long long v)
+{
+    return std::to_string(v) + "ull";
+}
+
+// Bank swizzle of LDS tile rows, the generic kernels' layout (linear over GF(2): the swizzle
+// of a ^ b is the XOR of the swizzles).
+uint32_t swz_host(uint32_t e)
+{
+    return e ^ (((e >> 4) ^ (e >> 8)) & 15u);
+}
+
+const char* kPrelude = R"YAO(
+typedef unsigned long long u64;
+__device__ __forceinline__ unsigned swz(unsigned e) { return e ^ (((e >> 4) ^ (e >> 8)) & 15u); }
+)YAO";
+
+// Code of one forward pass, or an empty string when the pass is not supported.
+std::string gen_forward_pass(const Plan& P, const Program& prog, int p, int n, int dtype, const std::string& name,
+                             int* nthr_out, size_t* lds_out)
+{
+    const HostPass& pass = P.passes[p];
+    const int RB = P.reg_bits, N = 1 << RB, t = P.t;
+    if (P.c != 0 || pass.standalone >= 0 || prog.pass_dmat_words[p] != 0) return "";
+    if (t - RB < 0 || t - RB > 9 || (int)pass.tile_qubits.size() != t) return "";
+    const int g0 = prog.pass_group0[p], ng = (int)pass.groups.size();
+    for (int g = 0; g < ng; ++g)
+        if (prog.groups[g0 + g].lds) return "";
+    const bool c64 = dtype == YAO_C64;
+    const size_t lds = (size_t)(c64 ? 8 : 16) << t;
+    if (lds > 65536) return "";
+    const int nthr = 1 << (t - RB);
+    const std::string V = c64 ? "float2" : "double2", R = c64 ? "float" : "double";
+    const std::string MK = c64 ? "make_float2" : "make_double2";
+    std::ostringstream o;
+    o << "extern \"C\" __global__ void __launch_bounds__(" << nthr << ") " << name
+      << "(void* psi_, const char* ops_, const char* zs_, int op_first) {\n";
+    o << "  extern __shared__ __align__(16) " << V << " lp[];\n";
+    o << "  const unsigned th = threadIdx.x;\n";
+    o << "  " << V << "* gp = (" << V << "*)psi_;\n  const char* ops = ops_;\n";
+    o << "  if (zs_) { const char* z = zs_ + 32 * blockIdx.z; gp = *(" << V
+      << "* const*)z; ops = *(const char* const*)(z + 16) + (u64)op_first * " << sizeof(POp) << "; }\n";
+    // Tile base: the tile index bits on the qubits outside the tile, ascending.
+    uint64_t T = 0;
+    for (int q : pass.tile_qubits) T |= uint64_t(1) << q;
+    o << "  const u64 tid = blockIdx.x;\n  u64 base = 0;\n";
+    {
+        int j = 0;
+        for (int q = 0; q < n; ++q) {
+            if ((T >> q) & 1) continue;
+            o << "  base |= ((tid >> " << j << ") & 1ull) << " << q << ";\n";
+            ++j;
+        }
+    }
+    // Load mapping: element e = th + r * nthr; bits of th on tile qubits 0 .. t-RB-1, bits of r
+    // on the next RB tile qubits.
+    o << "  u64 toff = base;\n";
+    for (int j = 0; j < t - RB; ++j) o << "  toff |= (u64)((th >> " << j << ") & 1u) << " << pass.tile_qubits[j] << ";\n";
+    std::vector<uint64_t> rofs(N);
+    for (int r = 0; r < N; ++r) {
+        uint64_t d = 0;
+        for (int b = 0; b < RB; ++b)
+            if ((r >> b) & 1) d |= uint64_t(1) << pass.tile_qubits[t - RB + b];
+        rofs[r] = d;
+    }
+    o << "  {\n";
+    for (int r = 0; r < N; ++r) o << "    const " << V << " v" << r << " = gp[toff | " << U(rofs[r]) << "];\n";
+    for (int r = 0; r < N; ++r) o << "    lp[swz(th + " << r * nthr << "u)] = v" << r << ";\n";
+    o << "  }\n  __syncthreads();\n";
+    // Register groups.
+    const int op_base = 0;  // records are addressed relative to the pass's first record
+    for (int g = 0; g < ng; ++g) {
+        const PGroupDesc& G = prog.groups[g0 + g];
+        uint32_t rmask = 0;
+        for (int j = 0; j < RB; ++j) rmask |= 1u << G.rpos[j];
+        std::vector<uint32_t> er(N);
+        for (int r = 0; r < N; ++r) {
+            uint32_t e = 0;
+            for (int j = 0; j < RB; ++j)
+                if ((r >> j) & 1) e |= 1u << G.rpos[j];
+            er[r] = e;
+        }
+        o << "  {\n    unsigned ethr = 0;\n";
+        {
+            int k = 0;
+            for (int b = 0; b < t; ++b) {
+                if ((rmask >> b) & 1) continue;
+                o << "    ethr |= ((th >> " << k << ") & 1u) << " << b << ";\n";
+                ++k;
+            }
+        }
+        o << "    const unsigned sw = swz(ethr);\n";
+        std::vector<int> perm(N);
+        for (int r = 0; r < N; ++r) {
+            perm[r] = r;
+            o << "    " << V << " x" << r << " = lp[sw ^ " << swz_host(er[r]) << "u];\n";
+        }
+        for (int i = 0; i < G.nops; ++i) {
+            const int oi = G.op0 + i;
+            const POp& op = prog.ops[prog.pass_op0[p] + oi];
+            const int J = op.rpos;
+            const int cls = op.var / RB;
+            const size_t uoff = (size_t)(op_base + oi) * sizeof(POp) + offsetof(POp, u);
+            const uint32_t tm = op.cmask & ~rmask, rm = op.cmask & rmask;
+            // Generic class: the outer controls decide per tile; fast classes have none.
+            const bool outer = cls >= kFwdGenericClass && op.omask != 0;
+            const bool swap = cls == 3;
+            const bool lane_pred = (cls == 3 || cls >= kFwdGenericClass) && tm != 0;
+            const bool cond = lane_pred || outer;
+            o << "    {\n";
+            if (!swap) o << "      const " << R << "* u = (const " << R << "*)(ops + " << uoff << ");\n";
+            if (cond) {
+                o << "      const bool pc = true";
+                if (lane_pred) o << " && ((ethr & " << tm << "u) == " << (op.cval & tm) << "u)";
+                if (outer) o << " && ((base & " << U(op.omask) << ") == " << U(op.oval) << ")";
+                o << ";\n";
+            }
+            for (int a = 0; a < N; ++a) {
+                if ((a >> J) & 1) continue;
+                if ((cls == 3 || cls >= kFwdGenericClass) && (er[a] & rm) != (op.cval & rm)) continue;
+                const std::string X = "x" + I(perm[a]), Y = "x" + I(perm[a | (1 << J)]);
+                if (swap) {
+                    if (!cond) {
+                        std::swap(perm[a], perm[a | (1 << J)]);
+                    } else {
+                        o << "      { const " << V << " p = " << X << ", q = " << Y << "; " << X << " = pc ? q : p; " << Y
+                          << " = pc ? p : q; }\n";
+                    }
+                    continue;
+                }
+                std::string np, nq;
+                if (cls == 0) {  // (c a + i s b, i s a + c b), c = u[0], s = u[5]
+                    np = MK + "(u[0] * p.x - u[5] * q.y, u[0] * p.y + u[5] * q.x)";
+                    nq = MK + "(u[0] * q.x - u[5] * p.y, u[0] * q.y + u[5] * p.x)";
+                } else if (cls == 1) {  // diag(u0 + i u4, u3 + i u7)
+                    np = MK + "(u[0] * p.x - u[4] * p.y, u[0] * p.y + u[4] * p.x)";
+                    nq = MK + "(u[3] * q.x - u[7] * q.y, u[3] * q.y + u[7] * q.x)";
+                } else {  // dense: mr = u[0..3], mi = u[4..7], row-major
+                    np = MK + "(u[0] * p.x - u[4] * p.y + u[1] * q.x - u[5] * q.y, u[0] * p.y + u[4] * p.x + u[1] * q.y + u[5] * q.x)";
+                    nq = MK + "(u[2] * p.x - u[6] * p.y + u[3] * q.x - u[7] * q.y, u[2] * p.y + u[6] * p.x + u[3] * q.y + u[7] * q.x)";
+                }
+                o << "      { const " << V << " p = " << X << ", q = " << Y << "; ";
+                if (cond) o << X << " = pc ? " << np << " : p; " << Y << " = pc ? " << nq << " : q; }\n";
+                else o << X << " = " << np << "; " << Y << " = " << nq << "; }\n";
+            }
+            o << "    }\n";
+        }
+        for (int r = 0; r < N; ++r) o << "    lp[sw ^ " << swz_host(er[r]) << "u] = x" << perm[r] << ";\n";
+        o << "  }\n  __syncthreads();\n";
+    }
+    // Store: element e = th + r * nthr of the stored tile comes from LDS tile element
+    // sth | sreg[r], thread bit i moving to tile bit store_src[i].
+    o << "  unsigned sth = 0;\n";
+    for (int i = 0; i < t - RB; ++i) {
+        const int src = pass.store_src.empty() ? i : pass.store_src[i];
+        o << "  sth |= ((th >> " << i << ") & 1u) << " << src << ";\n";
+    }
+    o << "  const unsigned ssw = swz(sth);\n";
+    for (int r = 0; r < N; ++r) {
+        uint32_t v = 0;
+        for (int j = 0; j < RB; ++j)
+            if ((r >> j) & 1) v |= 1u << (pass.store_src.empty() ? t - RB + j : pass.store_src[t - RB + j]);
+        o << "  gp[toff | " << U(rofs[r]) << "] = lp[ssw ^ " << swz_host(v) << "u];\n";
+    }
+    o << "}\n";
+    *nthr_out = nthr;
+    *lds_out = lds;
+    return o.str();
+}
+
+std::mutex g_jit_mu;
+int g_suspend = 0;
+std::atomic<long long> g_compiled_programs{0}, g_compiled_passes{0}, g_launches{0};
+
+}  // namespace
+
+struct JitPasses {
+    std::vector<hipModule_t> mod;   // per pass
+    std::vector<hipFunction_t> fn;  // per pass; null: the generic kernel
+    std::vector<int> nthr;
+    std::vector<size_t> lds;
+    std::vector<int> ntiles;
+};
+
+void jit_suspend(bool on)
+{
+    std::lock_guard<std::mutex> lk(g_jit_mu);
+    g_suspend += on ? 1 : -1;
+}
+
+namespace {
+
+// Source of each supported pass of a program (empty for passes left to the generic kernel),
+// every pass a program of its own so that the passes compile in parallel.
+int jit_source(const Plan& P, const Program& prog, bool bwd, int dtype, int n, std::vector<std::string>& src,
+               std::vector<int>& nthr, std::vector<size_t>& lds)
+{
+    src.assign(P.passes.size(), "");
+    nthr.assign(P.passes.size(), 0);
+    lds.assign(P.passes.size(), 0);
+    int count = 0;
+    if (bwd) return 0;
+    for (size_t p = 0; p < P.passes.size(); ++p) {
+        const std::string code = gen_forward_pass(P, prog, (int)p, n, dtype, "yao_pass", &nthr[p], &lds[p]);
+        if (code.empty()) continue;
+        src[p] = std::string(kPrelude) + code;
+        ++count;
+    }
+    return count;
+}
+
+// Compile the non-empty sources on a few host threads; code[p] stays empty for a failure, and
+// logs[p] then holds the compiler log.
+std::vector<char> jit_build(const std::string& src, std::string* log);
+void jit_build_all(const std::vector<std::string>& src, std::vector<std::vector<char>>& code,
+                   std::vector<std::string>& logs)
+{
+    code.assign(src.size(), {});
+    logs.assign(src.size(), "");
+    std::atomic<size_t> next{0};
+    auto work = [&] {
+        for (size_t p; (p = next.fetch_add(1)) < src.size();)
+            if (!src[p].empty()) code[p] = jit_build(src[p], &logs[p]);
+    };
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned i = 1; i < hw && i < src.size(); ++i) th.emplace_back(work);
+    work();
+    for (std::thread& x : th) x.join();
+}
+
+// hipRTC compile for gfx950 with the library's own code-generation flags. Returns the code
+// object, or an empty vector with the compiler log in *log.
+std::vector<char> jit_build(const std::string& src, std::string* log)
+{
+    std::vector<char> code;
+    hiprtcProgram rp;
+    if (hiprtcCreateProgram(&rp, src.c_str(), "yao_pass.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+        if (log) *log = "hiprtcCreateProgram failed";
+        return code;
+    }
+    // The load/store vectorizer finds nothing to merge here (LDS rows are XOR-swizzled, tile
+    // rows far apart) and costs a sixth of the compile time.
+    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-ffp-contract=fast", "-Xclang", "-target-feature",
+                          "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-load-store-vectorizer=false"};
+    if (hiprtcCompileProgram(rp, (int)(sizeof(opts) / sizeof(opts[0])), opts) == HIPRTC_SUCCESS) {
+        size_t cs = 0;
+        if (hiprtcGetCodeSize(rp, &cs) == HIPRTC_SUCCESS && cs > 0) {
+            code.resize(cs);
+            if (hiprtcGetCode(rp, code.data()) != HIPRTC_SUCCESS) code.clear();
+        }
+    } else if (log) {
+        size_t ls = 0;
+        if (hiprtcGetProgramLogSize(rp, &ls) == HIPRTC_SUCCESS && ls > 0) {
+            std::string l(ls, '\0');
+            if (hiprtcGetProgramLog(rp, &l[0]) == HIPRTC_SUCCESS) *log = l;
+        }
+    }
+    (void)hiprtcDestroyProgram(&rp);
+    return code;
+}
+
+}  // namespace
+
+// Compile every supported pass of a bound program into one module. Returns nullptr (and
+// leaves the program on the generic kernels) when nothing is supported or compiling fails.
+static JitPasses* jit_compile(const Plan& P, const Program& prog, bool bwd, int dtype, int n)
+{
+    std::vector<std::string> src, logs;
+    std::vector<int> nthr;
+    std::vector<size_t> lds;
+    if (jit_source(P, prog, bwd, dtype, n, src, nthr, lds) == 0) return nullptr;
+    std::vector<std::vector<char>> code;
+    jit_build_all(src, code, logs);
+    for (size_t p = 0; p < src.size(); ++p)
+        if (!src[p].empty() && code[p].empty()) return nullptr;
+    JitPasses* J = new JitPasses;
+    J->mod.assign(P.passes.size(), nullptr);
+    J->fn.assign(P.passes.size(), nullptr);
+    J->nthr = nthr;
+    J->lds = lds;
+    J->ntiles.assign(P.passes.size(), 0);
+    for (size_t p = 0; p < P.passes.size(); ++p) {
+        if (code[p].empty()) continue;
+        if (hipModuleLoadData(&J->mod[p], code[p].data()) != hipSuccess ||
+            hipModuleGetFunction(&J->fn[p], J->mod[p], "yao_pass") != hipSuccess) {
+            jit_free(J);
+            return nullptr;
+        }
+        J->ntiles[p] = 1 << (n - P.t);
+        ++g_compiled_passes;
+    }
+    ++g_compiled_programs;
+    return J;
+}
+
+const JitPasses* jit_passes(const BoundProgram* bp, const Plan& P, bool bwd, int dtype, int n, int B)
+{
+    if (!bp || B != 1 || bwd) return nullptr;
+    const int when = options().jit;
+    std::lock_guard<std::mutex> lk(g_jit_mu);
+    if (bp->jit || bp->jit_failed) return bp->jit;
+    if (when <= 0 || g_suspend > 0 || recording()) return nullptr;
+    if (++bp->uses < when) return nullptr;
+    bp->jit = jit_compile(P, bp->prog, bwd, dtype, n);
+    if (!bp->jit) bp->jit_failed = true;
+    return bp->jit;
+}
+
+bool jit_has(const JitPasses* J, int p)
+{
+    return J && p < (int)J->fn.size() && J->fn[p];
+}
+
+int jit_launch_forward(const JitPasses* J, int p, void* psi, const POp* ops, int op_first, double bytes,
+                       double flops)
+{
+    const ZSlot* zs = zbatch_slots();
+    const int nz = zs ? zbatch_count() : 1;
+    struct {
+        void* psi;
+        const void* ops;
+        const void* zs;
+        int op_first;
+        int pad;
+    } args{psi, ops + op_first, zs, op_first, 0};
+    size_t asz = sizeof(args);
+    void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &asz, HIP_LAUNCH_PARAM_END};
+    ++g_launches;
+    const int pi = prof_begin(YAO_KF_PASS_FWD);
+    YAO_HIP(hipModuleLaunchKernel(J->fn[p], (unsigned)J->ntiles[p], 1, (unsigned)nz, (unsigned)J->nthr[p], 1, 1,
+                                  (unsigned)J->lds[p], stream(), nullptr, cfg));
+    prof_end(pi, bytes * nz, flops * nz);
+    return 0;
+}
+
+int jit_selfcheck(const yao_circuit* c, int dtype, int tile_qubits, int* npasses, int* njit)
+{
+    const int n = c->n;
+    int t, cb, L;
+    tile_geometry_tq(n, 1, dtype, false, tile_qubits, &t, &cb, &L);
+    if (t - cb < kMaxRegBits + 1) return set_error(YAO_EINVAL, "circuit too small for tile passes");
+    const Plan& P = get_plan(c, 0, (int)c->gates.size(), 1, t, cb, L, false);
+    if (!P.valid) return set_error(YAO_EINVAL, "pass plan could not restore the qubit layout");
+    Program prog;
+    YAO_TRY(build_program(P, c, nullptr, false, dtype, prog));
+    if (!prog.bindable) return set_error(YAO_EINVAL, "circuit cannot be bound on the device");
+    std::vector<std::string> src, logs;
+    std::vector<int> nthr;
+    std::vector<size_t> lds;
+    *npasses = (int)P.passes.size();
+    *njit = jit_source(P, prog, false, dtype, n, src, nthr, lds);
+    std::vector<std::vector<char>> code;
+    jit_build_all(src, code, logs);
+    for (size_t p = 0; p < src.size(); ++p)
+        if (!src[p].empty() && code[p].empty())
+            return set_error(YAO_EHIP, "run-time compile of pass %zu failed: %.400s", p, logs[p].c_str());
+    return 0;
+}
+
+void jit_stats(long long* programs, long long* passes, long long* launches)
+{
+    *programs = g_compiled_programs.load();
+    *passes = g_compiled_passes.load();
+    *launches = g_launches.load();
+}
+
+void jit_free(JitPasses* J)
+{
+    if (!J) return;
+    for (hipModule_t m : J->mod)
+        if (m) (void)hipModuleUnload(m);
+    delete J;
+}
+
+}  // namespace yao

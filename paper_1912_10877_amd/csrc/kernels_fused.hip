@@ -42,6 +42,11 @@ int zbatch_count()
     return g_zbatch.zs ? g_zbatch.nz : 1;
 }
 
+const ZSlot* zbatch_slots()
+{
+    return g_zbatch.zs;
+}
+
 namespace {
 
 struct PassArgs {

@@ -11,7 +11,7 @@ namespace yao {
 
 static thread_local std::string g_err;
 static hipStream_t g_stream = nullptr;
-static yao_options g_opts = {0, 0, 1, 0, 0.0, 1};
+static yao_options g_opts = {0, 0, 1, 0, 0.0, 1, 1, 3};
 static int g_device_ok = -1;  // -1 unknown, 0 no gfx950, 1 ok
 
 int set_error(int code, const char* fmt, ...)
@@ -62,6 +62,7 @@ void default_options(yao_options& o)
     o.drift_tol = 0.0;
     o.mfma = 1;
     o.autotune = 1;
+    o.jit = 3;
 }
 
 int ensure_device()
@@ -157,6 +158,11 @@ static bool g_recording = false;
 void set_recording(bool on)
 {
     g_recording = on;
+}
+
+bool recording()
+{
+    return g_recording;
 }
 
 void* ring_upload(const void* host, size_t bytes)

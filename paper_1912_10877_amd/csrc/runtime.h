@@ -58,6 +58,7 @@ void* pinned(int slot, size_t bytes);
 // take their constants by value or from buffers that the graph owns.
 void* ring_upload(const void* host, size_t bytes);
 void set_recording(bool on);
+bool recording();
 // Copy a host block into workspace slot `slot` (grown as needed), ordered on the stream.
 void* upload_to(int slot, const void* host, size_t bytes);
 

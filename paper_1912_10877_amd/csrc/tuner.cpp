@@ -71,6 +71,10 @@ int time_forward(const yao_circuit* c, const double* params, void* data, int dty
     // Wall time of the whole sweep (host work for the program included), median of three runs
     // for small states and one for large ones, after one untimed run.
     const int reps = (uint64_t(1) << n) * (uint64_t)B >= (uint64_t(1) << 24) ? 1 : 3;
+    struct Suspend {
+        Suspend() { jit_suspend(true); }
+        ~Suspend() { jit_suspend(false); }
+    } suspend;
     YAO_TRY(forward_sweep(data, dtype, n, B, c, params, width, tq, nullptr));
     YAO_HIP(hipStreamSynchronize(stream()));
     std::vector<double> v;
