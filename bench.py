@@ -583,7 +583,7 @@ def main():
                    "params": circ_w.nparams, "gates": ngates, "grad_mode": args.mode,
                    "forward_fusion": "autotuned" if args.fuse_width < 0 else args.fuse_width,
                    "jit": yb.get_options().jit},
-        "energy": float(e[0]), "drift": drift,
+        "energy": float(e[0]), "drift": drift, "jit_stats": yb.jit_stats(),
         "plain_ms_per_step": plain_ms,
         "speedup_vs_plain": (plain_ms / ms_step) if plain_ms else None,
         "roofline": roofline, "cpu_baseline": cpu, "uneven_batch": batch, "configs": configs, "next_rows": nxt,

@@ -335,16 +335,20 @@ int yao_profile_read(int family, int* launches, double* total_ms, double* algo_b
  * At most 20 qubits; no GPU is used. */
 int yao_plan_selfcheck(const yao_circuit* c, const double* params, enum yao_dtype dt, int reverse, int tile_qubits,
                        double* max_err, int* npasses);
-/* Generates the run-time compiled forward passes (see yao_options.jit) of circuit c, held as a
- * device-bound program of a single-slot state of dtype dt over tiles of tile_qubits qubits (0:
- * default), and compiles them for gfx950 with hipRTC, without loading them (no GPU is used).
+/* Generates the run-time compiled forward passes (reverse = 0) or reverse-sweep passes with
+ * gradients (reverse = 1; see yao_options.jit) of circuit c, held as a device-bound program of
+ * a single-slot state of dtype dt over tiles of tile_qubits qubits (0: default), and compiles
+ * them for gfx950 with hipRTC, without loading them (no GPU is used).
  * *npasses receives the plan's pass count and *njit how many of them compile to straight-line
  * kernels. Errors: YAO_EINVAL when c cannot be bound on the device or is too small for tile
  * passes; YAO_EHIP with the compiler log when the generated source does not compile. */
-int yao_jit_selfcheck(const yao_circuit* c, enum yao_dtype dt, int tile_qubits, int* npasses, int* njit);
-/* Counters of the run-time compiled passes since the library was loaded: programs compiled,
- * passes compiled, and launches of compiled passes. Any argument may be NULL. */
-int yao_jit_stats(long long* programs, long long* passes, long long* launches);
+int yao_jit_selfcheck(const yao_circuit* c, enum yao_dtype dt, int reverse, int tile_qubits, int* npasses,
+                      int* njit);
+/* Counters of the run-time compiled passes since the library was loaded, into out[0 .. 4]:
+ * programs compiled, passes compiled, programs whose compile or load failed (they keep the
+ * generic kernels; the reason is printed once to stderr), launches of compiled forward passes
+ * and launches of compiled reverse passes. */
+int yao_jit_stats(long long* out);
 
 #ifdef __cplusplus
 }

@@ -81,8 +81,8 @@ _SIGS = {
     "yao_profile_enable": [I],
     "yao_profile_read": [I, P, P, P, P],
     "yao_plan_selfcheck": [P, P, I, I, I, P, P],
-    "yao_jit_selfcheck": [P, I, I, P, P],
-    "yao_jit_stats": [P, P, P],
+    "yao_jit_selfcheck": [P, I, I, I, P, P],
+    "yao_jit_stats": [P],
 }
 
 
@@ -432,16 +432,18 @@ def plan_selfcheck(circ: Circuit, params, dtype=0, reverse=False, tile_qubits=0)
     return err.value, npass.value
 
 
-def jit_selfcheck(circ: Circuit, dtype=0, tile_qubits=0):
-    """Generate and compile (hipRTC, host only) the run-time forward passes of the circuit as
-    a device-bound program: returns (number of passes, number compiled to straight-line code)."""
+def jit_selfcheck(circ: Circuit, dtype=0, reverse=False, tile_qubits=0):
+    """Generate and compile (hipRTC, host only) the run-time forward (or reverse-sweep) passes of
+    the circuit as a device-bound program: returns (number of passes, number compiled)."""
     npass, njit = ctypes.c_int(), ctypes.c_int()
-    _check(lib().yao_jit_selfcheck(circ.h, int(dtype), int(tile_qubits), ctypes.byref(npass), ctypes.byref(njit)))
+    _check(lib().yao_jit_selfcheck(circ.h, int(dtype), int(bool(reverse)), int(tile_qubits), ctypes.byref(npass),
+                                   ctypes.byref(njit)))
     return npass.value, njit.value
 
 
 def jit_stats():
-    """(programs compiled, passes compiled, launches of compiled passes) since the library loaded."""
-    a, b, c = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
-    _check(lib().yao_jit_stats(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-    return a.value, b.value, c.value
+    """Since the library loaded: dict of programs and passes compiled, failed programs, and
+    launches of compiled forward and reverse passes."""
+    out = (ctypes.c_longlong * 5)()
+    _check(lib().yao_jit_stats(out))
+    return {"programs": out[0], "passes": out[1], "failures": out[2], "fwd_launches": out[3], "bwd_launches": out[4]}

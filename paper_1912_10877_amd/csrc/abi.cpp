@@ -446,23 +446,21 @@ int yao_profile_read(int family, int* launches, double* total_ms, double* algo_b
     return prof_read(family, launches, total_ms, algo_bytes, algo_flops);
 }
 
-int yao_jit_stats(long long* programs, long long* passes, long long* launches)
+int yao_jit_stats(long long* out)
 {
-    long long a = 0, b = 0, c = 0;
-    yao::jit_stats(&a, &b, &c);
-    if (programs) *programs = a;
-    if (passes) *passes = b;
-    if (launches) *launches = c;
+    if (!out) return set_error(YAO_EINVAL, "out is NULL");
+    yao::jit_stats(out);
     return 0;
 }
 
-int yao_jit_selfcheck(const yao_circuit* c, enum yao_dtype dt, int tile_qubits, int* npasses, int* njit)
+int yao_jit_selfcheck(const yao_circuit* c, enum yao_dtype dt, int reverse, int tile_qubits, int* npasses,
+                      int* njit)
 {
     if (!c || !npasses || !njit) return set_error(YAO_EINVAL, "NULL argument");
     if (dt != YAO_C64 && dt != YAO_C128) return set_error(YAO_EINVAL, "unknown dtype %d", (int)dt);
     if (tile_qubits < 0 || tile_qubits > 14) return set_error(YAO_EINVAL, "tile_qubits must be 0..14");
     if (c->n > kMaxQubits) return set_error(YAO_EINVAL, "too many qubits");
-    return yao::jit_selfcheck(c, dt, tile_qubits, npasses, njit);
+    return yao::jit_selfcheck(c, dt, reverse, tile_qubits, npasses, njit);
 }
 
 int yao_plan_selfcheck(const yao_circuit* c, const double* params, enum yao_dtype dt, int reverse, int tile_qubits,

@@ -743,7 +743,7 @@ int record_z_unit(Cache& C, const Unit& U)
     {
         ZBatchScope z(C.d_zs + U.zb, nz);
         YAO_TRY(launch_backward_passes(*it.bwd, bwd_prog(it), it.db, it.c, nullptr, C.psi64[bk], C.lam[bk], dt, n, 1,
-                                       C.gpart[bk], it.W));
+                                       C.gpart[bk], it.W, it.bb));
     }
     return launch_row_sums(C.gpart[bk], nz * it.nslots, it.W, C.d_out + it.out_g);
 }
@@ -760,7 +760,7 @@ int record_item(Cache& C, Item& it)
     YAO_TRY(launch_fill(C.gpart[bk], (size_t)it.nslots * it.W, 0.0));
     if (it.bb) YAO_TRY(bind_program(it.bb, C.d_params + it.poff));
     YAO_TRY(launch_backward_passes(*it.bwd, bwd_prog(it), it.db, it.c, nullptr, C.psi64[bk], C.lam[bk], dt, n, 1,
-                                   C.gpart[bk], it.W));
+                                   C.gpart[bk], it.W, it.bb));
     return launch_row_sums(C.gpart[bk], it.nslots, it.W, C.d_out + it.out_g);
 }
 

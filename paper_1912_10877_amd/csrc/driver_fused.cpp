@@ -478,11 +478,18 @@ int launch_forward_passes(const Plan& P, const Program& prog, const DevProgram& 
 
 int launch_backward_passes(const Plan& P, const Program& prog, const DevProgram& d, const yao_circuit* c,
                            const double* params, double* psi, void* lam, int lam_dtype, int n, int B, double* gpartial,
-                           int W)
+                           int W, const BoundProgram* bp)
 {
     if (!P.valid) return set_error(YAO_EINVAL, "pass plan could not restore the qubit layout");
+    const JitPasses* J = bp && &bp->prog == &prog ? jit_passes(bp, P, true, lam_dtype, n, B) : nullptr;
     for (size_t p = 0; p < P.passes.size(); ++p) {
         const HostPass& pass = P.passes[p];
+        if (jit_has(J, (int)p)) {
+            const double N = (double)(uint64_t(1) << n) * B;
+            YAO_TRY(jit_launch_backward(J, (int)p, psi, lam, d.ops, prog.pass_op0[p], d.mats, gpartial, W,
+                                        2.0 * N * (16 + (lam_dtype == YAO_C64 ? 8 : 16)), prog.pass_flops[p] * N));
+            continue;
+        }
         if (pass.standalone >= 0) {
             // Matrices come from the program; the launch takes only their size from Ud and M.
             const int gi = P.ops[pass.standalone].gate;
@@ -741,7 +748,7 @@ static int backward_reversible(yao_state* s, const yao_circuit* c, const double*
     if (bp) YAO_TRY(bind_program(bp, dp));
     else YAO_TRY(upload_program(hprog, hd, WS_MAT2));
     const Program& prog = bp ? bp->prog : hprog;
-    YAO_TRY(launch_backward_passes(P, prog, bp ? bp->d : hd, c, params, psi, lam, s->dtype, n, B, gpartial, W));
+    YAO_TRY(launch_backward_passes(P, prog, bp ? bp->d : hd, c, params, psi, lam, s->dtype, n, B, gpartial, W, bp));
     if (nslots) YAO_TRY(launch_row_sums(gpartial, nslots * B, W, sums));
     const size_t nres = (size_t)B + (size_t)nslots * B;
     double* hres = (double*)pinned(WS_PARTIAL, sizeof(double) * nres);

@@ -225,7 +225,7 @@ int launch_forward_passes(const Plan& P, const Program& prog, const DevProgram& 
                           const yao_circuit* c, const double* params, const BoundProgram* bp = nullptr);
 int launch_backward_passes(const Plan& P, const Program& prog, const DevProgram& d, const yao_circuit* c,
                            const double* params, double* psi, void* lam, int lam_dtype, int n, int B, double* gpartial,
-                           int W);
+                           int W, const BoundProgram* bp = nullptr);
 
 // Drivers.
 int forward_fused(void* data, int dtype, int n, int B, const yao_circuit* c, const double* params);
@@ -290,10 +290,14 @@ bool jit_has(const JitPasses* J, int p);
 int jit_launch_forward(const JitPasses* J, int p, void* psi, const POp* ops, int op_first, double bytes,
                        double flops);
 void jit_free(JitPasses* J);
-void jit_stats(long long* programs, long long* passes, long long* launches);
-// Host only: generate and compile (no module load) the run-time forward passes of circuit c
-// as a bound program; *njit of *npasses passes are compiled.
-int jit_selfcheck(const yao_circuit* c, int dtype, int tile_qubits, int* npasses, int* njit);
+// Programs compiled, passes compiled, programs that failed to compile or load, launches of
+// compiled forward passes, of compiled reverse passes.
+void jit_stats(long long* out);
+// Host only: generate and compile (no module load) the run-time forward (or reverse) passes of
+// circuit c as a bound program; *njit of *npasses passes are compiled.
+int jit_selfcheck(const yao_circuit* c, int dtype, int reverse, int tile_qubits, int* npasses, int* njit);
+int jit_launch_backward(const JitPasses* J, int p, double* psi, void* lam, const POp* ops, int op_first,
+                        const double* mats, double* gpartial, int pstride, double bytes, double flops);
 // Nested: while any suspension is active nothing is compiled (autotuner trials).
 void jit_suspend(bool on);
 const BoundProgram* bound_program(const Plan& P, const yao_circuit* c, bool bwd, int dtype,

@@ -10,12 +10,13 @@
 // and the matrix entries are read from the records at constant offsets.
 //
 // Supported: single-slot states (B = 1), passes whose groups are all register groups (no
-// LDS-applied k = 2, 3 ops and no dense blocks), LDS tiles of at most 64 KiB. Any other pass
-// of the program runs the generic kernel. A compile failure switches the program back to the
-// generic kernels for good.
+// LDS-applied k = 2, 3 ops and no dense blocks); the LDS of a compiled pass is a static
+// allocation of the sizes the pass needs. Any other pass of the program runs the generic
+// kernel. A compile failure switches the program back to the generic kernels for good.
 #include <hip/hiprtc.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <atomic>
 #include <cstddef>
 #include <mutex>
@@ -46,8 +47,12 @@ uint32_t swz_host(uint32_t e)
     return e ^ (((e >> 4) ^ (e >> 8)) & 15u);
 }
 
+// Pointers in the generated code carry their address space: global memory for states and
+// partials (global instead of flat loads) and constant for the op records (scalar loads).
 const char* kPrelude = R"YAO(
 typedef unsigned long long u64;
+#define GLB __attribute__((address_space(1)))
+#define CST __attribute__((address_space(4)))
 __device__ __forceinline__ unsigned swz(unsigned e) { return e ^ (((e >> 4) ^ (e >> 8)) & 15u); }
 )YAO";
 
@@ -64,18 +69,19 @@ std::string gen_forward_pass(const Plan& P, const Program& prog, int p, int n, i
         if (prog.groups[g0 + g].lds) return "";
     const bool c64 = dtype == YAO_C64;
     const size_t lds = (size_t)(c64 ? 8 : 16) << t;
-    if (lds > 65536) return "";
+    if (lds > 160 * 1024) return "";
     const int nthr = 1 << (t - RB);
     const std::string V = c64 ? "float2" : "double2", R = c64 ? "float" : "double";
     const std::string MK = c64 ? "make_float2" : "make_double2";
     std::ostringstream o;
     o << "extern \"C\" __global__ void __launch_bounds__(" << nthr << ") " << name
       << "(void* psi_, const char* ops_, const char* zs_, int op_first) {\n";
-    o << "  extern __shared__ __align__(16) " << V << " lp[];\n";
+    // LDS sized at compile time (static allocations may exceed the 64 KiB of a dynamic one).
+    o << "  __shared__ __align__(16) " << V << " lp[" << (1 << t) << "];\n";
     o << "  const unsigned th = threadIdx.x;\n";
-    o << "  " << V << "* gp = (" << V << "*)psi_;\n  const char* ops = ops_;\n";
-    o << "  if (zs_) { const char* z = zs_ + 32 * blockIdx.z; gp = *(" << V
-      << "* const*)z; ops = *(const char* const*)(z + 16) + (u64)op_first * " << sizeof(POp) << "; }\n";
+    o << "  GLB " << V << "* gp = (GLB " << V << "*)psi_;\n  const CST char* ops = (const CST char*)ops_;\n";
+    o << "  if (zs_) { const CST u64* z = (const CST u64*)(zs_ + 32 * blockIdx.z); gp = (GLB " << V
+      << "*)z[0]; ops = (const CST char*)z[2] + (u64)op_first * " << sizeof(POp) << "; }\n";
     // Tile base: the tile index bits on the qubits outside the tile, ascending.
     uint64_t T = 0;
     for (int q : pass.tile_qubits) T |= uint64_t(1) << q;
@@ -144,7 +150,7 @@ std::string gen_forward_pass(const Plan& P, const Program& prog, int p, int n, i
             const bool lane_pred = (cls == 3 || cls >= kFwdGenericClass) && tm != 0;
             const bool cond = lane_pred || outer;
             o << "    {\n";
-            if (!swap) o << "      const " << R << "* u = (const " << R << "*)(ops + " << uoff << ");\n";
+            if (!swap) o << "      const CST " << R << "* u = (const CST " << R << "*)(ops + " << uoff << ");\n";
             if (cond) {
                 o << "      const bool pc = true";
                 if (lane_pred) o << " && ((ethr & " << tm << "u) == " << (op.cval & tm) << "u)";
@@ -204,9 +210,269 @@ std::string gen_forward_pass(const Plan& P, const Program& prog, int p, int n, i
     return o.str();
 }
 
+// Gradient term of one pair for generator class gen (Re or Im of lambda^dagger M psi on the
+// pair, the generic kernels' formulas): p0, p1 psi and l0, l1 lambda of the pair.
+std::string grad_expr(int gen, const std::string& p0, const std::string& p1, const std::string& l0,
+                      const std::string& l1)
+{
+    switch (gen) {
+    case GEN_X: return "fma(" + l0 + ".x, " + p1 + ".y, fma(-" + l0 + ".y, " + p1 + ".x, fma(" + l1 + ".x, " + p0 + ".y, -" + l1 + ".y * " + p0 + ".x)))";
+    case GEN_Y: return "fma(" + l1 + ".x, " + p0 + ".x, fma(" + l1 + ".y, " + p0 + ".y, fma(-" + l0 + ".x, " + p1 + ".x, -" + l0 + ".y * " + p1 + ".y)))";
+    case GEN_Z: return "fma(" + l0 + ".x, " + p0 + ".y, fma(-" + l0 + ".y, " + p0 + ".x, fma(-" + l1 + ".x, " + p1 + ".y, " + l1 + ".y * " + p1 + ".x)))";
+    case GEN_P1: return "(-2.0 * fma(" + l1 + ".x, " + p1 + ".y, -" + l1 + ".y * " + p1 + ".x))";
+    default:
+        return "dense_grad(gm, " + p0 + ", " + p1 + ", " + l0 + ", " + l1 + ")";
+    }
+}
+
+const char* kBwdPrelude = R"YAO(
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
+{
+    const u64 b = __builtin_bit_cast(u64, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((u64)hi << 32) | lo);
+}
+// Sum over the 16 lanes of a DPP row (single-slot tiles): lane 0 of the row holds it.
+__device__ __forceinline__ double row_sum16(double v)
+{
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x124>(v);
+    v += dpp_f64<0x128>(v);
+    return v;
+}
+// 2 Re(conj(l) M p) for a dense 2 x 2 generator M (re[4], im[4], row-major).
+__device__ __forceinline__ double dense_grad(const CST double* m, double2 p0, double2 p1, double2 l0, double2 l1)
+{
+    const double m0x = m[0] * p0.x - m[4] * p0.y + m[1] * p1.x - m[5] * p1.y;
+    const double m0y = m[0] * p0.y + m[4] * p0.x + m[1] * p1.y + m[5] * p1.x;
+    const double m1x = m[2] * p0.x - m[6] * p0.y + m[3] * p1.x - m[7] * p1.y;
+    const double m1y = m[2] * p0.y + m[6] * p0.x + m[3] * p1.y + m[7] * p1.x;
+    return 2.0 * (l0.x * m0x + l0.y * m0y + l1.x * m1x + l1.y * m1y);
+}
+)YAO";
+
+// Code of one reverse pass (psi in FP64, lambda in the state's precision), or an empty
+// string when the pass is not supported.
+std::string gen_backward_pass(const Plan& P, const Program& prog, int p, int n, int dtype, const std::string& name,
+                              int* nthr_out, size_t* lds_out)
+{
+    const HostPass& pass = P.passes[p];
+    const int RB = P.reg_bits, N = 1 << RB, t = P.t;
+    if (P.c != 0 || pass.standalone >= 0) return "";
+    if (t - RB < 4 || t - RB > 9 || (int)pass.tile_qubits.size() != t) return "";
+    const int g0 = prog.pass_group0[p], ng = (int)pass.groups.size();
+    int maxslots = 0;
+    for (int g = 0; g < ng; ++g) {
+        if (prog.groups[g0 + g].lds) return "";
+        maxslots = std::max(maxslots, prog.groups[g0 + g].nslot);
+    }
+    const bool c64 = dtype == YAO_C64;
+    const int nthr = 1 << (t - RB), E = nthr >> 4;
+    const int lb = c64 ? 8 : 16;
+    const size_t lds = ((size_t)(16 + lb) << t) + sizeof(double) * 2 * (size_t)std::max(1, maxslots) * E;
+    if (lds > 160 * 1024) return "";
+    const std::string VL = c64 ? "float2" : "double2", RL = c64 ? "float" : "double";
+    std::ostringstream o;
+    o << "extern \"C\" __global__ void __launch_bounds__(" << nthr << ") " << name
+      << "(void* psi_, void* lam_, const char* ops_, const double* mats, double* gpart_, const char* zs_, int op_first, "
+         "int pstride) {\n";
+    o << "  __shared__ __align__(16) unsigned char smem[" << lds << "];\n";
+    o << "  double2* lp = (double2*)smem;\n  " << VL << "* ll = (" << VL << "*)(smem + " << (16 << t) << ");\n";
+    o << "  double* red0 = (double*)(smem + " << ((16 + lb) << t) << ");\n";
+    o << "  const unsigned th = threadIdx.x;\n";
+    o << "  GLB double2* gp = (GLB double2*)psi_;\n  GLB " << VL << "* gl = (GLB " << VL << "*)lam_;\n";
+    o << "  const CST char* ops = (const CST char*)ops_;\n  GLB double* gpart = (GLB double*)gpart_;\n";
+    o << "  if (zs_) { const CST u64* z = (const CST u64*)(zs_ + 32 * blockIdx.z); gp = (GLB double2*)z[0]; gl = (GLB "
+      << VL << "*)z[1]; ops = (const CST char*)z[2] + (u64)op_first * " << sizeof(POp)
+      << "; gpart = (GLB double*)z[3]; }\n";
+    uint64_t T = 0;
+    for (int q : pass.tile_qubits) T |= uint64_t(1) << q;
+    o << "  const u64 tid = blockIdx.x;\n  u64 base = 0;\n";
+    {
+        int j = 0;
+        for (int q = 0; q < n; ++q) {
+            if ((T >> q) & 1) continue;
+            o << "  base |= ((tid >> " << j << ") & 1ull) << " << q << ";\n";
+            ++j;
+        }
+    }
+    o << "  u64 toff = base;\n";
+    for (int j = 0; j < t - RB; ++j) o << "  toff |= (u64)((th >> " << j << ") & 1u) << " << pass.tile_qubits[j] << ";\n";
+    std::vector<uint64_t> rofs(N);
+    for (int r = 0; r < N; ++r) {
+        uint64_t d = 0;
+        for (int b = 0; b < RB; ++b)
+            if ((r >> b) & 1) d |= uint64_t(1) << pass.tile_qubits[t - RB + b];
+        rofs[r] = d;
+    }
+    o << "  {\n";
+    for (int r = 0; r < N; ++r)
+        o << "    const double2 v" << r << " = gp[toff | " << U(rofs[r]) << "]; const " << VL << " w" << r << " = gl[toff | "
+          << U(rofs[r]) << "];\n";
+    for (int r = 0; r < N; ++r)
+        o << "    lp[swz(th + " << r * nthr << "u)] = v" << r << "; ll[swz(th + " << r * nthr << "u)] = w" << r << ";\n";
+    o << "  }\n  __syncthreads();\n";
+    o << "  double phr = 1.0, phi = 0.0;\n";
+    int buf = 0;
+    for (int g = 0; g < ng; ++g) {
+        const PGroupDesc& G = prog.groups[g0 + g];
+        uint32_t rmask = 0;
+        for (int j = 0; j < RB; ++j) rmask |= 1u << G.rpos[j];
+        std::vector<uint32_t> er(N);
+        for (int r = 0; r < N; ++r) {
+            uint32_t e = 0;
+            for (int j = 0; j < RB; ++j)
+                if ((r >> j) & 1) e |= 1u << G.rpos[j];
+            er[r] = e;
+        }
+        o << "  {\n    unsigned ethr = 0;\n";
+        {
+            int k = 0;
+            for (int b = 0; b < t; ++b) {
+                if ((rmask >> b) & 1) continue;
+                o << "    ethr |= ((th >> " << k << ") & 1u) << " << b << ";\n";
+                ++k;
+            }
+        }
+        o << "    const unsigned sw = swz(ethr);\n";
+        o << "    double* red = red0 + " << buf * std::max(1, maxslots) * E << ";\n";
+        std::vector<int> perm(N);
+        for (int r = 0; r < N; ++r) {
+            perm[r] = r;
+            o << "    double2 x" << r << " = lp[sw ^ " << swz_host(er[r]) << "u]; double2 y" << r << "; { const " << VL
+              << " q = ll[sw ^ " << swz_host(er[r]) << "u]; y" << r << " = make_double2((double)q.x, (double)q.y); }\n";
+        }
+        int nslot = 0;
+        for (int i = 0; i < G.nops; ++i) {
+            const int oi = G.op0 + i;
+            const POp& op = prog.ops[prog.pass_op0[p] + oi];
+            const int J = op.rpos;
+            const int cls = op.var / RB;
+            const size_t uoff = (size_t)oi * sizeof(POp) + offsetof(POp, u);
+            const uint32_t tm = op.cmask & ~rmask, rm = op.cmask & rmask;
+            const bool generic = cls >= kBwdGenericClass;
+            const bool outer = generic && op.omask != 0;
+            const bool lane_pred = (cls == 2 || generic) && tm != 0;
+            const bool cond = lane_pred || outer;
+            o << "    {\n      const CST double* u = (const CST double*)(ops + " << uoff << ");\n";
+            if (generic && op.slot >= 0 && op.gen == GEN_DENSE)
+                o << "      const CST double* gm = (const CST double*)mats + " << op.mat + 8 << ";\n";
+            if (cond) {
+                o << "      const bool pc = true";
+                if (lane_pred) o << " && ((ethr & " << tm << "u) == " << (op.cval & tm) << "u)";
+                if (outer) o << " && ((base & " << U(op.omask) << ") == " << U(op.oval) << ")";
+                o << ";\n";
+            }
+            // Pairs whose register-bit controls hold.
+            std::vector<int> pairs;
+            for (int a = 0; a < N; ++a) {
+                if ((a >> J) & 1) continue;
+                if ((cls == 2 || generic) && (er[a] & rm) != (op.cval & rm)) continue;
+                pairs.push_back(a);
+            }
+            // Gradient from psi and lambda before the update.
+            if (op.slot >= 0) {
+                const int gen = cls == 0 ? GEN_X : cls == 1 ? GEN_Z : op.gen;
+                o << "      double g = 0.0;\n";
+                for (int a : pairs) {
+                    const std::string e = grad_expr(gen, "x" + I(perm[a]), "x" + I(perm[a | (1 << J)]), "y" + I(perm[a]),
+                                                    "y" + I(perm[a | (1 << J)]));
+                    if (cond) o << "      g += pc ? " << e << " : 0.0;\n";
+                    else o << "      g += " << e << ";\n";
+                }
+                o << "      g = row_sum16(g);\n      if ((th & 15u) == 0) red[" << nslot * E << " + (th >> 4)] = g;\n";
+                ++nslot;
+            }
+            for (int a : pairs) {
+                const std::string X = "x" + I(perm[a]), Y = "x" + I(perm[a | (1 << J)]);
+                const std::string LX = "y" + I(perm[a]), LY = "y" + I(perm[a | (1 << J)]);
+                if (cls == 2) {
+                    if (!cond) {
+                        std::swap(perm[a], perm[a | (1 << J)]);
+                    } else {
+                        for (const auto& pr : {std::make_pair(X, Y), std::make_pair(LX, LY)})
+                            o << "      { const double2 p = " << pr.first << ", q = " << pr.second << "; " << pr.first
+                              << " = pc ? q : p; " << pr.second << " = pc ? p : q; }\n";
+                    }
+                    continue;
+                }
+                for (const auto& pr : {std::make_pair(X, Y), std::make_pair(LX, LY)}) {
+                    const std::string& A = pr.first;
+                    const std::string& B = pr.second;
+                    if (cls == 0) {  // (c a + i s b, i s a + c b)
+                        o << "      { const double2 p = " << A << ", q = " << B << "; " << A
+                          << " = make_double2(u[0] * p.x - u[5] * q.y, u[0] * p.y + u[5] * q.x); " << B
+                          << " = make_double2(u[0] * q.x - u[5] * p.y, u[0] * q.y + u[5] * p.x); }\n";
+                    } else if (cls == 1) {  // diag(1, u3 + i u7); the first entry goes to the phase
+                        o << "      { const double2 q = " << B << "; " << B
+                          << " = make_double2(u[3] * q.x - u[7] * q.y, u[3] * q.y + u[7] * q.x); }\n";
+                    } else {
+                        const std::string np = "make_double2(u[0] * p.x - u[4] * p.y + u[1] * q.x - u[5] * q.y, u[0] * p.y + u[4] * p.x + u[1] * q.y + u[5] * q.x)";
+                        const std::string nq = "make_double2(u[2] * p.x - u[6] * p.y + u[3] * q.x - u[7] * q.y, u[2] * p.y + u[6] * p.x + u[3] * q.y + u[7] * q.x)";
+                        o << "      { const double2 p = " << A << ", q = " << B << "; ";
+                        if (cond) o << A << " = pc ? " << np << " : p; " << B << " = pc ? " << nq << " : q; }\n";
+                        else o << A << " = " << np << "; " << B << " = " << nq << "; }\n";
+                    }
+                }
+            }
+            if (cls == 1) o << "      { const double pr = phr * u[0] - phi * u[4]; phi = phr * u[4] + phi * u[0]; phr = pr; }\n";
+            o << "    }\n";
+        }
+        if (nslot != G.nslot) return "";  // the record's slots and the group's list disagree
+        for (int r = 0; r < N; ++r)
+            o << "    lp[sw ^ " << swz_host(er[r]) << "u] = x" << perm[r] << "; ll[sw ^ " << swz_host(er[r]) << "u] = make_"
+              << VL << "((" << RL << ")y" << perm[r] << ".x, (" << RL << ")y" << perm[r] << ".y);\n";
+        o << "  }\n  __syncthreads();\n";
+        if (nslot > 0) {
+            // Partials of each gradient over the tile: 16 tasks per gradient, E entries each.
+            o << "  {\n    const double* red = red0 + " << buf * std::max(1, maxslots) * E << ";\n";
+            o << "    for (unsigned task = th; task < " << nslot * 16 << "u; task += " << nthr << "u) {\n";
+            o << "      const unsigned s = task >> 4, j = task & 15u;\n      double v = 0.0;\n";
+            o << "      for (unsigned e = j; e < " << E << "u; e += 16u) v += red[s * " << E << "u + e];\n";
+            o << "      for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, 16);\n";
+            o << "      int slot = " << G.slots[0] << ";\n";
+            for (int k = 1; k < nslot; ++k) o << "      if (s == " << k << "u) slot = " << G.slots[k] << ";\n";
+            o << "      if (j == 0) gpart[(u64)slot * (u64)pstride + blockIdx.x] = v;\n    }\n  }\n";
+            buf ^= 1;
+        }
+    }
+    // Store with the accumulated phase.
+    o << "  unsigned sth = 0;\n";
+    for (int i = 0; i < t - RB; ++i) {
+        const int src = pass.store_src.empty() ? i : pass.store_src[i];
+        o << "  sth |= ((th >> " << i << ") & 1u) << " << src << ";\n";
+    }
+    o << "  const unsigned ssw = swz(sth);\n";
+    for (int r = 0; r < N; ++r) {
+        uint32_t v = 0;
+        for (int j = 0; j < RB; ++j)
+            if ((r >> j) & 1) v |= 1u << (pass.store_src.empty() ? t - RB + j : pass.store_src[t - RB + j]);
+        o << "  { const double2 v = lp[ssw ^ " << swz_host(v) << "u]; const " << VL << " w = ll[ssw ^ " << swz_host(v)
+          << "u]; const double wx = (double)w.x, wy = (double)w.y;\n";
+        o << "    gp[toff | " << U(rofs[r]) << "] = make_double2(phr * v.x - phi * v.y, phr * v.y + phi * v.x);\n";
+        o << "    gl[toff | " << U(rofs[r]) << "] = make_" << VL << "((" << RL << ")(phr * wx - phi * wy), (" << RL
+          << ")(phr * wy + phi * wx)); }\n";
+    }
+    o << "}\n";
+    *nthr_out = nthr;
+    *lds_out = lds;
+    return o.str();
+}
+
 std::mutex g_jit_mu;
 int g_suspend = 0;
-std::atomic<long long> g_compiled_programs{0}, g_compiled_passes{0}, g_launches{0};
+std::atomic<long long> g_compiled_programs{0}, g_compiled_passes{0}, g_failures{0};
+std::atomic<long long> g_launches_fwd{0}, g_launches_bwd{0};
+
+// A program that could not be compiled keeps the generic kernels; say why, once per program.
+void report_failure(const char* what, const std::string& detail)
+{
+    ++g_failures;
+    fprintf(stderr, "yao: run-time compiled passes unavailable (%s): %.300s; using the generic kernels\n", what,
+            detail.c_str());
+}
 
 }  // namespace
 
@@ -235,11 +501,11 @@ int jit_source(const Plan& P, const Program& prog, bool bwd, int dtype, int n, s
     nthr.assign(P.passes.size(), 0);
     lds.assign(P.passes.size(), 0);
     int count = 0;
-    if (bwd) return 0;
     for (size_t p = 0; p < P.passes.size(); ++p) {
-        const std::string code = gen_forward_pass(P, prog, (int)p, n, dtype, "yao_pass", &nthr[p], &lds[p]);
+        const std::string code = bwd ? gen_backward_pass(P, prog, (int)p, n, dtype, "yao_pass", &nthr[p], &lds[p])
+                                     : gen_forward_pass(P, prog, (int)p, n, dtype, "yao_pass", &nthr[p], &lds[p]);
         if (code.empty()) continue;
-        src[p] = std::string(kPrelude) + code;
+        src[p] = std::string(kPrelude) + (bwd ? kBwdPrelude : "") + code;
         ++count;
     }
     return count;
@@ -309,7 +575,10 @@ static JitPasses* jit_compile(const Plan& P, const Program& prog, bool bwd, int 
     std::vector<std::vector<char>> code;
     jit_build_all(src, code, logs);
     for (size_t p = 0; p < src.size(); ++p)
-        if (!src[p].empty() && code[p].empty()) return nullptr;
+        if (!src[p].empty() && code[p].empty()) {
+            report_failure("compile", logs[p]);
+            return nullptr;
+        }
     JitPasses* J = new JitPasses;
     J->mod.assign(P.passes.size(), nullptr);
     J->fn.assign(P.passes.size(), nullptr);
@@ -318,8 +587,10 @@ static JitPasses* jit_compile(const Plan& P, const Program& prog, bool bwd, int 
     J->ntiles.assign(P.passes.size(), 0);
     for (size_t p = 0; p < P.passes.size(); ++p) {
         if (code[p].empty()) continue;
-        if (hipModuleLoadData(&J->mod[p], code[p].data()) != hipSuccess ||
-            hipModuleGetFunction(&J->fn[p], J->mod[p], "yao_pass") != hipSuccess) {
+        hipError_t e = hipModuleLoadData(&J->mod[p], code[p].data());
+        if (e == hipSuccess) e = hipModuleGetFunction(&J->fn[p], J->mod[p], "yao_pass");
+        if (e != hipSuccess) {
+            report_failure("module load", hipGetErrorString(e));
             jit_free(J);
             return nullptr;
         }
@@ -332,7 +603,7 @@ static JitPasses* jit_compile(const Plan& P, const Program& prog, bool bwd, int 
 
 const JitPasses* jit_passes(const BoundProgram* bp, const Plan& P, bool bwd, int dtype, int n, int B)
 {
-    if (!bp || B != 1 || bwd) return nullptr;
+    if (!bp || B != 1) return nullptr;
     const int when = options().jit;
     std::lock_guard<std::mutex> lk(g_jit_mu);
     if (bp->jit || bp->jit_failed) return bp->jit;
@@ -362,30 +633,31 @@ int jit_launch_forward(const JitPasses* J, int p, void* psi, const POp* ops, int
     } args{psi, ops + op_first, zs, op_first, 0};
     size_t asz = sizeof(args);
     void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &asz, HIP_LAUNCH_PARAM_END};
-    ++g_launches;
+    ++g_launches_fwd;
     const int pi = prof_begin(YAO_KF_PASS_FWD);
-    YAO_HIP(hipModuleLaunchKernel(J->fn[p], (unsigned)J->ntiles[p], 1, (unsigned)nz, (unsigned)J->nthr[p], 1, 1,
-                                  (unsigned)J->lds[p], stream(), nullptr, cfg));
+    YAO_HIP(hipModuleLaunchKernel(J->fn[p], (unsigned)J->ntiles[p], 1, (unsigned)nz, (unsigned)J->nthr[p], 1, 1, 0,
+                                  stream(), nullptr, cfg));
     prof_end(pi, bytes * nz, flops * nz);
     return 0;
 }
 
-int jit_selfcheck(const yao_circuit* c, int dtype, int tile_qubits, int* npasses, int* njit)
+int jit_selfcheck(const yao_circuit* c, int dtype, int reverse, int tile_qubits, int* npasses, int* njit)
 {
     const int n = c->n;
+    const bool bwd = reverse != 0;
     int t, cb, L;
-    tile_geometry_tq(n, 1, dtype, false, tile_qubits, &t, &cb, &L);
+    tile_geometry_tq(n, 1, dtype, bwd, tile_qubits, &t, &cb, &L);
     if (t - cb < kMaxRegBits + 1) return set_error(YAO_EINVAL, "circuit too small for tile passes");
-    const Plan& P = get_plan(c, 0, (int)c->gates.size(), 1, t, cb, L, false);
+    const Plan& P = get_plan(c, 0, (int)c->gates.size(), 1, t, cb, L, bwd, dtype == YAO_C64 ? 8 : 16);
     if (!P.valid) return set_error(YAO_EINVAL, "pass plan could not restore the qubit layout");
     Program prog;
-    YAO_TRY(build_program(P, c, nullptr, false, dtype, prog));
+    YAO_TRY(build_program(P, c, nullptr, bwd, dtype, prog));
     if (!prog.bindable) return set_error(YAO_EINVAL, "circuit cannot be bound on the device");
     std::vector<std::string> src, logs;
     std::vector<int> nthr;
     std::vector<size_t> lds;
     *npasses = (int)P.passes.size();
-    *njit = jit_source(P, prog, false, dtype, n, src, nthr, lds);
+    *njit = jit_source(P, prog, bwd, dtype, n, src, nthr, lds);
     std::vector<std::vector<char>> code;
     jit_build_all(src, code, logs);
     for (size_t p = 0; p < src.size(); ++p)
@@ -394,11 +666,39 @@ int jit_selfcheck(const yao_circuit* c, int dtype, int tile_qubits, int* npasses
     return 0;
 }
 
-void jit_stats(long long* programs, long long* passes, long long* launches)
+int jit_launch_backward(const JitPasses* J, int p, double* psi, void* lam, const POp* ops, int op_first,
+                        const double* mats, double* gpartial, int pstride, double bytes, double flops)
 {
-    *programs = g_compiled_programs.load();
-    *passes = g_compiled_passes.load();
-    *launches = g_launches.load();
+    const ZSlot* zs = zbatch_slots();
+    const int nz = zs ? zbatch_count() : 1;
+    const int ps = std::max(pstride, J->ntiles[p]);
+    struct {
+        void* psi;
+        void* lam;
+        const void* ops;
+        const double* mats;
+        double* gpart;
+        const void* zs;
+        int op_first;
+        int pstride;
+    } args{psi, lam, ops + op_first, mats, gpartial, zs, op_first, ps};
+    size_t asz = sizeof(args);
+    void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &asz, HIP_LAUNCH_PARAM_END};
+    ++g_launches_bwd;
+    const int pi = prof_begin(YAO_KF_PASS_BWD);
+    YAO_HIP(hipModuleLaunchKernel(J->fn[p], (unsigned)J->ntiles[p], 1, (unsigned)nz, (unsigned)J->nthr[p], 1, 1, 0,
+                                  stream(), nullptr, cfg));
+    prof_end(pi, bytes * nz, flops * nz);
+    return 0;
+}
+
+void jit_stats(long long* out)
+{
+    out[0] = g_compiled_programs.load();
+    out[1] = g_compiled_passes.load();
+    out[2] = g_failures.load();
+    out[3] = g_launches_fwd.load();
+    out[4] = g_launches_bwd.load();
 }
 
 void jit_free(JitPasses* J)

@@ -26,6 +26,7 @@ def gpu():
     yb.init()
     yb.set_options(jit=1, autotune=0, fuse_width=0)
     yield
+    assert yb.jit_stats()["failures"] == 0
     yb.set_options(jit=3, autotune=1, fuse_width=0)
 
 
@@ -75,9 +76,9 @@ def test_compiled_forward_matches_oracle(kind, n, d, dtype, width):
     for rep in range(3):
         params = w.angles(900 + 17 * rep + n, c.nparams)
         s = yb.State(n, 1, dtype)
-        l0 = yb.jit_stats()[2]
+        l0 = yb.jit_stats()["fwd_launches"]
         yb.forward(s, circ, params)
-        assert yb.jit_stats()[2] > l0, "no compiled pass ran"
+        assert yb.jit_stats()["fwd_launches"] > l0, "no compiled pass ran"
         want = oracle.forward(c, params, w.zero_state(n))
         err = np.abs(s.download() - want).max()
         assert err <= tol(dtype, len(c.gates)), (rep, err)
@@ -92,9 +93,9 @@ def test_compiled_forward_inside_backward():
     for rep in range(2):
         params = w.angles(950 + rep, c.nparams)
         s = yb.State(14, 1, 0)
-        l0 = yb.jit_stats()[2]
+        l0 = yb.jit_stats()["fwd_launches"]
         e, g, _ = yb.backward(s, circ, params, h)
-        assert yb.jit_stats()[2] > l0, "the forward sweep did not use the compiled passes"
+        assert yb.jit_stats()["fwd_launches"] > l0, "the forward sweep did not use the compiled passes"
         e_ref, g_ref, _ = oracle.adjoint(H, c, params, w.zero_state(14))
         assert abs(e - e_ref[0]) <= 1e-5
         assert np.abs(np.asarray(g).ravel() - g_ref[0]).max() <= 1e-4 * max(1.0, np.abs(g_ref[0]).max())
@@ -118,3 +119,29 @@ def test_batched_and_lds_passes_keep_generic_kernels():
     for _ in range(2):
         got = run_forward(c2, p2, 0)
     assert np.abs(got - oracle.forward(c2, p2, w.zero_state(13))).max() <= tol(0, len(c2.gates))
+
+
+@pytest.mark.parametrize("kind,n,d,dtype", [("hea", 13, 3, 0), ("hea", 14, 2, 1), ("hea", 16, 4, 0),
+                                            ("rand", 13, 70, 0), ("rand", 15, 60, 1)])
+def test_compiled_reverse_sweep_matches_oracle(kind, n, d, dtype):
+    """Reverse passes compiled with their gradients: energy and every gradient against the
+    oracle's adjoint, for two angle sets after compiling (the compiled code reads the
+    bound records)."""
+    yb.set_options(jit=1, autotune=0, fuse_width=0)
+    c = w.hea_circuit(n, d) if kind == "hea" else random_bindable(n, d, seed=1100 + n + d)
+    H = w.heisenberg(n)
+    circ, h = yb.Circuit.from_workload(c), yb.PauliSum.from_workload(H)
+    for rep in range(2):
+        params = w.angles(1200 + 31 * rep + n, c.nparams)
+        s = yb.State(n, 1, dtype)
+        l0 = yb.jit_stats()["bwd_launches"]
+        e, g, _ = yb.backward(s, circ, params, h)
+        assert yb.jit_stats()["bwd_launches"] > l0, "the reverse sweep did not use the compiled passes"
+        e_ref, g_ref, _ = oracle.adjoint(H, c, params, w.zero_state(n))
+        te, tg = (1e-5, 1e-4) if dtype == 0 else (1e-10, 1e-9)
+        assert abs(e - e_ref[0]) <= te, (rep, e, e_ref[0])
+        scale = max(1.0, float(np.abs(g_ref[0]).max()))
+        assert np.abs(np.asarray(g).ravel() - g_ref[0]).max() <= tg * scale, rep
+        # The state keeps the forward sweep's output (the reverse sweep runs on its own copy).
+        want = oracle.forward(c, params, w.zero_state(n))
+        assert np.abs(s.download() - want).max() <= tol(dtype, len(c.gates))

@@ -8,9 +8,10 @@ from paper_1912_10877_amd import binding as yb
 
 
 @pytest.mark.parametrize("n,depth,dtype", [(8, 2, 0), (10, 2, 1)])
-def test_ansatz_passes_all_compile(n, depth, dtype):
+@pytest.mark.parametrize("reverse", [False, True])
+def test_ansatz_passes_all_compile(n, depth, dtype, reverse):
     circ = yb.Circuit.from_workload(w.hea_circuit(n, depth))
-    npass, njit = yb.jit_selfcheck(circ, dtype)
+    npass, njit = yb.jit_selfcheck(circ, dtype, reverse=reverse)
     assert npass >= 1 and njit == npass
 
 
@@ -19,8 +20,9 @@ def test_controlled_one_qubit_gates_compile():
              w.Gate("Ry", (5,), param=1, ctrls=(2,), cvals=(0,)), w.Gate("shift", (8,), param=2, ctrls=(0,), cvals=(1,)),
              w.Gate("H", (6,)), w.Gate("Z", (4,), ctrls=(8,), cvals=(1,))]
     circ = yb.Circuit.from_workload(w.Circuit(9, gates, 3))
-    npass, njit = yb.jit_selfcheck(circ, 0)
-    assert njit == npass
+    for reverse in (False, True):
+        npass, njit = yb.jit_selfcheck(circ, 0, reverse=reverse)
+        assert njit == npass
 
 
 def test_two_qubit_gates_stay_generic():
