@@ -380,7 +380,8 @@ def run_case(name, reps):
         # The headline step with the forward fusion the autotuner picks for it (runs of one-qubit
         # gates merged), fixed so that no timing trial runs under the profiler.
         B = 64 if name == "step20_b64" else 1
-        yb.set_options(autotune=0, fuse_width=1)
+        # Compiled passes from the first (untimed) call on, so every profiled step runs them.
+        yb.set_options(autotune=0, fuse_width=1, jit=1)
         c = w.hea_circuit(20, 20)
         cc, H, p = yb.Circuit.from_workload(c), yb.PauliSum.from_workload(w.heisenberg(20)), w.angles(2, c.nparams)
         s = yb.State(20, B, yb.C64)
@@ -497,11 +498,15 @@ def main():
         # library's stream): per-kernel durations for the roofline. The events slow the host's
         # launches, so the step time above is taken without them.
         import ctypes
+        js0 = yb.jit_stats()
         yb.lib().yao_profile_enable(1)
         for _ in range(args.steps):
             step()
         torch.cuda.synchronize()
         yb.lib().yao_profile_enable(0)
+        js1 = yb.jit_stats()
+        jit_fwd = js1["fwd_launches"] > js0["fwd_launches"]
+        jit_bwd = js1["bwd_launches"] > js0["bwd_launches"]
         yb.lib().yao_profile_read.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         for fam in FAMILIES:
             nl, ms, by, fl = ctypes.c_int(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
@@ -539,10 +544,18 @@ def main():
         else:
             roofline = {"bound": "alu", "achieved": round(tfl, 3), "peak": peak_alu, "unit": "TFLOP/s",
                         "frac": round(tfl / peak_alu, 4), "traffic": None}
-        if dtype == yb.C64 and fam in (2, 3):
-            roofline["traffic"] = (measured_traffic("k_pass_bwd<float, true>", "k_pass_bwd_vqe20.txt") if fam == 3 else
-                                   measured_traffic("k_pass_fwd<float>", "k_pass_fwd_vqe20.txt"))
-        roofline.update({"kernel": KERNEL_NAMES[fam], "launches_per_step": nl / args.steps,
+        # The pass families run the run-time compiled kernels once a program has compiled.
+        kname = KERNEL_NAMES[fam]
+        if fam == 3 and jit_bwd:
+            kname = "yao_pass_bwd"
+        elif fam == 2 and jit_fwd:
+            kname = "yao_pass_fwd"
+        if dtype == yb.C64 and B == 1 and fam in (2, 3):
+            summary = {"k_pass_bwd": "k_pass_bwd_vqe20.txt", "k_pass_fwd": "k_pass_fwd_vqe20.txt",
+                       "yao_pass_bwd": "yao_pass_bwd_vqe20.txt", "yao_pass_fwd": "yao_pass_fwd_vqe20.txt"}[kname]
+            counted = {"k_pass_bwd": "k_pass_bwd<float, true>", "k_pass_fwd": "k_pass_fwd<float>"}.get(kname, kname)
+            roofline["traffic"] = measured_traffic(counted, summary)
+        roofline.update({"kernel": kname, "launches_per_step": nl / args.steps,
                          "avg_launch_us": round(ms * 1e3 / nl, 2), "algo_bytes_per_launch": by / nl,
                          "algo_flops_per_launch": fl / nl, "achieved_gbs": round(gbs, 1),
                          "achieved_tflops": round(tfl, 3),

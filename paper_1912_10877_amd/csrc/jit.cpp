@@ -502,8 +502,8 @@ int jit_source(const Plan& P, const Program& prog, bool bwd, int dtype, int n, s
     lds.assign(P.passes.size(), 0);
     int count = 0;
     for (size_t p = 0; p < P.passes.size(); ++p) {
-        const std::string code = bwd ? gen_backward_pass(P, prog, (int)p, n, dtype, "yao_pass", &nthr[p], &lds[p])
-                                     : gen_forward_pass(P, prog, (int)p, n, dtype, "yao_pass", &nthr[p], &lds[p]);
+        const std::string code = bwd ? gen_backward_pass(P, prog, (int)p, n, dtype, "yao_pass_bwd", &nthr[p], &lds[p])
+                                     : gen_forward_pass(P, prog, (int)p, n, dtype, "yao_pass_fwd", &nthr[p], &lds[p]);
         if (code.empty()) continue;
         src[p] = std::string(kPrelude) + (bwd ? kBwdPrelude : "") + code;
         ++count;
@@ -588,7 +588,7 @@ static JitPasses* jit_compile(const Plan& P, const Program& prog, bool bwd, int 
     for (size_t p = 0; p < P.passes.size(); ++p) {
         if (code[p].empty()) continue;
         hipError_t e = hipModuleLoadData(&J->mod[p], code[p].data());
-        if (e == hipSuccess) e = hipModuleGetFunction(&J->fn[p], J->mod[p], "yao_pass");
+        if (e == hipSuccess) e = hipModuleGetFunction(&J->fn[p], J->mod[p], bwd ? "yao_pass_bwd" : "yao_pass_fwd");
         if (e != hipSuccess) {
             report_failure("module load", hipGetErrorString(e));
             jit_free(J);
