@@ -77,9 +77,10 @@ def parse():
     p.add_argument("--batch-steps", type=int, default=5)
     p.add_argument("--fuse-width", type=int, default=-1,
                    help="forward fusion width 0..5 with the autotuner off (-1: autotuned)")
-    p.add_argument("--jit", type=int, default=-1,
-                   help="run-time compiled passes after this many uses of a bound program (0: off; -1: the "
-                        "library default)")
+    p.add_argument("--tile-qubits", type=int, default=0, help="tile qubits of the pass kernels (0: default)")
+    p.add_argument("--jit", type=int, default=1,
+                   help="run-time compiled passes from this use of a bound program on (0: off); 1 compiles on "
+                        "the first use, so the untimed warm-up call of every measurement absorbs the compile")
     return p.parse_args()
 
 
@@ -466,8 +467,9 @@ def main():
     yb.use_torch_stream()
     if args.fuse_width >= 0:
         yb.set_options(autotune=0, fuse_width=args.fuse_width)
-    if args.jit >= 0:
-        yb.set_options(jit=args.jit)
+    yb.set_options(jit=args.jit)
+    if args.tile_qubits:
+        yb.set_options(tile_qubits=args.tile_qubits)
     n, depth, B = args.qubits, args.depth, args.batch
     dtype = yb.C64 if args.dtype == "c64" else yb.C128
     mode = {"reversible": yb.GRAD_REVERSIBLE, "checkpoint": yb.GRAD_CHECKPOINT, "auto": yb.GRAD_AUTO}[args.mode]

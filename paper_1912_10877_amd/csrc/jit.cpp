@@ -76,8 +76,12 @@ std::string gen_forward_pass(const Plan& P, const Program& prog, int p, int n, i
     std::ostringstream o;
     o << "extern \"C\" __global__ void __launch_bounds__(" << nthr << ") " << name
       << "(void* psi_, const char* ops_, const char* zs_, int op_first) {\n";
-    // LDS sized at compile time (static allocations may exceed the 64 KiB of a dynamic one).
+    // LDS sized at compile time (static allocations may exceed the 64 KiB of a dynamic one):
+    // the tile, and the pass's one-qubit matrices (8 entries per record), copied in with the
+    // tile so that the ops read them from LDS instead of waiting on a scalar load each.
+    const int nrec = prog.pass_nops[p];
     o << "  __shared__ __align__(16) " << V << " lp[" << (1 << t) << "];\n";
+    o << "  __shared__ __align__(16) " << R << " um[" << std::max(1, nrec) * 8 << "];\n";
     o << "  const unsigned th = threadIdx.x;\n";
     o << "  GLB " << V << "* gp = (GLB " << V << "*)psi_;\n  const CST char* ops = (const CST char*)ops_;\n";
     o << "  if (zs_) { const CST u64* z = (const CST u64*)(zs_ + 32 * blockIdx.z); gp = (GLB " << V
@@ -107,10 +111,15 @@ std::string gen_forward_pass(const Plan& P, const Program& prog, int p, int n, i
     }
     o << "  {\n";
     for (int r = 0; r < N; ++r) o << "    const " << V << " v" << r << " = gp[toff | " << U(rofs[r]) << "];\n";
+    {
+        const int W = c64 ? 8 : 16;  // dwords of a record's matrix
+        o << "    { const CST unsigned* src = (const CST unsigned*)ops; unsigned* dst = (unsigned*)um;\n"
+          << "      for (unsigned i = th; i < " << nrec * W << "u; i += " << nthr << "u) dst[i] = src[(i / " << W << "u) * "
+          << sizeof(POp) / 4 << "u + " << offsetof(POp, u) / 4 << "u + i % " << W << "u]; }\n";
+    }
     for (int r = 0; r < N; ++r) o << "    lp[swz(th + " << r * nthr << "u)] = v" << r << ";\n";
     o << "  }\n  __syncthreads();\n";
-    // Register groups.
-    const int op_base = 0;  // records are addressed relative to the pass's first record
+    // Register groups (records are addressed relative to the pass's first record).
     for (int g = 0; g < ng; ++g) {
         const PGroupDesc& G = prog.groups[g0 + g];
         uint32_t rmask = 0;
@@ -142,7 +151,6 @@ std::string gen_forward_pass(const Plan& P, const Program& prog, int p, int n, i
             const POp& op = prog.ops[prog.pass_op0[p] + oi];
             const int J = op.rpos;
             const int cls = op.var / RB;
-            const size_t uoff = (size_t)(op_base + oi) * sizeof(POp) + offsetof(POp, u);
             const uint32_t tm = op.cmask & ~rmask, rm = op.cmask & rmask;
             // Generic class: the outer controls decide per tile; fast classes have none.
             const bool outer = cls >= kFwdGenericClass && op.omask != 0;
@@ -150,7 +158,7 @@ std::string gen_forward_pass(const Plan& P, const Program& prog, int p, int n, i
             const bool lane_pred = (cls == 3 || cls >= kFwdGenericClass) && tm != 0;
             const bool cond = lane_pred || outer;
             o << "    {\n";
-            if (!swap) o << "      const CST " << R << "* u = (const CST " << R << "*)(ops + " << uoff << ");\n";
+            if (!swap) o << "      const " << R << "* u = um + " << oi * 8 << ";\n";
             if (cond) {
                 o << "      const bool pc = true";
                 if (lane_pred) o << " && ((ethr & " << tm << "u) == " << (op.cval & tm) << "u)";
@@ -275,7 +283,12 @@ std::string gen_backward_pass(const Plan& P, const Program& prog, int p, int n, 
     if (lds > 160 * 1024) return "";
     const std::string VL = c64 ? "float2" : "double2", RL = c64 ? "float" : "double";
     std::ostringstream o;
-    o << "extern \"C\" __global__ void __launch_bounds__(" << nthr << ") " << name
+    // Workgroups per CU that the LDS allows; when that is more than the registers would
+    // allow at the compiler's choice, ask for the register budget that fits them.
+    const int wg_lds = (int)std::min<size_t>(8, (160 * 1024) / lds);
+    const int waves = std::max(1, wg_lds * (nthr / 64) / 4);  // per SIMD
+    o << "extern \"C\" __global__ void __launch_bounds__(" << nthr << ") __attribute__((amdgpu_waves_per_eu("
+      << std::min(waves, 8) << "))) " << name
       << "(void* psi_, void* lam_, const char* ops_, const double* mats, double* gpart_, const char* zs_, int op_first, "
          "int pstride) {\n";
     o << "  __shared__ __align__(16) unsigned char smem[" << lds << "];\n";
@@ -350,13 +363,15 @@ std::string gen_backward_pass(const Plan& P, const Program& prog, int p, int n, 
             const POp& op = prog.ops[prog.pass_op0[p] + oi];
             const int J = op.rpos;
             const int cls = op.var / RB;
-            const size_t uoff = (size_t)oi * sizeof(POp) + offsetof(POp, u);
             const uint32_t tm = op.cmask & ~rmask, rm = op.cmask & rmask;
             const bool generic = cls >= kBwdGenericClass;
             const bool outer = generic && op.omask != 0;
             const bool lane_pred = (cls == 2 || generic) && tm != 0;
             const bool cond = lane_pred || outer;
-            o << "    {\n      const CST double* u = (const CST double*)(ops + " << uoff << ");\n";
+            // Reverse ops read their matrices through the scalar cache (in LDS they would occupy
+            // VGPRs, and the reverse kernel has none to spare).
+            o << "    {\n      const CST double* u = (const CST double*)(ops + " << (size_t)oi * sizeof(POp) + offsetof(POp, u)
+              << ");\n";
             if (generic && op.slot >= 0 && op.gen == GEN_DENSE)
                 o << "      const CST double* gm = (const CST double*)mats + " << op.mat + 8 << ";\n";
             if (cond) {
