@@ -31,6 +31,14 @@ KERNEL_NAMES = {0: "k_gate1/k_gatek", 1: "k_adjoint", 2: "k_pass_fwd", 3: "k_pas
                 11: "Krylov vector kernels"}
 
 
+_T0 = time.time()
+
+
+def log(msg):
+    """Progress line on stderr (long measurements, run-time compiles): seconds since start."""
+    print(f"bench [{time.time() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def measured_traffic(kernel, summary):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
     profiles/<summary> (FETCH_SIZE and WRITE_SIZE per dispatch, calibrated by a cold copy of
@@ -164,6 +172,7 @@ def bench_configs(yb, w, torch):
             s.reset()
             yb.backward(s, cc, p, H)
         out["c1_10q_fwd_grad_c128_us"] = round(timed(c1, 50) * 1e3, 1)
+        log("config c1 (10 qubits, complex128) done")
 
         # 25 qubits, depth 20: forward + energy (autotuned fusion), complex64 and complex128;
         # and one Rx launch of the per-gate form (reads and writes the state once).
@@ -187,6 +196,7 @@ def bench_configs(yb, w, torch):
             out[f"c2_25q_per_gate_{name}"] = {"us": round(gate_ms * 1e3, 1), "hbm_gbs": round(gbs, 1),
                                               "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}
             del s
+            log(f"config c2 (25 qubits, {name}) done")
 
         # 20 qubits, depth 20, the same circuit on a batch of 64 states (512 MiB complex64).
         c = w.hea_circuit(20, 20)
@@ -200,6 +210,7 @@ def bench_configs(yb, w, torch):
         out["c3_20q_b64_fwd_grad_ms"] = round(ms, 2)
         out["c3_20q_b64_amplitude_updates_per_s"] = 3.0 * len(c.gates) * float(1 << 20) * 64 / (ms / 1e3)
         del s
+        log("config c3 (20 qubits, batch 64) done")
 
         # 30 qubits, depth 24, Haar-random one-qubit layers + CZ pairs: complex64 with 5-qubit
         # blocks on the FP32 matrix cores against complex128 (one-qubit runs merged).
@@ -214,14 +225,17 @@ def bench_configs(yb, w, torch):
             yb.forward(s64, cc, [])
         yb.set_options(autotune=1, mfma=1)
         ms64_tuned = timed(f64, 2)
+        log("config c5 (30 qubits) autotuned complex64 done")
         yb.set_options(autotune=0, fuse_width=5, mfma=1)
         ms64 = timed(f64, 2)
+        log("config c5 (30 qubits) 5-qubit blocks done")
         yb.set_options(autotune=0, fuse_width=1)
 
         def f128():
             s128.reset()
             yb.forward(s128, cc, [])
         ms128 = timed(f128, 2)
+        log("config c5 (30 qubits) complex128 done")
         fid = float(abs(torch.vdot(t128, t64.to(torch.complex128)).item()) ** 2)
         e64, e128 = float(yb.expect(s64, zz)[0]), float(yb.expect(s128, zz)[0])
         out["c5_30q"] = {"gates": len(c.gates), "c64_mfma_w5_ms": round(ms64, 1),
@@ -266,6 +280,7 @@ def bench_next_rows(yb, w, torch):
         out[f"f1_shift_{n}q"] = {"params": c.nparams, "circuits": 2 * c.nparams + 1,
                                  "dtype": "c128" if dt == yb.C128 else "c64", "shift_ms": round(shift_ms, 2),
                                  "adjoint_ms": round(adj_ms, 3), "shift_over_adjoint": round(shift_ms / adj_ms, 1)}
+        log(f"next row f1 shift rule ({n} qubits) done")
         del s
     # QFT kernel and qubit permutation at 25 qubits.
     n = 25
@@ -284,6 +299,7 @@ def bench_next_rows(yb, w, torch):
         pprof = profile_family(yb, 8)
         out[f"f4_qft_25q_{name}"] = {"ms": round(qms, 3), **prof}
         out[f"f4_permute_25q_{name}"] = {"ms": round(pms, 3), **pprof}
+        log(f"next row f4 QFT and permutation (25 qubits, {name}) done")
         if dt == yb.C128:
             out["f4_qft_25q_c128"]["traffic_per_launch"] = measured_traffic("k_qft_pass<double, false>",
                                                                             "k_qft_pass_qft25_c128.txt")
@@ -303,6 +319,7 @@ def bench_next_rows(yb, w, torch):
     mms = timed(lambda: yb.measure(s, list(range(n)), u), 3)
     yb.lib().yao_profile_enable(0)
     out["f2_measure_24q_c128"] = {"shots": 1 << 20, "ms": round(mms, 3), **profile_family(yb, 10)}
+    log("next row f2 measurement done")
     del s
     # Time evolution (the 16-qubit size of Listing "Hamiltonian evolution is faster with cache").
     for n in (16, 20):
@@ -317,6 +334,7 @@ def bench_next_rows(yb, w, torch):
         up_ms = timed(lambda: s.upload(psi), 3)
         te_ms = timed(te, 3) - up_ms
         out[f"f3_evolve_{n}q_c128"] = {"t": 0.1, "substeps": steps, "ms": round(te_ms, 3)}
+        log(f"next row f3 time evolution ({n} qubits) done")
         del s
     # The headline step in checkpointed mode, and in complex128.
     c = w.hea_circuit(20, 20)
@@ -489,6 +507,7 @@ def main():
     for _ in range(args.warmup):
         e, g, drift = step()
     torch.cuda.synchronize()
+    log("headline warm-up done (run-time compiles included)")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         e, g, drift = step()
@@ -566,13 +585,16 @@ def main():
     batch = None
     if args.batch_circuits > 0:
         batch = bench_uneven_batch(yb, w, torch, args.batch_circuits, args.batch_steps)
+        log("uneven batch done")
 
     configs = None
     if not args.no_configs:
         configs = bench_configs(yb, w, torch)
+        log("configurations done")
     nxt = None
     if not args.no_next:
         nxt = bench_next_rows(yb, w, torch)
+        log("next rows done")
 
     cpu = None
     if not args.no_cpu_baseline:
