@@ -86,9 +86,9 @@ def parse():
     p.add_argument("--fuse-width", type=int, default=-1,
                    help="forward fusion width 0..5 with the autotuner off (-1: autotuned)")
     p.add_argument("--tile-qubits", type=int, default=0, help="tile qubits of the pass kernels (0: default)")
-    p.add_argument("--jit", type=int, default=1,
-                   help="run-time compiled passes from this use of a bound program on (0: off); 1 compiles on "
-                        "the first use, so the untimed warm-up call of every measurement absorbs the compile")
+    p.add_argument("--jit", type=int, default=-1,
+                   help="run-time compiled passes from this use of a bound program on (0: off; -1: the library "
+                        "default, the third use: every timed measurement runs three warm-up calls first)")
     return p.parse_args()
 
 
@@ -152,7 +152,8 @@ def bench_configs(yb, w, torch):
     import numpy as np
 
     def timed(f, reps):
-        f()
+        for _ in range(3):  # warm-up; a program's third use compiles its passes at run time
+            f()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
@@ -257,7 +258,8 @@ def bench_next_rows(yb, w, torch):
     import numpy as np
 
     def timed(f, reps):
-        f()
+        for _ in range(3):  # warm-up; a program's third use compiles its passes at run time
+            f()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
@@ -485,7 +487,8 @@ def main():
     yb.use_torch_stream()
     if args.fuse_width >= 0:
         yb.set_options(autotune=0, fuse_width=args.fuse_width)
-    yb.set_options(jit=args.jit)
+    if args.jit >= 0:
+        yb.set_options(jit=args.jit)
     if args.tile_qubits:
         yb.set_options(tile_qubits=args.tile_qubits)
     n, depth, B = args.qubits, args.depth, args.batch
