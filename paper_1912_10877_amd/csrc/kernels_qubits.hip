@@ -110,6 +110,40 @@ __global__ __launch_bounds__(kQThreads) void k_permute(const V* __restrict__ in,
     }
 }
 
+// Single-slot states with tiles of 256 * NPER rows: row e = threadIdx.x + 256 i, so the row's
+// low table half is the lane's (fixed for the launch) and its high half the wave's (uniform);
+// the tables come by value with the arguments (scalar loads, nothing staged in LDS) and every
+// thread's NPER loads are issued before the first LDS write.
+struct PermArgsB1 {
+    PermTables tab;
+    int nrest;
+    int rpos[kMaxIndexBits];
+    int rout[kMaxIndexBits];
+};
+static_assert(sizeof(PermArgsB1) + 16 <= 4096, "kernel arguments must fit the 4 KiB argument segment");
+
+template <typename V, int NPER>
+__global__ __launch_bounds__(kQThreads) void k_permute_b1(const V* __restrict__ in, V* __restrict__ out, PermArgsB1 pa)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    V* tile = reinterpret_cast<V*>(lds_raw);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t r = blockIdx.x;
+    const uint64_t base_in = deposit_rest(r, pa.rpos, pa.nrest) | pa.tab.in_lo[lane];
+    const uint64_t base_out = deposit_rest(r, pa.rout, pa.nrest) | pa.tab.out_lo[lane];
+    const int slo = (int)pa.tab.src_lo[lane];
+    V v[NPER];
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) v[i] = in[base_in | pa.tab.in_hi[wave + 4 * i]];
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) tile[swz_row(threadIdx.x + kQThreads * i)] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NPER; ++i)
+        out[base_out | pa.tab.out_hi[wave + 4 * i]] = tile[swz_row(slo | (int)pa.tab.src_hi[wave + 4 * i])];
+}
+
 // ------------------------------------------------------------------------------ QFT passes
 struct QftTables {
     uint64_t in_lo[64], in_hi[64];  // index bits of each tile row (memory order)
@@ -318,6 +352,43 @@ int launch_permute(const void* in, void* out, int dtype, int n, int B, const int
     fill_halves(tab.in_lo, tab.in_hi, m, fin);
     fill_halves(tab.out_lo, tab.out_hi, m, fout);
     fill_halves(tab.src_lo, tab.src_hi, m, fsrc);
+    if (B == 1 && m >= 8 && m <= 12) {
+        // Tiles of 256 .. 4096 rows on single-slot states: the table-by-value kernel.
+        PermArgsB1 pb;
+        memset(&pb, 0, sizeof(pb));
+        pb.tab = tab;
+        pb.nrest = pa.nrest;
+        for (int j = 0; j < pa.nrest; ++j) {
+            pb.rpos[j] = pa.rpos[j];
+            pb.rout[j] = pa.rout[j];
+        }
+        const uint64_t nb = uint64_t(1) << pa.nrest;
+        if (nb > 0x7fffffffull) return set_error(YAO_EINVAL, "permutation grid too large");
+        const size_t lds1 = ((size_t)1 << m) * es;
+        const int pi = prof_begin(YAO_KF_PERMUTE);
+#define YAO_PERM_B1(V, NP) k_permute_b1<V, NP><<<(unsigned)nb, kQThreads, lds1, stream()>>>((const V*)in, (V*)out, pb)
+        if (dtype == YAO_C64) {
+            switch (m) {
+            case 8: YAO_PERM_B1(float2, 1); break;
+            case 9: YAO_PERM_B1(float2, 2); break;
+            case 10: YAO_PERM_B1(float2, 4); break;
+            case 11: YAO_PERM_B1(float2, 8); break;
+            default: YAO_PERM_B1(float2, 16); break;
+            }
+        } else {
+            switch (m) {
+            case 8: YAO_PERM_B1(double2, 1); break;
+            case 9: YAO_PERM_B1(double2, 2); break;
+            case 10: YAO_PERM_B1(double2, 4); break;
+            case 11: YAO_PERM_B1(double2, 8); break;
+            default: YAO_PERM_B1(double2, 16); break;
+            }
+        }
+#undef YAO_PERM_B1
+        prof_end(pi, 2.0 * (double)((uint64_t(1) << n) * B) * es, 0.0);
+        YAO_HIP(hipGetLastError());
+        return 0;
+    }
     pa.tab = (const PermTables*)ring_upload(&tab, sizeof(tab));
     if (!pa.tab) return YAO_ENOMEM;
     const uint64_t blocks = uint64_t(1) << pa.nrest;
