@@ -145,3 +145,34 @@ def test_compiled_reverse_sweep_matches_oracle(kind, n, d, dtype):
         # The state keeps the forward sweep's output (the reverse sweep runs on its own copy).
         want = oracle.forward(c, params, w.zero_state(n))
         assert np.abs(s.download() - want).max() <= tol(dtype, len(c.gates))
+
+
+def test_compiled_passes_inside_batch_units():
+    """Circuits whose programs were compiled before a batch is recorded run their compiled
+    passes inside the batch graph, over a unit of same-structure circuits (grid z, each circuit
+    its own state and records): energies, gradients and output states against the oracle."""
+    yb.set_options(jit=1, autotune=0, fuse_width=0)
+    c = w.hea_circuit(13, 2)
+    H = w.heisenberg(13)
+    circs = [yb.Circuit.from_workload(c) for _ in range(3)]
+    hams = [yb.PauliSum.from_workload(H) for _ in range(3)]
+    states = [yb.State(13, 1, 0) for _ in range(3)]
+    params = [w.angles(1300 + i, c.nparams) for i in range(3)]
+    # Compile every circuit's forward and reverse programs through the eager path first.
+    for i in range(3):
+        yb.backward(states[i], circs[i], params[i], hams[i])
+    st0 = yb.jit_stats()
+    e, g = yb.batch_run(states, circs, params, hams)
+    st1 = yb.jit_stats()
+    # The graph was recorded with the compiled kernels (counted when recorded).
+    assert st1["fwd_launches"] > st0["fwd_launches"] and st1["bwd_launches"] > st0["bwd_launches"]
+    for rep in range(2):
+        if rep:
+            params = [w.angles(1400 + i, c.nparams) for i in range(3)]
+            e, g = yb.batch_run(states, circs, params, hams)
+        for i in range(3):
+            e_ref, g_ref, _ = oracle.adjoint(H, c, params[i], w.zero_state(13))
+            assert abs(e[i] - e_ref[0]) <= 1e-5, (rep, i)
+            assert np.abs(g[i] - g_ref[0]).max() <= 1e-4 * max(1.0, float(np.abs(g_ref[0]).max())), (rep, i)
+            want = oracle.forward(c, params[i], w.zero_state(13))
+            assert np.abs(states[i].download() - want).max() <= tol(0, len(c.gates)), (rep, i)
