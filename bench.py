@@ -369,7 +369,7 @@ def profile_family(yb, fam):
 
 
 CASES = ("step20", "step20_b64", "rx25_c128", "rx25_c64", "fwd25_c128", "fwd25_c64", "w5mfma30_c64",
-         "qft25_c128", "perm25_c128", "measure24_c128", "copy1g", "c4batch")
+         "qft25_c128", "qft25_c64", "perm25_c128", "measure24_c128", "copy1g", "c4batch")
 
 
 def run_case(name, reps):
@@ -431,8 +431,8 @@ def run_case(name, reps):
         def f():
             s.reset()
             yb.forward(s, cc, [])
-    elif name == "qft25_c128":
-        s = yb.State(25, 1, yb.C128)
+    elif name.startswith("qft25"):
+        s = yb.State(25, 1, yb.C128 if name.endswith("c128") else yb.C64)
         f = lambda: yb.qft(s, list(range(25)))
     elif name == "perm25_c128":
         s, t = yb.State(25, 1, yb.C128), yb.State(25, 1, yb.C128)

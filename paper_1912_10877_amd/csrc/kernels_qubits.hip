@@ -14,9 +14,11 @@
 //    the value of the sub-index bits below j (already y bits). No bit reversal is needed: the
 //    output comes out in natural order. The inverse runs the stages backwards with the inverse
 //    butterflies. A pass takes up to t consecutive stages: its tile holds their qubits plus the
-//    lowest other index bits (for contiguous rows), and every stage of the pass runs in LDS.
+//    lowest other index bits (for contiguous rows). Batched states run every stage of a pass
+//    in LDS (k_qft_pass); single-slot states of >= 10 qubits run them in registers, a few
+//    stages per round, with LDS only to move the tile between rounds (k_qft_b1).
 //
-// The batch stays innermost in both kernels: a tile row is B contiguous slots.
+// The batch stays innermost in every kernel: a tile row is B contiguous slots.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -246,6 +248,248 @@ __global__ __launch_bounds__(kQThreads) void k_qft_pass(vec2_t<R>* __restrict__ 
     }
 }
 
+// ------------------------------------------------------------------ QFT passes, one-slot states
+// A tile of 2^m rows (m = 10..12) held as 2^RR elements per thread (RR = m - 8, 256 threads).
+// A layout assigns RR tile row bits to the register index and the other 8 to the thread index
+// (ascending; the lowest 6 are the lanes). A round takes r <= RR consecutive stages whose rows
+// are register bits 0..r-1 (the others are fillers), so its butterflies run in registers; the
+// tile moves to the next round's layout through LDS, real parts first, then imaginary parts,
+// so a workgroup holds half a tile of LDS (16 KiB). The tile's lowest rows are the lowest
+// index bits, 256 contiguous bytes; the global load and store use the first and last round's
+// layouts when those keep these rows on lanes, else a layout of memory order plus one more
+// exchange.
+//
+// Exchange slots: for the writing layout A and the reading layout B, LDS slot = (row bits
+// outside A's lanes, compressed) * 64 + P(row) with P a linear map onto 6 bits that sends A's
+// lane rows to the lane numbers and B's lane rows outside A's lanes to the lane numbers of A's
+// lane rows outside B's lanes. Both sides' 64 lanes then hit 64 distinct slots modulo 64, and
+// slot(row) is linear in the row's bits, so a thread's slots are its thread part XOR a
+// register part, from per-bit tables.
+//
+// Twiddles: in a round whose register bit 0 is global stage J, the y bits below J that a pair's
+// twiddle needs are fixed per thread and filler group (M: the block's, the thread rows' and
+// the filler rows' sub-index bits below J); the stage J + p twiddle is
+// exp(i pi M / 2^{J+p}) * exp(i pi c / 2^p), c the pair's register bits below p. The first
+// factor for p = r - 1 comes from four table lookups (roots of unity at 12, 24, 36 and 40 bits
+// of pi M / 2^{J+r-1}), the others by squaring; the second is one of eight constants.
+// The 2^{-1/2} per stage is one 2^{-nst/2} at the store.
+constexpr int kQftB1MaxRounds = 6;
+constexpr int kQftB1MaxEx = 7;
+constexpr int kQftB1MaxStages = 12;
+constexpr int kQftTwEntries = 3 * 4096 + 16;
+
+struct QftExchange {
+    uint16_t wth[8], wrg[16];  // LDS slot parts of the writing layout's thread bits / register index
+    uint16_t rth[8], rrg[16];  // the same for the reading layout
+};
+
+struct QftRound {
+    uint64_t tsub[8];  // per thread bit: the sub-index bit (below J) its row carries, else 0
+    double2 fill[3];   // per filler bit: exp(i pi 2^s / 2^{J+r-1}) for its row's sub-index bit s
+                       // below J, else 1
+    int J, r;          // global stage of register bit 0; stages in the round
+};
+
+struct QftArgsB1 {
+    uint64_t ld_th[8], ld_rg[16];  // state index bits of the first layout's thread bits / register index
+    uint64_t st_th[8], st_rg[16];  // the same for the last layout
+    int8_t rpos[kMaxIndexBits];    // state index bit of block index bit j
+    int8_t rsub[kMaxIndexBits];    // sub-index bit (below the pass) of block index bit j, else -1
+    QftRound rd[kQftB1MaxRounds];
+    QftExchange x[kQftB1MaxEx];
+    double scale;
+    int nrest, nrounds, load_ex, store_ex;
+};
+static_assert(sizeof(QftArgsB1) + 24 <= 4096, "kernel arguments must fit the 4 KiB argument segment");
+
+__device__ __forceinline__ double2 cmul_d(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// w * exp(i pi e / 8), e = 0..7, in the state's real type.
+template <typename R, int E>
+__device__ __forceinline__ vec2_t<R> rot8(vec2_t<R> w)
+{
+    constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, h = 0.70710678118654752440;
+    constexpr double cs[8] = {1.0, c1, h, s1, 0.0, -s1, -h, -c1};
+    constexpr double sn[8] = {0.0, s1, h, c1, 1.0, c1, h, s1};
+    vec2_t<R> o;
+    if constexpr (E == 0) {
+        o = w;
+    } else if constexpr (E == 4) {
+        o.x = -w.y;
+        o.y = w.x;
+    } else {
+        const R c = (R)cs[E], s = (R)sn[E];
+        o.x = c * w.x - s * w.y;
+        o.y = c * w.y + s * w.x;
+    }
+    return o;
+}
+
+// The twiddle of register pair (i, i | 2^P) in a round of r stages: base[g] * exp(i pi c / 2^P).
+template <typename R, int P, int I>
+__device__ __forceinline__ vec2_t<R> pair_twiddle(vec2_t<R> base)
+{
+    constexpr int c = I & ((1 << P) - 1);
+    return rot8<R, (c << (3 - P)) & 7>(base);
+}
+
+template <typename R, bool INV, int NE, int P, int r, int I>
+__device__ __forceinline__ void qft_pairs(vec2_t<R> (&v)[NE], const vec2_t<R> (&wb)[NE >> r][r])
+{
+    if constexpr (I < NE) {
+        if constexpr (!((I >> P) & 1)) {
+            const vec2_t<R> w = pair_twiddle<R, P, I>(wb[I >> r][P]);
+            const vec2_t<R> x0 = v[I], x1 = v[I | (1 << P)];
+            if (!INV) {
+                const R wr = w.x * x1.x - w.y * x1.y, wi = w.x * x1.y + w.y * x1.x;
+                v[I].x = x0.x + wr;
+                v[I].y = x0.y + wi;
+                v[I | (1 << P)].x = x0.x - wr;
+                v[I | (1 << P)].y = x0.y - wi;
+            } else {
+                const R dr = x0.x - x1.x, di = x0.y - x1.y;
+                v[I].x = x0.x + x1.x;
+                v[I].y = x0.y + x1.y;
+                v[I | (1 << P)].x = w.x * dr + w.y * di;
+                v[I | (1 << P)].y = w.x * di - w.y * dr;
+            }
+        }
+        qft_pairs<R, INV, NE, P, r, I + 1>(v, wb);
+    }
+}
+
+template <typename R, bool INV, int NE, int r, int S>
+__device__ __forceinline__ void qft_stages(vec2_t<R> (&v)[NE], const vec2_t<R> (&wb)[NE >> r][r])
+{
+    if constexpr (S < r) {
+        qft_pairs<R, INV, NE, INV ? r - 1 - S : S, r, 0>(v, wb);
+        qft_stages<R, INV, NE, r, S + 1>(v, wb);
+    }
+}
+
+template <typename R, bool INV, int NE, int r>
+__device__ __forceinline__ void qft_round(vec2_t<R> (&v)[NE], const double2* __restrict__ tw, uint64_t mt,
+                                          const QftRound& rd)
+{
+    constexpr int NG = NE >> r;
+    // Filler group g = 0 from the table; group g from the group without its top bit times that
+    // filler bit's factor; every group's stage p < r - 1 by squaring.
+    double2 w[NG];
+    const uint64_t f = mt << (40 - (rd.J + r - 1));
+    w[0] = cmul_d(cmul_d(tw[f >> 28], tw[4096 + ((f >> 16) & 4095)]),
+                  cmul_d(tw[8192 + ((f >> 4) & 4095)], tw[12288 + (f & 15)]));
+#pragma unroll
+    for (int g = 1; g < NG; ++g) {
+        const int top = 31 - __builtin_clz(g);
+        w[g] = cmul_d(w[g ^ (1 << top)], rd.fill[top]);
+    }
+    vec2_t<R> wb[NG][r];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        double2 x = w[g];
+#pragma unroll
+        for (int p = r - 1; p >= 0; --p) {
+            wb[g][p].x = (R)x.x;
+            wb[g][p].y = (R)x.y;
+            if (p > 0) x = cmul_d(x, x);
+        }
+    }
+    qft_stages<R, INV, NE, r, 0>(v, wb);
+}
+
+// Moves a thread's elements from layout A to layout B through `tile` (2^m reals); waits first
+// for the readers of an earlier exchange when there was one.
+template <typename R, int NE>
+__device__ __forceinline__ void qft_exchange(R* tile, vec2_t<R> (&v)[NE], const QftExchange& X, int t, bool wait_readers)
+{
+    if (wait_readers) __syncthreads();
+    int ws = 0, rs = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if ((t >> b) & 1) {
+            ws ^= X.wth[b];
+            rs ^= X.rth[b];
+        }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) tile[ws ^ X.wrg[i]] = v[i].x;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NE; ++i) v[i].x = tile[rs ^ X.rrg[i]];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NE; ++i) tile[ws ^ X.wrg[i]] = v[i].y;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NE; ++i) v[i].y = tile[rs ^ X.rrg[i]];
+}
+
+template <typename R, bool INV, int RR>
+__global__ __launch_bounds__(kQThreads) void k_qft_b1(vec2_t<R>* __restrict__ psi, const double2* __restrict__ tw,
+                                                     QftArgsB1 q)
+{
+    using V = vec2_t<R>;
+    constexpr int NE = 1 << RR;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    R* tile = reinterpret_cast<R*>(lds_raw);
+    const int t = threadIdx.x;
+    const uint64_t blk = blockIdx.x;
+    uint64_t base = 0, sub_base = 0;
+    for (int j = 0; j < q.nrest; ++j)
+        if ((blk >> j) & 1) {
+            base |= uint64_t(1) << q.rpos[j];
+            if (q.rsub[j] >= 0) sub_base |= uint64_t(1) << q.rsub[j];
+        }
+    V v[NE];
+    {
+        uint64_t it = base;
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            if ((t >> b) & 1) it |= q.ld_th[b];
+#pragma unroll
+        for (int i = 0; i < NE; ++i) v[i] = psi[it | q.ld_rg[i]];
+    }
+    int x = 0;
+    if (q.load_ex) {
+        qft_exchange<R, NE>(tile, v, q.x[0], t, false);
+        x = 1;
+    }
+    for (int k = 0; k < q.nrounds; ++k) {
+        if (k > 0) {
+            qft_exchange<R, NE>(tile, v, q.x[x], t, x > 0);
+            ++x;
+        }
+        const QftRound& rd = q.rd[k];
+        uint64_t mt = sub_base;
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            if ((t >> b) & 1) mt |= rd.tsub[b];
+        if constexpr (RR >= 4) {
+            if (rd.r == 4) qft_round<R, INV, NE, 4>(v, tw, mt, rd);
+        }
+        if constexpr (RR >= 3) {
+            if (rd.r == 3) qft_round<R, INV, NE, 3>(v, tw, mt, rd);
+        }
+        if (rd.r == 2) qft_round<R, INV, NE, 2>(v, tw, mt, rd);
+        if (rd.r == 1) qft_round<R, INV, NE, 1>(v, tw, mt, rd);
+    }
+    if (q.store_ex) qft_exchange<R, NE>(tile, v, q.x[x], t, x > 0);
+    const R sc = (R)q.scale;
+    uint64_t ot = base;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if ((t >> b) & 1) ot |= q.st_th[b];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        V o;
+        o.x = v[i].x * sc;
+        o.y = v[i].y * sc;
+        psi[ot | q.st_rg[i]] = o;
+    }
+}
+
 // Lowest `c` index bits make rows of >= 128 contiguous bytes together with the batch.
 int contiguity_bits(int B, int elem_bytes, int n)
 {
@@ -285,17 +529,15 @@ void split_bits(int n, uint64_t mask, std::vector<int>& tpos, std::vector<int>& 
     for (int b = 0; b < n; ++b) ((mask >> b) & 1 ? tpos : rpos).push_back(b);
 }
 
-// QFT passes: runs of consecutive stages whose qubits, with the lowest c index bits, fit the
-// tile budget (at most kMaxStages stages).
-std::vector<std::pair<int, int>> qft_pass_list(int n, int B, int es, const int* locs, int k)
+// QFT passes: runs of consecutive stages (at most max_stages) whose qubits, with the lowest c
+// index bits, fit a tile of `budget` bits.
+std::vector<std::pair<int, int>> stage_runs(int c, int budget, int max_stages, const int* locs, int k)
 {
-    const int c = contiguity_bits(B, es, n);
-    const int budget = std::max(tile_budget_bits(B, es), std::min(n, c + 1));
     std::vector<std::pair<int, int>> passes;
     for (int j0 = 0; j0 < k;) {
         int j1 = j0;
         uint64_t smask = 0;
-        while (j1 < k && j1 - j0 < kMaxStages) {
+        while (j1 < k && j1 - j0 < max_stages) {
             const uint64_t s2 = smask | (uint64_t(1) << locs[j1]);
             uint64_t t2 = s2;
             for (int b = 0; b < c; ++b) t2 |= uint64_t(1) << b;
@@ -307,6 +549,112 @@ std::vector<std::pair<int, int>> qft_pass_list(int n, int B, int es, const int* 
         j0 = j1;
     }
     return passes;
+}
+
+std::vector<std::pair<int, int>> qft_pass_list(int n, int B, int es, const int* locs, int k)
+{
+    const int c = contiguity_bits(B, es, n);
+    return stage_runs(c, std::max(tile_budget_bits(B, es), std::min(n, c + 1)), kMaxStages, locs, k);
+}
+
+// Single-slot states of >= 10 qubits take k_qft_b1: tiles of 32 KiB of state (2^12 complex64
+// or 2^11 complex128 rows; half of that in LDS), up to 12 stages per pass.
+bool qft_b1_path(int n, int B)
+{
+    return B == 1 && n >= 10;
+}
+
+int qft_b1_tile_bits(int n, int es)
+{
+    return std::min(n, es == 8 ? 12 : 11);
+}
+
+// Lowest index bits of a one-slot QFT tile: 256 contiguous bytes.
+int qft_b1_contig(int n, int es)
+{
+    return std::min(n, contiguity_bits(1, es, n) + 1);
+}
+
+std::vector<std::pair<int, int>> qft_pass_list_b1(int n, int es, const int* locs, int k)
+{
+    return stage_runs(qft_b1_contig(n, es), qft_b1_tile_bits(n, es), kQftB1MaxStages, locs, k);
+}
+
+// Roots of unity of the one-slot QFT kernel: exp(i pi a / 2^12), exp(i pi a / 2^24) and
+// exp(i pi a / 2^36) for a < 4096, then exp(i pi a / 2^40) for a < 16, rounded from long
+// double. Filled once into its own workspace slot.
+const double2* qft_twiddles()
+{
+    static const void* filled = nullptr;
+    void* d = workspace(WS_QFTTW, sizeof(double2) * kQftTwEntries);
+    if (!d) return nullptr;
+    if (d != filled) {
+        if (recording()) {
+            set_error(YAO_EINVAL, "QFT root table first filled while a graph is being recorded");
+            return nullptr;
+        }
+        std::vector<double> h(2 * (size_t)kQftTwEntries);
+        const long double pi = 3.14159265358979323846264338327950288L;
+        const int bits[4] = {12, 24, 36, 40};
+        for (int t = 0; t < 4; ++t)
+            for (int a = 0; a < (t < 3 ? 4096 : 16); ++a) {
+                const long double ang = pi * ldexpl((long double)a, -bits[t]);
+                h[2 * (4096 * t + a)] = (double)cosl(ang);
+                h[2 * (4096 * t + a) + 1] = (double)sinl(ang);
+            }
+        if (hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, stream()) != hipSuccess ||
+            hipStreamSynchronize(stream()) != hipSuccess) {
+            set_error(YAO_EHIP, "QFT root table upload failed");
+            return nullptr;
+        }
+        filled = d;
+    }
+    return (const double2*)d;
+}
+
+// A layout of a tile of m rows: register index bit q <-> row rg[q] (RR bits), thread index bit
+// b <-> row th[b] (8 bits; the lanes are b < 6).
+struct QftLayout {
+    int th[8];
+    int rg[4];
+};
+
+// LDS slots of one exchange from layout a (writes) to layout b (reads); see k_qft_b1.
+QftExchange make_exchange(const QftLayout& a, const QftLayout& b, int m, int RR)
+{
+    uint32_t pv[kMaxTileBits] = {};
+    int lane_a[kMaxTileBits];
+    bool in_lb[kMaxTileBits] = {};
+    for (int t = 0; t < m; ++t) lane_a[t] = -1;
+    for (int i = 0; i < 6; ++i) {
+        lane_a[a.th[i]] = i;
+        in_lb[b.th[i]] = true;
+    }
+    int free_lanes[6], nfree = 0;
+    for (int i = 0; i < 6; ++i)
+        if (!in_lb[a.th[i]]) free_lanes[nfree++] = i;
+    int used = 0, rank = 0;
+    for (int t = 0; t < m; ++t) {
+        if (lane_a[t] >= 0) {
+            pv[t] = 1u << lane_a[t];
+            continue;
+        }
+        pv[t] = 1u << (6 + rank++);
+        if (in_lb[t]) pv[t] |= 1u << free_lanes[used++];
+    }
+    QftExchange x;
+    memset(&x, 0, sizeof(x));
+    for (int i = 0; i < 8; ++i) {
+        x.wth[i] = (uint16_t)pv[a.th[i]];
+        x.rth[i] = (uint16_t)pv[b.th[i]];
+    }
+    for (int i = 0; i < (1 << RR); ++i)
+        for (int q = 0; q < RR; ++q)
+            if ((i >> q) & 1) {
+                x.wrg[i] ^= (uint16_t)pv[a.rg[q]];
+                x.rrg[i] ^= (uint16_t)pv[b.rg[q]];
+            }
+    return x;
 }
 
 }  // namespace
@@ -404,10 +752,158 @@ int launch_permute(const void* in, void* out, int dtype, int n, int B, const int
     return 0;
 }
 
+namespace {
+
+// One-slot QFT passes (k_qft_b1); see the kernel for the layouts, exchanges and twiddles.
+int launch_qft_b1(void* data, int dtype, int n, const int* locs, int k, bool inverse)
+{
+    const int es = dtype == YAO_C64 ? 8 : 16;
+    const int c = qft_b1_contig(n, es);
+    const int mt = qft_b1_tile_bits(n, es);
+    int sub_of_bit[kMaxIndexBits];
+    for (int b = 0; b < n; ++b) sub_of_bit[b] = -1;
+    for (int j = 0; j < k; ++j) sub_of_bit[locs[j]] = j;
+    std::vector<std::pair<int, int>> passes = qft_pass_list_b1(n, es, locs, k);
+    if (inverse) std::reverse(passes.begin(), passes.end());
+    const double2* tw = qft_twiddles();
+    if (!tw) return YAO_EHIP;
+    const double elems = (double)(uint64_t(1) << n);
+    for (const auto& ps : passes) {
+        const int j0 = ps.first, j1 = ps.second, nst = j1 - j0;
+        // Tile: the stage qubits and the lowest c bits, then bits that carry no sub-index bit
+        // below j0 (no twiddle depends on them), then the lowest others.
+        uint64_t mask = 0;
+        for (int j = j0; j < j1; ++j) mask |= uint64_t(1) << locs[j];
+        for (int b = 0; b < c; ++b) mask |= uint64_t(1) << b;
+        for (int b = 0; b < n && __builtin_popcountll(mask) < mt; ++b)
+            if (sub_of_bit[b] < 0 || sub_of_bit[b] >= j0) mask |= uint64_t(1) << b;
+        for (int b = 0; b < n && __builtin_popcountll(mask) < mt; ++b) mask |= uint64_t(1) << b;
+        std::vector<int> tpos, rpos;
+        split_bits(n, mask, tpos, rpos);
+        const int m = (int)tpos.size(), RR = m - 8;
+        if (RR < 2 || RR > 4) return set_error(YAO_EINVAL, "QFT tile of %d bits", m);
+        int row_sub[kMaxTileBits], stage_row[kQftB1MaxStages];
+        for (int t = 0; t < m; ++t) {
+            row_sub[t] = sub_of_bit[tpos[t]];
+            if (row_sub[t] >= j0 && row_sub[t] < j1) stage_row[row_sub[t] - j0] = t;
+        }
+        QftArgsB1 q;
+        memset(&q, 0, sizeof(q));
+        q.nrest = (int)rpos.size();
+        for (int j = 0; j < q.nrest; ++j) {
+            q.rpos[j] = (int8_t)rpos[j];
+            const int sb = sub_of_bit[rpos[j]];
+            q.rsub[j] = (int8_t)(sb >= 0 && sb < j0 ? sb : -1);
+        }
+        // Rounds in execution order: runs of RR stages, ascending (forward) or descending.
+        std::vector<QftLayout> lay;
+        std::vector<int> seq;
+        for (int st = 0; st < nst; ++st) seq.push_back(inverse ? nst - 1 - st : st);
+        const int nrounds = (nst + RR - 1) / RR;
+        if (nrounds > kQftB1MaxRounds) return set_error(YAO_EINVAL, "QFT pass of %d rounds", nrounds);
+        for (int rk = 0; rk < nrounds; ++rk) {
+            const int a = rk * RR, e = std::min(nst, a + RR);
+            int st0 = seq[a];
+            for (int i = a; i < e; ++i) st0 = std::min(st0, seq[i]);
+            const int r = e - a;
+            QftLayout L;
+            bool used[kMaxTileBits] = {};
+            for (int p = 0; p < r; ++p) {
+                L.rg[p] = stage_row[st0 + p];
+                used[L.rg[p]] = true;
+            }
+            for (int p = r, t = m - 1; p < RR; ++p) {  // fillers: the highest other rows
+                while (used[t]) --t;
+                L.rg[p] = t;
+                used[t] = true;
+            }
+            for (int t = 0, b = 0; t < m; ++t)
+                if (!used[t]) L.th[b++] = t;
+            QftRound& rd = q.rd[rk];
+            rd.J = j0 + st0;
+            rd.r = r;
+            auto below = [&](int row) -> uint64_t {
+                const int sb = row_sub[row];
+                return sb >= 0 && sb < rd.J ? uint64_t(1) << sb : 0;
+            };
+            for (int b = 0; b < 8; ++b) rd.tsub[b] = below(L.th[b]);
+            for (int qb = 0; qb < 3; ++qb) {
+                rd.fill[qb] = make_double2(1.0, 0.0);
+                const int sb = qb < RR - r ? row_sub[L.rg[r + qb]] : -1;
+                if (sb >= 0 && sb < rd.J) {
+                    const long double ang = 3.14159265358979323846264338327950288L * ldexpl(1.0L, sb - (rd.J + r - 1));
+                    rd.fill[qb] = make_double2((double)cosl(ang), (double)sinl(ang));
+                }
+            }
+            lay.push_back(L);
+        }
+        q.nrounds = nrounds;
+        // Global access in memory order (lanes on rows 0..5) unless the first / last round
+        // already keeps the c contiguous rows on lanes.
+        QftLayout mem;
+        for (int b = 0; b < 8; ++b) mem.th[b] = b;
+        for (int p = 0; p < RR; ++p) mem.rg[p] = 8 + p;
+        auto lanes_contiguous = [&](const QftLayout& L) {
+            for (int p = 0; p < RR; ++p)
+                if (L.rg[p] < c) return false;
+            return true;
+        };
+        q.load_ex = !lanes_contiguous(lay.front());
+        q.store_ex = !lanes_contiguous(lay.back());
+        if (q.load_ex) lay.insert(lay.begin(), mem);
+        if (q.store_ex) lay.push_back(mem);
+        if ((int)lay.size() - 1 > kQftB1MaxEx) return set_error(YAO_EINVAL, "QFT pass of %d exchanges", (int)lay.size() - 1);
+        for (size_t i = 0; i + 1 < lay.size(); ++i) q.x[i] = make_exchange(lay[i], lay[i + 1], m, RR);
+        const QftLayout &lf = lay.front(), &ll = lay.back();
+        for (int b = 0; b < 8; ++b) {
+            q.ld_th[b] = uint64_t(1) << tpos[lf.th[b]];
+            q.st_th[b] = uint64_t(1) << tpos[ll.th[b]];
+        }
+        for (int i = 0; i < (1 << RR); ++i)
+            for (int p = 0; p < RR; ++p)
+                if ((i >> p) & 1) {
+                    q.ld_rg[i] |= uint64_t(1) << tpos[lf.rg[p]];
+                    q.st_rg[i] |= uint64_t(1) << tpos[ll.rg[p]];
+                }
+        q.scale = std::pow(2.0, -0.5 * nst);
+        const uint64_t blocks = uint64_t(1) << q.nrest;
+        if (blocks > 0x7fffffffull) return set_error(YAO_EINVAL, "QFT grid too large");
+        const size_t lds = ((size_t)1 << m) * es / 2;
+        const int pi = prof_begin(YAO_KF_QFT);
+#define YAO_QFT_B1(R, INV, RRv)                                                                \
+    do {                                                                                      \
+        const void* kf = reinterpret_cast<const void*>(&k_qft_b1<R, INV, RRv>);              \
+        k_qft_b1<R, INV, RRv><<<(unsigned)blocks, kQThreads, lds, stream()>>>( \
+            (vec2_t<R>*)data, tw, q);                                                        \
+    } while (0)
+#define YAO_QFT_B1_RR(R, INV)          \
+    do {                               \
+        if (RR == 2) YAO_QFT_B1(R, INV, 2); \
+        else if (RR == 3) YAO_QFT_B1(R, INV, 3); \
+        else YAO_QFT_B1(R, INV, 4);    \
+    } while (0)
+        if (dtype == YAO_C64) {
+            if (inverse) YAO_QFT_B1_RR(float, true);
+            else YAO_QFT_B1_RR(float, false);
+        } else {
+            if (inverse) YAO_QFT_B1_RR(double, true);
+            else YAO_QFT_B1_RR(double, false);
+        }
+#undef YAO_QFT_B1_RR
+#undef YAO_QFT_B1
+        prof_end(pi, 2.0 * elems * es, 5.0 * nst * elems);
+        YAO_HIP(hipGetLastError());
+    }
+    return 0;
+}
+
+}  // namespace
+
 int launch_qft(void* data, int dtype, int n, int B, const int* locs, int k, bool inverse)
 {
     const int es = dtype == YAO_C64 ? 8 : 16;
     if (n > kMaxIndexBits) return set_error(YAO_EINVAL, "too many qubits for the QFT kernel");
+    if (qft_b1_path(n, B)) return launch_qft_b1(data, dtype, n, locs, k, inverse);
     const int c = contiguity_bits(B, es, n);
     const int budget = std::max(tile_budget_bits(B, es), std::min(n, c + 1));
     int sub_of_bit[kMaxIndexBits];
@@ -492,7 +988,9 @@ int launch_qft(void* data, int dtype, int n, int B, const int* locs, int k, bool
 
 int qft_passes(int dtype, int n, int B, const int* locs, int k)
 {
-    return (int)qft_pass_list(n, B, dtype == YAO_C64 ? 8 : 16, locs, k).size();
+    const int es = dtype == YAO_C64 ? 8 : 16;
+    if (qft_b1_path(n, B)) return (int)qft_pass_list_b1(n, es, locs, k).size();
+    return (int)qft_pass_list(n, B, es, locs, k).size();
 }
 
 }  // namespace yao

@@ -43,6 +43,7 @@ enum WsSlot {
     WS_MEAS,        // outcome probabilities, cumulative sums and sampled outcomes
     WS_KRYLOV,      // Krylov vectors of the time evolution
     WS_SHIFT,       // the shifted-circuit register of the faithful gradient
+    WS_QFTTW,       // the QFT's table of roots of unity (filled once)
     WS_COUNT
 };
 void* workspace(int slot, size_t bytes);

@@ -69,6 +69,10 @@ def test_focus_qft_relax_listing(dtype):
     (3, 1, [0, 1, 2]), (8, 1, list(range(8))), (12, 1, list(range(12))), (14, 3, [13, 2, 7, 0, 9, 4]),
     (15, 1, list(range(15))), (11, 5, [10, 9, 8, 7, 6, 5, 4, 3, 2, 1, 0]), (9, 64, [1, 3, 5, 7]),
     (13, 2, [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12]),
+    # single-slot states of >= 10 qubits (the register-radix passes): scattered, reversed and
+    # partial qubit sets, so that tiles take code rows, free rows and filler rows
+    (14, 1, [13, 2, 7, 0, 9, 4]), (13, 1, list(range(12, -1, -1))), (10, 1, [9, 0, 5]),
+    (18, 1, [17, 3, 11, 0, 5, 9, 14, 1, 7, 12]), (16, 1, [4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 0, 1]),
 ])
 def test_qft_matches_oracle(dtype, n, B, locs):
     psi = w.random_state(n, B, n + B)
