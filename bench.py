@@ -303,10 +303,13 @@ def bench_next_rows(yb, w, torch):
         out[f"f4_permute_25q_{name}"] = {"ms": round(pms, 3), **pprof}
         log(f"next row f4 QFT and permutation (25 qubits, {name}) done")
         if dt == yb.C128:
-            out["f4_qft_25q_c128"]["traffic_per_launch"] = measured_traffic("k_qft_pass<double, false>",
-                                                                            "k_qft_pass_qft25_c128.txt")
+            out["f4_qft_25q_c128"]["traffic_per_launch"] = measured_traffic("k_qft_b1<double, false, 3>",
+                                                                            "k_qft_b1_qft25_c128.txt")
             out["f4_permute_25q_c128"]["traffic_per_launch"] = measured_traffic(
-                "k_permute<HIP_vector_type<double, 2u> >", "k_permute_perm25_c128.txt")
+                "k_permute_b1<HIP_vector_type<double, 2u>, 8>", "k_permute_b1_perm25_c128.txt")
+        else:
+            out["f4_qft_25q_c64"]["traffic_per_launch"] = measured_traffic("k_qft_b1<float, false, 4>",
+                                                                           "k_qft_b1_qft25_c64.txt")
         if dt == yb.C128:
             qc = yb.Circuit.from_workload(w.qft_circuit(n))
             out["f4_qft_25q_c128"]["gate_circuit_ms"] = round(timed(lambda: yb.forward(s, qc, []), 2), 3)
