@@ -328,6 +328,49 @@ std::string gen_backward_pass(const Plan& P, const Program& prog, int p, int n, 
         o << "    lp[swz(th + " << r * nthr << "u)] = v" << r << "; ll[swz(th + " << r * nthr << "u)] = w" << r << ";\n";
     o << "  }\n  __syncthreads();\n";
     o << "  double phr = 1.0, phi = 0.0;\n";
+    // Matrix entries each op reads (cls 0: u0, u5; cls 1: u3, u7 and the phase's u0, u4;
+    // swaps none; generic: all eight). They come through the scalar cache a batch ahead:
+    // batches of up to 8 consecutive ops (at most 16 entries); at the first op of batch b the
+    // kernel waits for batch b's loads and issues batch b + 1's, so records that miss the
+    // scalar cache are fetched while batch b computes. The loads are volatile so that the
+    // compiler keeps them where they are issued instead of next to their uses.
+    std::vector<std::pair<int, int>> seq;  // (group, op within group) in pass order
+    for (int g = 0; g < ng; ++g)
+        for (int i = 0; i < prog.groups[g0 + g].nops; ++i) seq.push_back({g, i});
+    auto coeffs = [&](int oi) -> std::vector<int> {
+        const int cls = prog.ops[prog.pass_op0[p] + oi].var / RB;
+        if (cls == 0) return {0, 5};
+        if (cls == 1) return {3, 7, 0, 4};
+        if (cls == 2) return {};
+        return {0, 1, 2, 3, 4, 5, 6, 7};
+    };
+    auto op_index = [&](size_t i) { return prog.groups[g0 + seq[i].first].op0 + seq[i].second; };
+    std::vector<size_t> batch_first;  // first op (in seq) of each batch
+    {
+        int cnt = 0, ent = 0;
+        for (size_t i = 0; i < seq.size(); ++i) {
+            const int c = (int)coeffs(op_index(i)).size();
+            if (batch_first.empty() || cnt == 8 || ent + c > 16) {
+                batch_first.push_back(i);
+                cnt = 0;
+                ent = 0;
+            }
+            ++cnt;
+            ent += c;
+        }
+        batch_first.push_back(seq.size());
+    }
+    auto emit_loads = [&](size_t b) {
+        if (b + 1 >= batch_first.size()) return;
+        for (size_t i = batch_first[b]; i < batch_first[b + 1]; ++i)
+            for (int k : coeffs(op_index(i)))
+                o << "    U" << i << "_" << k << " = ((const volatile CST double*)(ops + "
+                  << (size_t)op_index(i) * sizeof(POp) + offsetof(POp, u) << "))[" << k << "];\n";
+    };
+    for (size_t i = 0; i < seq.size(); ++i)
+        for (int k : coeffs(op_index(i))) o << "  double U" << i << "_" << k << ";\n";
+    size_t si = 0, bi = 0;
+    emit_loads(0);
     int buf = 0;
     for (int g = 0; g < ng; ++g) {
         const PGroupDesc& G = prog.groups[g0 + g];
@@ -369,9 +412,16 @@ std::string gen_backward_pass(const Plan& P, const Program& prog, int p, int n, 
             const bool lane_pred = (cls == 2 || generic) && tm != 0;
             const bool cond = lane_pred || outer;
             // Reverse ops read their matrices through the scalar cache (in LDS they would occupy
-            // VGPRs, and the reverse kernel has none to spare).
-            o << "    {\n      const CST double* u = (const CST double*)(ops + " << (size_t)oi * sizeof(POp) + offsetof(POp, u)
-              << ");\n";
+            // VGPRs, and the reverse kernel has none to spare), prefetched one op ahead.
+            if (si == batch_first[bi]) {
+                o << "    __builtin_amdgcn_s_waitcnt(0xC07F);\n    __builtin_amdgcn_sched_barrier(0);\n";
+                emit_loads(++bi);
+                o << "    __builtin_amdgcn_sched_barrier(0);\n";
+            }
+            const size_t cur = si++;
+            std::ostringstream enclosing;
+            std::swap(o, enclosing);  // the op's code goes to its own stream first
+            o << "    {\n";
             if (generic && op.slot >= 0 && op.gen == GEN_DENSE)
                 o << "      const CST double* gm = (const CST double*)mats + " << op.mat + 8 << ";\n";
             if (cond) {
@@ -434,6 +484,15 @@ std::string gen_backward_pass(const Plan& P, const Program& prog, int p, int n, 
             }
             if (cls == 1) o << "      { const double pr = phr * u[0] - phi * u[4]; phi = phr * u[4] + phi * u[0]; phr = pr; }\n";
             o << "    }\n";
+            // The op's u[k] are the prefetched U<cur>_k.
+            std::string body = o.str();
+            for (int k = 0; k < 8; ++k) {
+                const std::string from = "u[" + I(k) + "]", to = "U" + I((long long)cur) + "_" + I(k);
+                for (size_t pos = body.find(from); pos != std::string::npos; pos = body.find(from, pos + to.size()))
+                    body.replace(pos, from.size(), to);
+            }
+            std::swap(o, enclosing);
+            o << body;
         }
         if (nslot != G.nslot) return "";  // the record's slots and the group's list disagree
         for (int r = 0; r < N; ++r)
