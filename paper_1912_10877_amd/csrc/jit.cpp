@@ -277,9 +277,17 @@ std::string gen_backward_pass(const Plan& P, const Program& prog, int p, int n, 
         maxslots = std::max(maxslots, prog.groups[g0 + g].nslot);
     }
     const bool c64 = dtype == YAO_C64;
-    const int nthr = 1 << (t - RB), E = nthr >> 4;
+    const int nthr = 1 << (t - RB);
     const int lb = c64 ? 8 : 16;
-    const size_t lds = ((size_t)(16 + lb) << t) + sizeof(double) * 2 * (size_t)std::max(1, maxslots) * E;
+    // Gradient partials: each gradient is summed over lane pairs (one DPP step) and the pair sums
+    // go to LDS, E = nthr / 2 entries per gradient, two buffers of the group's gradients; when
+    // that does not fit, over rows of 16 lanes (E = nthr / 16).
+    auto lds_for = [&](int e) {
+        return ((size_t)(16 + lb) << t) + sizeof(double) * 2 * (size_t)std::max(1, maxslots) * e;
+    };
+    const int red_lanes = lds_for(nthr >> 1) <= 160 * 1024 ? 2 : 16;
+    const int E = nthr / red_lanes;
+    const size_t lds = lds_for(E);
     if (lds > 160 * 1024) return "";
     const std::string VL = c64 ? "float2" : "double2", RL = c64 ? "float" : "double";
     std::ostringstream o;
@@ -447,7 +455,10 @@ std::string gen_backward_pass(const Plan& P, const Program& prog, int p, int n, 
                     if (cond) o << "      g += pc ? " << e << " : 0.0;\n";
                     else o << "      g += " << e << ";\n";
                 }
-                o << "      g = row_sum16(g);\n      if ((th & 15u) == 0) red[" << nslot * E << " + (th >> 4)] = g;\n";
+                if (red_lanes == 2)
+                    o << "      g += dpp_f64<0xB1>(g);\n      if ((th & 1u) == 0) red[" << nslot * E << " + (th >> 1)] = g;\n";
+                else
+                    o << "      g = row_sum16(g);\n      if ((th & 15u) == 0) red[" << nslot * E << " + (th >> 4)] = g;\n";
                 ++nslot;
             }
             for (int a : pairs) {
