@@ -250,6 +250,15 @@ __device__ __forceinline__ double row_sum16(double v)
     v += dpp_f64<0x128>(v);
     return v;
 }
+// Exchanges two double2 registers in place (v_swap_b32 on each 32-bit half), so that a swap
+// under a lane mask needs neither selects nor copies where the lanes rejoin.
+__device__ __forceinline__ void swap_d2(double2& a, double2& b)
+{
+    unsigned* x = reinterpret_cast<unsigned*>(&a);
+    unsigned* y = reinterpret_cast<unsigned*>(&b);
+    asm volatile("v_swap_b32 %0, %1\n\tv_swap_b32 %2, %3\n\tv_swap_b32 %4, %5\n\tv_swap_b32 %6, %7"
+                 : "+v"(x[0]), "+v"(y[0]), "+v"(x[1]), "+v"(y[1]), "+v"(x[2]), "+v"(y[2]), "+v"(x[3]), "+v"(y[3]));
+}
 // 2 Re(conj(l) M p) for a dense 2 x 2 generator M (re[4], im[4], row-major).
 __device__ __forceinline__ double dense_grad(const CST double* m, double2 p0, double2 p1, double2 l0, double2 l1)
 {
@@ -468,9 +477,11 @@ std::string gen_backward_pass(const Plan& P, const Program& prog, int p, int n, 
                     if (!cond) {
                         std::swap(perm[a], perm[a | (1 << J)]);
                     } else {
-                        for (const auto& pr : {std::make_pair(X, Y), std::make_pair(LX, LY)})
-                            o << "      { const double2 p = " << pr.first << ", q = " << pr.second << "; " << pr.first
-                              << " = pc ? q : p; " << pr.second << " = pc ? p : q; }\n";
+                        // Swapped in place under the lane mask: one branch around the op's pairs,
+                        // no selects and no copies where the lanes rejoin.
+                        if (a == pairs.front()) o << "      if (pc) {\n";
+                        o << "        swap_d2(" << X << ", " << Y << "); swap_d2(" << LX << ", " << LY << ");\n";
+                        if (a == pairs.back()) o << "      }\n";
                     }
                     continue;
                 }
