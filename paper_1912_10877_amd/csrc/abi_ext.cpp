@@ -97,7 +97,7 @@ int measure_impl(yao_state* s, const int* locs, int k, int nshots, const double*
     YAO_TRY(launch_outcome_probs(s, locs, k, P));
     YAO_TRY(launch_cdf(P, C, k, B, tot));
     YAO_HIP(hipMemcpyAsync(du, u, sizeof(double) * shots, hipMemcpyHostToDevice, st));
-    YAO_TRY(launch_sample(C, k, B, nshots, du, dout));
+    YAO_TRY(launch_sample(C, tot, k, B, nshots, du, dout));
     if (collapse) {
         YAO_HIP(hipMemcpyAsync(dlocs, locs, sizeof(int) * k, hipMemcpyHostToDevice, st));
         YAO_TRY(launch_collapse(s, P, dlocs, locs, k, dout, dep, scale, dprob));

@@ -7,10 +7,12 @@
 //   1. probabilities P[b][x] of every outcome: |psi|^2 summed over the other qubits (the locs
 //      are first moved onto the lowest index bits by a qubit permutation unless they already
 //      are 0..k-1 in order);
-//   2. the cumulative sums C[b][x] = sum_{y <= x} P[b][y]: chunks of 2048 outcomes scanned in
-//      LDS, chunk totals scanned per slot, chunk offsets added;
+//   2. the cumulative sums C[b][x] = sum_{y <= x} P[b][y], held as chunks of 2048 outcomes
+//      scanned in LDS (Q) and the exclusive scan of the chunk totals per slot (O), so that
+//      C[x] = Q[x] + O[chunk of x] (chunk 0: Q[x]);
 //   3. each shot s of slot b takes the smallest x with C[b][x] > u[b][s] * C[b][last] for a
-//      caller-supplied uniform number u in [0, 1) (binary search);
+//      caller-supplied uniform number u in [0, 1): a binary search over the chunk boundaries,
+//      then one inside the chunk;
 //   4. measure! keeps the amplitudes whose locs read the outcome and divides them by
 //      sqrt(P[b][x_b]); the others become 0.
 #include <algorithm>
@@ -73,23 +75,32 @@ __global__ __launch_bounds__(kMThreads) void k_sum_chunks(const double* __restri
     out[r] = s;
 }
 
-// Inclusive scan of one chunk of kChunk values of slot b (rows of length len) from p to q (which
-// may be p); chunk totals to tot[b * nchunks + chunk]. Thread i scans its 8 values, the 256 thread sums are
-// scanned in LDS (Hillis-Steele, fixed order), then each thread adds its prefix.
+// Inclusive scan of one chunk of kChunk values of slot b (rows of length len) from p to q
+// (which may be p); chunk totals to tot[b * nchunks + chunk]. The chunk goes through LDS so that
+// global loads and stores run along contiguous addresses (element e = threadIdx.x + 256 i);
+// thread i then scans the 8 consecutive values 8i..8i+7 (one padding slot per 32 values keeps
+// those reads on distinct banks), the 256 thread sums are scanned in LDS (Hillis-Steele, fixed
+// order), and each thread adds its prefix.
 __global__ __launch_bounds__(kMThreads) void k_scan_chunks(const double* p, double* q, uint64_t len, int nchunks,
                                                            double* __restrict__ tot)
 {
+    __shared__ double vals[kChunk + kChunk / 32];
     __shared__ double sh[2][kMThreads];
     const int b = blockIdx.y;
     const uint64_t base = (uint64_t)b * len + (uint64_t)blockIdx.x * kChunk;
     const uint64_t lim = len - (uint64_t)blockIdx.x * kChunk;
+    auto slot = [](int e) { return e + (e >> 5); };
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int e = threadIdx.x + kMThreads * i;
+        vals[slot(e)] = (uint64_t)e < lim ? p[base + e] : 0.0;
+    }
+    __syncthreads();
     double v[8];
     double run = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const uint64_t o = (uint64_t)threadIdx.x * 8 + j;
-        v[j] = o < lim ? p[base + o] : 0.0;
-        run += v[j];
+        run += vals[slot(threadIdx.x * 8 + j)];
         v[j] = run;
     }
     int cur = 0;
@@ -103,16 +114,22 @@ __global__ __launch_bounds__(kMThreads) void k_scan_chunks(const double* p, doub
     }
     const double prefix = threadIdx.x > 0 ? sh[cur][threadIdx.x - 1] : 0.0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const uint64_t o = (uint64_t)threadIdx.x * 8 + j;
-        if (o < lim) q[base + o] = v[j] + prefix;
+    for (int j = 0; j < 8; ++j) vals[slot(threadIdx.x * 8 + j)] = v[j] + prefix;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int e = threadIdx.x + kMThreads * i;
+        if ((uint64_t)e < lim) q[base + e] = vals[slot(e)];
     }
     if (threadIdx.x == kMThreads - 1) tot[(uint64_t)b * nchunks + blockIdx.x] = sh[cur][kMThreads - 1];
 }
 
 // Exclusive scan of the chunk totals of slot b = blockIdx.x: thread i scans a contiguous
-// segment, the segment totals are scanned in LDS, then each thread writes its exclusive prefixes.
-__global__ __launch_bounds__(kMThreads) void k_scan_totals(double* __restrict__ tot, int nchunks)
+// segment, the segment totals are scanned in LDS, then each thread writes its exclusive prefixes
+// O[c]; then the last cumulative sum of every chunk, Q[last of c] + O[c], to tot[B * nchunks +
+// b * nchunks + c] (the table the sampling searches first).
+__global__ __launch_bounds__(kMThreads) void k_scan_totals(double* __restrict__ tot, int nchunks,
+                                                           const double* __restrict__ q, uint64_t len)
 {
     __shared__ double sh[2][kMThreads];
     double* t = tot + (uint64_t)blockIdx.x * nchunks;
@@ -135,35 +152,83 @@ __global__ __launch_bounds__(kMThreads) void k_scan_totals(double* __restrict__ 
         t[c] = pre;
         pre += v;
     }
+    __syncthreads();
+    double* last = tot + (uint64_t)gridDim.x * nchunks + (uint64_t)blockIdx.x * nchunks;
+    const double* Q = q + (uint64_t)blockIdx.x * len;
+    for (int c = threadIdx.x; c < nchunks; c += kMThreads) {
+        const uint64_t e = (uint64_t)c * kChunk + kChunk - 1;
+        const double v = Q[e < len ? e : len - 1];
+        last[c] = c > 0 ? v + t[c] : v;
+    }
 }
 
-__global__ __launch_bounds__(kMThreads) void k_add_offsets(double* __restrict__ p, uint64_t len, int nchunks,
-                                                           const double* __restrict__ off)
-{
-    const int b = blockIdx.y;
-    const uint64_t o = (uint64_t)blockIdx.x * kMThreads + threadIdx.x;
-    if (o >= len) return;
-    const uint64_t c = o / kChunk;
-    if (c == 0) return;
-    p[(uint64_t)b * len + o] += off[(uint64_t)b * nchunks + c];
-}
-
-// Shot s of slot b: smallest x with C[b][x] > u * C[b][last].
-__global__ __launch_bounds__(kMThreads) void k_sample(const double* __restrict__ cdf, uint64_t len, int B, int nshots,
+// Shots s of slot b: smallest x with C[b][x] > u * C[b][last], C[x] = Q[x] + O[x / kChunk]
+// (chunk 0: Q[x]). First the chunk: the smallest c whose last entry C exceeds the target; then
+// the entry inside it. Each thread takes kShots shots of one slot whose searches run level by
+// level together, so their loads are in flight at once.
+constexpr int kShots = 2;
+__global__ __launch_bounds__(kMThreads) void k_sample(const double* __restrict__ q, const double* __restrict__ off,
+                                                      uint64_t len, int nchunks, int B, int nshots,
                                                       const double* __restrict__ u, uint64_t* __restrict__ out)
 {
+    const int per = (nshots + kShots - 1) / kShots;
     const uint64_t t = (uint64_t)blockIdx.x * kMThreads + threadIdx.x;
-    if (t >= (uint64_t)B * nshots) return;
-    const uint64_t b = t / nshots;
-    const double* c = cdf + b * len;
-    const double target = u[t] * c[len - 1];
-    uint64_t lo = 0, hi = len - 1;
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (c[mid] > target) hi = mid;
-        else lo = mid + 1;
+    if (t >= (uint64_t)B * per) return;
+    const uint64_t b = t / per;
+    const int s0 = (int)(t - b * per) * kShots;
+    const double* Q = q + b * len;
+    const double* O = off + b * (uint64_t)nchunks;
+    const int lastc = nchunks - 1;
+    const double total = Q[len - 1] + (lastc > 0 ? O[lastc] : 0.0);
+    double target[kShots];
+    int clo[kShots], chi[kShots];
+#pragma unroll
+    for (int i = 0; i < kShots; ++i) {
+        const int s = s0 + i < nshots ? s0 + i : nshots - 1;
+        target[i] = u[b * nshots + s] * total;
+        clo[i] = 0;
+        chi[i] = lastc;
     }
-    out[t] = lo;
+    // Chunk: smallest c in [0, lastc] whose last entry exceeds the target (c = lastc when none).
+    const double* Last = off + ((uint64_t)B + b) * (uint64_t)nchunks;
+    auto chunk_last = [&](int c) { return Last[c]; };
+    for (int step = 0; step < 32; ++step) {
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < kShots; ++i)
+            if (clo[i] < chi[i]) {
+                any = true;
+                const int mid = (clo[i] + chi[i]) >> 1;
+                if (chunk_last(mid) > target[i]) chi[i] = mid;
+                else clo[i] = mid + 1;
+            }
+        if (!any) break;
+    }
+    uint64_t lo[kShots], hi[kShots];
+    double o[kShots];
+#pragma unroll
+    for (int i = 0; i < kShots; ++i) {
+        lo[i] = (uint64_t)clo[i] * kChunk;
+        const uint64_t end = lo[i] + kChunk;
+        hi[i] = (end < len ? end : len) - 1;
+        o[i] = clo[i] > 0 ? O[clo[i]] : 0.0;
+    }
+    for (int step = 0; step < 32; ++step) {
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < kShots; ++i)
+            if (lo[i] < hi[i]) {
+                any = true;
+                const uint64_t mid = (lo[i] + hi[i]) >> 1;
+                const double c = clo[i] > 0 ? Q[mid] + o[i] : Q[mid];
+                if (c > target[i]) hi[i] = mid;
+                else lo[i] = mid + 1;
+            }
+        if (!any) break;
+    }
+#pragma unroll
+    for (int i = 0; i < kShots; ++i)
+        if (s0 + i < nshots) out[b * nshots + s0 + i] = lo[i];
 }
 
 // Per slot: the index bits the outcome fixes (deposit of x_b on locs) and 1/sqrt(P[b][x_b]).
@@ -276,26 +341,27 @@ int launch_cdf(const double* p, double* q, int k, int B, double* tot)
     k_scan_chunks<<<dim3(nchunks, B), kMThreads, 0, stream()>>>(p, q, len, nchunks, tot);
     YAO_HIP(hipGetLastError());
     if (nchunks > 1) {
-        k_scan_totals<<<B, kMThreads, 0, stream()>>>(tot, nchunks);
-        k_add_offsets<<<dim3((unsigned)((len + kMThreads - 1) / kMThreads), B), kMThreads, 0, stream()>>>(q, len, nchunks,
-                                                                                                          tot);
+        k_scan_totals<<<B, kMThreads, 0, stream()>>>(tot, nchunks, q, len);
         YAO_HIP(hipGetLastError());
     }
-    prof_end(pi, 8.0 * B * (double)len * (nchunks > 1 ? 4.0 : 2.0), (double)B * len * (nchunks > 1 ? 2.0 : 1.0));
+    prof_end(pi, 8.0 * B * (double)len * 2.0, (double)B * len);
     return 0;
 }
 
 size_t cdf_tot_doubles(int k, int B)
 {
-    return (size_t)B * (((uint64_t(1) << k) + kChunk - 1) / kChunk);
+    return 2 * (size_t)B * (((uint64_t(1) << k) + kChunk - 1) / kChunk);
 }
 
-int launch_sample(const double* cdf, int k, int B, int nshots, const double* u, uint64_t* out)
+int launch_sample(const double* cdf, const double* tot, int k, int B, int nshots, const double* u, uint64_t* out)
 {
     const uint64_t total = (uint64_t)B * nshots;
+    const uint64_t len = uint64_t(1) << k;
+    const int nchunks = (int)((len + kChunk - 1) / kChunk);
+    const uint64_t threads = (uint64_t)B * ((nshots + kShots - 1) / kShots);
     const int pi = prof_begin(YAO_KF_MEASURE);
-    k_sample<<<(unsigned)((total + kMThreads - 1) / kMThreads), kMThreads, 0, stream()>>>(cdf, uint64_t(1) << k, B,
-                                                                                          nshots, u, out);
+    k_sample<<<(unsigned)((threads + kMThreads - 1) / kMThreads), kMThreads, 0, stream()>>>(cdf, tot, len, nchunks, B,
+                                                                                            nshots, u, out);
     prof_end(pi, 16.0 * total + 8.0 * k * total, 0.0);
     YAO_HIP(hipGetLastError());
     return 0;

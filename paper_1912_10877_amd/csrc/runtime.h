@@ -191,13 +191,14 @@ int shift_grad(const yao_state* st, const yao_circuit* c, const double* params, 
 int time_evolve(yao_state* s, yao_pauli_sum* h, double t, double tol, int krylov_dim, int* nsteps);
 
 // Measurement (kernels_measure.hip). prob: B * 2^k doubles [b][x]; launch_cdf scans p into q
-// (tot: cdf_tot_doubles(k, B)); launch_sample draws nshots outcomes per slot from u (device,
-// [B][nshots]); launch_collapse projects s onto the outcomes x (device, [B]) and writes dep, scale
+// per chunk of 2048 outcomes and writes the chunks' exclusive offsets to tot
+// (cdf_tot_doubles(k, B)); launch_sample draws nshots outcomes per slot from u (device,
+// [B][nshots]) with q and tot as launch_cdf left them; launch_collapse projects s onto the outcomes x (device, [B]) and writes dep, scale
 // and prob (device, B each). locs_dev: the k locs in device memory.
 int launch_outcome_probs(const yao_state* s, const int* locs, int k, double* prob);
 int launch_cdf(const double* p, double* q, int k, int B, double* tot);
 size_t cdf_tot_doubles(int k, int B);
-int launch_sample(const double* cdf, int k, int B, int nshots, const double* u, uint64_t* out);
+int launch_sample(const double* cdf, const double* tot, int k, int B, int nshots, const double* u, uint64_t* out);
 int launch_collapse(yao_state* s, const double* probs, const int* locs_dev, const int* locs, int k, const uint64_t* x,
                     uint64_t* dep, double* scale, double* prob);
 
