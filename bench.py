@@ -375,9 +375,10 @@ CASES = ("step20", "step20_b64", "rx25_c128", "rx25_c64", "fwd25_c128", "fwd25_c
          "qft25_c128", "qft25_c64", "perm25_c128", "measure24_c128", "copy1g", "c4batch")
 
 
-def run_case(name, reps):
+def run_case(name, reps, jit=-1):
     """One workload, repeated, for profiling runs (rocprofv3 kernel traces and counters): each
-    case launches only what it names, after one untimed run, and prints its wall time per rep."""
+    case launches only what it names, after one untimed run, and prints its wall time per rep.
+    jit >= 0 overrides the case's compiled-pass setting (0: the generic pass kernels only)."""
     import numpy as np
     import torch
 
@@ -461,6 +462,8 @@ def run_case(name, reps):
         f = lambda: yb.batch_run(states, circs, params, hams)
     else:
         raise SystemExit(f"unknown case {name}; cases: {', '.join(CASES)}")
+    if jit >= 0:
+        yb.set_options(jit=jit)
     f()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -473,7 +476,7 @@ def run_case(name, reps):
 def main():
     args = parse()
     if args.case:
-        run_case(args.case, args.steps)
+        run_case(args.case, args.steps, args.jit)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
