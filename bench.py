@@ -480,7 +480,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU sharding of the state is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding the state over GPUs is designed but not built)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
