@@ -479,7 +479,7 @@ def main():
         run_case(args.case, args.steps, args.jit)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(sharding the state over GPUs is designed but not built)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
