@@ -51,6 +51,8 @@ def check_samples(got, psi, n, locs, u, dtype):
 @pytest.mark.parametrize("n,B,locs", [
     (1, 1, [0]), (6, 3, [0, 1, 2, 3, 4, 5]), (10, 1, [3, 7]), (12, 5, [11, 0, 6]),
     (14, 2, list(range(14))), (13, 1, [2, 9, 4, 12, 0, 7, 1]), (9, 64, [0, 1, 2]), (16, 1, [15]),
+    # 2^16 outcomes in 32 scanned chunks per slot, three slots, locs scattered (permuted first)
+    (17, 3, [16, 0, 5, 9, 2, 13, 7, 11, 1, 15, 4, 8, 12, 3, 14, 6]),
 ])
 def test_probs_and_samples_match_oracle(dtype, n, B, locs):
     psi = w.random_state(n, B, 100 + n)

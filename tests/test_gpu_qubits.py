@@ -123,6 +123,25 @@ def test_qft_full_size_sampled(dtype):
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
+def test_qft_scattered_qubits_full_size_sampled(dtype):
+    """QFT on 14 scattered qubits of a 24-qubit state (single slot: register-radix passes whose
+    tiles take code rows and filler rows): sampled outputs against the oracle computed one by
+    one, and the inverse restoring the input."""
+    n = 24
+    locs = [23, 2, 17, 9, 0, 12, 5, 20, 14, 7, 1, 19, 11, 4]
+    psi = w.random_state(n, 1, 31)
+    s = yb.State(n, 1, dtype)
+    s.upload(psi)
+    yb.qft(s, locs)
+    got = s.download()
+    idx = np.random.default_rng(7).choice(1 << n, 24, replace=False)
+    want = oracle.qft(psi, n, locs, idx=idx)
+    assert np.abs(got[idx] - want).max() <= (1e-12 if dtype == 1 else 1e-5)
+    yb.qft(s, locs, inverse=True)
+    assert np.abs(s.download() - psi).max() <= (1e-12 if dtype == 1 else 2e-5)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
 def test_permute_full_size(dtype):
     """A 24-qubit permutation reversing the qubit order (every bit moves), against the oracle
     on sampled indices and exactly inverted by the inverse permutation."""
