@@ -1340,8 +1340,8 @@ size_t small_circuit_lds_bytes(int n)
 // and adds, for every element j of the tile and group g, c_t i^{ny} (-1)^{|(j ^ x) & z|}
 // psi[j ^ x] over the group's terms (eq. expectation). Partners stay inside the tile, so the
 // state is read once per pass instead of once per group.
-constexpr int kObsRegBits = 4;  // elements per thread: 16
-constexpr int kObsMaxTile = 13;
+constexpr int kObsRegBits = 3;  // elements per thread: 8
+constexpr int kObsMaxTile = 12;
 struct ObsGroupT {
     uint32_t x;  // X mask in tile-bit coordinates
     int t0, t1;  // terms
