@@ -894,12 +894,11 @@ __global__ __launch_bounds__(512, sizeof(RP) == 4 ? 3 : 1) void k_pass_fwd(PassA
     {
         uint4 w[kDmRegs];
         dm_load(a, th, nthr, w);
-        VP v[N];
+        // The tile goes straight to LDS before the matrices' remaining words: a register copy
+        // of it held across that loop stayed in scratch memory.
 #pragma unroll
-        for (int r = 0; r < N; ++r) v[r] = gp[tile_off<RB>(a, tc, r)];
+        for (int r = 0; r < N; ++r) lp[swz((uint32_t)th + (uint32_t)r * nthr)] = gp[tile_off<RB>(a, tc, r)];
         if (a.ndm) dm_store(a, ldm, th, nthr, w);
-#pragma unroll
-        for (int r = 0; r < N; ++r) lp[swz((uint32_t)th + (uint32_t)r * nthr)] = v[r];
     }
     __syncthreads();
 
@@ -1161,21 +1160,14 @@ __global__ __launch_bounds__(512, 3) void k_pass_bwd(PassArgs a)
     const TileCtx tc = tile_ctx<RB>(a, th);
     double2* gp = (double2*)z_psi(a);
     VL* gl = (VL*)z_lam(a);
-    {
-        double2 v[N];
-        VL w[N];
+    // Straight from global memory to LDS: a staging array here stayed in scratch memory
+    // (a store and a reload per element through the cache hierarchy).
 #pragma unroll
-        for (int r = 0; r < N; ++r) {
-            const uint64_t off = tile_off<RB>(a, tc, r);
-            v[r] = gp[off];
-            w[r] = gl[off];
-        }
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            const uint32_t e = swz((uint32_t)th + (uint32_t)r * nthr);
-            lp[e] = v[r];
-            ll[e] = w[r];
-        }
+    for (int r = 0; r < N; ++r) {
+        const uint64_t off = tile_off<RB>(a, tc, r);
+        const uint32_t e = swz((uint32_t)th + (uint32_t)r * nthr);
+        lp[e] = gp[off];
+        ll[e] = gl[off];
     }
     __syncthreads();
 
@@ -1373,13 +1365,9 @@ __global__ __launch_bounds__(512) void k_obs_pass(PassArgs a, const ObsGroupT* _
     double* red = (double*)(smem + (sizeof(VP) << t));
     const TileCtx tc = tile_ctx<RB>(a, th);
     const VP* gp = (const VP*)z_psi(a);
-    {
-        VP v[N];
+    // Straight from global memory to LDS (a staging array stayed in scratch memory).
 #pragma unroll
-        for (int r = 0; r < N; ++r) v[r] = gp[tile_off<RB>(a, tc, r)];
-#pragma unroll
-        for (int r = 0; r < N; ++r) lp[swz((uint32_t)th + (uint32_t)r * nthr)] = v[r];
-    }
+    for (int r = 0; r < N; ++r) lp[swz((uint32_t)th + (uint32_t)r * nthr)] = gp[tile_off<RB>(a, tc, r)];
     __syncthreads();
     const YAO_CONST ObsGroupT* gq = cptr(groups);
     const YAO_CONST ObsTermT* tq = cptr(terms);
