@@ -229,6 +229,19 @@ def bench_configs(yb, w, torch):
         log("config c5 (30 qubits) autotuned complex64 done")
         yb.set_options(autotune=0, fuse_width=5, mfma=1)
         ms64 = timed(f64, 2)
+        # One more forward with a pair of HIP events around every launch: the matrix-core blocks'
+        # share of the HBM and FP32 matrix-core peaks, and the time of the passes between them.
+        yb.lib().yao_profile_enable(1)
+        f64()
+        torch.cuda.synchronize()
+        yb.lib().yao_profile_enable(0)
+        mfma_prof = profile_family(yb, 6, with_flops=True)
+        if mfma_prof:
+            mfma_prof["mfma_frac"] = round(mfma_prof["achieved_tflops"] / FP32_PEAK_TFLOPS, 3)
+        pass_prof = profile_family(yb, 2)
+        w5_split = {"mfma_blocks": mfma_prof,
+                    "pass_fwd_ms": round(pass_prof.get("launches", 0) * pass_prof.get("avg_launch_us", 0.0) / 1e3, 1),
+                    "pass_fwd_launches": pass_prof.get("launches", 0)}
         log("config c5 (30 qubits) 5-qubit blocks done")
         yb.set_options(autotune=0, fuse_width=1)
 
@@ -240,7 +253,8 @@ def bench_configs(yb, w, torch):
         fid = float(abs(torch.vdot(t128, t64.to(torch.complex128)).item()) ** 2)
         e64, e128 = float(yb.expect(s64, zz)[0]), float(yb.expect(s128, zz)[0])
         out["c5_30q"] = {"gates": len(c.gates), "c64_mfma_w5_ms": round(ms64, 1),
-                         "c64_autotuned_ms": round(ms64_tuned, 1), "c128_w1_ms": round(ms128, 1),
+                         "c64_autotuned_ms": round(ms64_tuned, 1), "c64_mfma_w5_split": w5_split,
+                         "c128_w1_ms": round(ms128, 1),
                          "fidelity_c64_vs_c128": fid, "z0z1_c64": e64, "z0z1_c128": e128,
                          "z0z1_abs_err": abs(e64 - e128)}
         del s64, s128, t64, t128
@@ -356,9 +370,9 @@ def bench_next_rows(yb, w, torch):
     return out
 
 
-def profile_family(yb, fam):
-    """Launches, mean duration and algorithmic GB/s of one kernel family since profiling was
-    last enabled (HIP events on the library's stream)."""
+def profile_family(yb, fam, with_flops=False):
+    """Launches, mean duration and algorithmic GB/s (and TFLOP/s) of one kernel family since
+    profiling was last enabled (HIP events on the library's stream)."""
     import ctypes
     yb.lib().yao_profile_read.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     nl, ms, by, fl = ctypes.c_int(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
@@ -366,9 +380,13 @@ def profile_family(yb, fam):
     if not nl.value:
         return {}
     gbs = by.value / (ms.value / 1e3) / 1e9
-    return {"launches": nl.value, "avg_launch_us": round(ms.value * 1e3 / nl.value, 2),
-            "algo_bytes_per_launch": by.value / nl.value, "achieved_gbs": round(gbs, 1),
-            "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}
+    r = {"launches": nl.value, "avg_launch_us": round(ms.value * 1e3 / nl.value, 2),
+         "algo_bytes_per_launch": by.value / nl.value, "achieved_gbs": round(gbs, 1),
+         "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}
+    if with_flops:
+        r["algo_flops_per_launch"] = fl.value / nl.value
+        r["achieved_tflops"] = round(fl.value / (ms.value / 1e3) / 1e12, 2)
+    return r
 
 
 CASES = ("step20", "step20_b64", "rx25_c128", "rx25_c64", "fwd25_c128", "fwd25_c64", "w5mfma30_c64",
