@@ -118,6 +118,23 @@ def bench_uneven_batch(yb, w, torch, ncirc, steps):
         e, g = yb.batch_run(states, circs, params, hams)
     torch.cuda.synchronize()
     batch_ms = (time.perf_counter() - t0) * 1e3 / steps
+    # A second list (every other circuit) called in turn with the first: each list replays its
+    # own recorded graph, so a pair costs about one replay of each.
+    half = slice(1, None, 2)
+    lists = [(states, circs, params, hams), (states[half], circs[half], params[half], hams[half])]
+    yb.batch_run(*lists[1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        yb.batch_run(*lists[1])
+    torch.cuda.synchronize()
+    half_ms = (time.perf_counter() - t0) * 1e3 / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for lst in lists:
+            yb.batch_run(*lst)
+    torch.cuda.synchronize()
+    pair_ms = (time.perf_counter() - t0) * 1e3 / steps
 
     def loop():
         for i in range(ncirc):
@@ -139,6 +156,7 @@ def bench_uneven_batch(yb, w, torch, ncirc, steps):
                         "ansatz, periodic Heisenberg energy + all gradients per circuit, complex64",
             "circuits": ncirc, "gates": gates, "ms_per_batch": batch_ms,
             "amplitude_updates_per_s": au / (batch_ms / 1e3), "record_s": t_record,
+            "half_list_ms": half_ms, "alternating_pair_ms": pair_ms,
             "fused_loop_ms": fused_loop_ms, "plain_loop_ms": plain_ms,
             "speedup_vs_plain": plain_ms / batch_ms, "speedup_vs_fused_loop": fused_loop_ms / batch_ms,
             "energy_sum": float(np.sum(e))}

@@ -402,7 +402,8 @@ def auto_fallbacks() -> int:
 
 def batch_run(states: Sequence[State], circs: Sequence[Circuit], params: Sequence[np.ndarray],
               hams: Sequence[PauliSum]):
-    """Energy and gradient of independent circuits in one persistent launch."""
+    """Energy and gradient of independent circuits in one replay of the graph recorded for this
+    list (recorded on its first call)."""
     m = len(states)
     ps = [_params(p) for p in params]
     grads = [np.zeros(max(1, c.nparams)) for c in circs]

@@ -119,7 +119,11 @@ struct Cache {
     void** d_ptrs = nullptr;
 };
 
-Cache* g_cache = nullptr;
+// Recorded batches, most recently used first: a caller that alternates between a few batch
+// lists replays each one's graph instead of recording it again. Each entry owns its scratch
+// buffers, so the least recently used one is freed past kMaxCaches.
+constexpr size_t kMaxCaches = 4;
+std::vector<Cache*> g_caches;
 hipStream_t g_capture = nullptr;
 hipStream_t g_bank[kBanks] = {};
 hipEvent_t g_fork = nullptr, g_join[kBanks] = {};
@@ -828,6 +832,17 @@ int record(Cache& C)
     return 0;
 }
 
+// Same circuits, states, observables and types in the same order (circuit versions aside).
+bool same_objects(const Key& a, const Key& b)
+{
+    if (a.size() != b.size()) return false;
+    for (size_t i = 0; i < a.size(); ++i)
+        if (std::get<0>(a[i]) != std::get<0>(b[i]) || std::get<2>(a[i]) != std::get<2>(b[i]) ||
+            std::get<3>(a[i]) != std::get<3>(b[i]) || std::get<4>(a[i]) != std::get<4>(b[i]))
+            return false;
+    return true;
+}
+
 bool same_options(const yao_options& a, const yao_options& b)
 {
     return a.tile_qubits == b.tile_qubits && a.fuse_width == b.fuse_width && a.mfma == b.mfma &&
@@ -843,31 +858,50 @@ int batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* cir
     const hipStream_t origin = stream();
     Key key;
     for (int i = 0; i < ncirc; ++i) key.emplace_back(circs[i], circs[i]->version, states[i], h[i], states[i]->dtype);
-    bool fresh = !g_cache || g_cache->key != key || !same_options(g_cache->opt, options());
-    if (!fresh) {
-        const int r = build_programs(*g_cache, params, false);
+    Cache* hit = nullptr;
+    for (size_t i = 0; i < g_caches.size(); ++i)
+        if (g_caches[i]->key == key && same_options(g_caches[i]->opt, options())) {
+            hit = g_caches[i];
+            g_caches.erase(g_caches.begin() + (long)i);
+            g_caches.insert(g_caches.begin(), hit);
+            break;
+        }
+    bool fresh = !hit;
+    if (hit) {
+        const int r = build_programs(*hit, params, false);
         if (r < 0) return r;
         if (r == 1) fresh = true;
         else {
-            pack_all(*g_cache);
-            pack_params(*g_cache, params);
+            pack_all(*hit);
+            pack_params(*hit, params);
         }
     }
     if (fresh) {
         YAO_HIP(hipStreamSynchronize(origin));
-        free_cache(g_cache);
-        g_cache = new Cache;
-        g_cache->key = key;
-        int rc = build_cache(*g_cache, ncirc, states, circs, params, h);
-        if (!rc) rc = record(*g_cache);
+        // Drop the entry being replaced, entries for the same objects at older circuit versions
+        // (they can never match again), and the least recently used one past the limit.
+        for (size_t i = 0; i < g_caches.size();) {
+            if (g_caches[i] == hit || same_objects(g_caches[i]->key, key)) {
+                free_cache(g_caches[i]);
+                g_caches.erase(g_caches.begin() + (long)i);
+            } else ++i;
+        }
+        while (g_caches.size() >= kMaxCaches) {
+            free_cache(g_caches.back());
+            g_caches.pop_back();
+        }
+        Cache* c = new Cache;
+        c->key = key;
+        int rc = build_cache(*c, ncirc, states, circs, params, h);
+        if (!rc) rc = record(*c);
         set_stream(origin);
         if (rc) {
-            free_cache(g_cache);
-            g_cache = nullptr;
+            free_cache(c);
             return rc;
         }
+        g_caches.insert(g_caches.begin(), c);
     }
-    Cache& C = *g_cache;
+    Cache& C = *g_caches.front();
     const int pi = prof_begin(YAO_KF_BATCH);
     if (C.prog_bytes) YAO_HIP(hipMemcpyAsync(C.d_prog, C.h_prog, C.prog_bytes, hipMemcpyHostToDevice, origin));
     if (C.nparams)
@@ -892,14 +926,16 @@ int batch_run(int ncirc, yao_state* const* states, const yao_circuit* const* cir
 
 void drop_batch(const void* obj)
 {
-    if (!g_cache) return;
-    for (const Item& it : g_cache->items)
-        if ((const void*)it.c == obj || (const void*)it.s == obj || (const void*)it.h == obj) {
+    for (size_t i = 0; i < g_caches.size();) {
+        bool uses = false;
+        for (const Item& it : g_caches[i]->items)
+            uses |= (const void*)it.c == obj || (const void*)it.s == obj || (const void*)it.h == obj;
+        if (uses) {
             (void)hipDeviceSynchronize();
-            free_cache(g_cache);
-            g_cache = nullptr;
-            return;
-        }
+            free_cache(g_caches[i]);
+            g_caches.erase(g_caches.begin() + (long)i);
+        } else ++i;
+    }
 }
 
 }  // namespace yao

@@ -1,7 +1,7 @@
 """GPU parity of the graph-recorded batch of uneven circuits (yao_batch_run) against the oracle:
 energies and every gradient per circuit, replays with new parameters, autotuned and forced
-fusion widths, re-recording after a circuit changes, and the full 1024-circuit workload against
-stored oracle values."""
+fusion widths, re-recording after a circuit changes, batch lists called in turn, and the full
+1024-circuit workload against stored oracle values."""
 import numpy as np
 import pytest
 
@@ -179,6 +179,27 @@ def test_changed_circuit_is_recorded_anew():
     refs[1] = (extra, H1)
     e, g = yb.batch_run(states, circs, params, hams)
     check(e, g, params, refs, 1)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_alternating_batch_lists_keep_their_graphs(dtype):
+    """Two batch lists called in turn (and a third list sharing states and circuits with the
+    first): each call replays the graph recorded for its own list, with new angles each time;
+    every energy and gradient is checked against the oracle."""
+    spec_a = [(7, 2, 41), (9, 3, 42), (13, 2, 43)]
+    spec_b = [(6, 1, 44), (10, 2, 45), (12, 3, 46), (8, 2, 47)]
+    sa, ca, ha, pa, ra = make_batch(spec_a, dtype)
+    sb, cb, hb, pb, rb = make_batch(spec_b, dtype)
+    for rep in range(3):
+        pa = [w.angles(100 + 10 * rep + i, r[0].nparams) for i, r in enumerate(ra)]
+        pb = [w.angles(200 + 10 * rep + i, r[0].nparams) for i, r in enumerate(rb)]
+        e, g = yb.batch_run(sa, ca, pa, ha)
+        check(e, g, pa, ra, dtype)
+        e, g = yb.batch_run(sb, cb, pb, hb)
+        check(e, g, pb, rb, dtype)
+        # The first list's circuits in another order on the same states.
+        e, g = yb.batch_run(sa[::-1], ca[::-1], pa[::-1], ha[::-1])
+        check(e, g, pa[::-1], ra[::-1], dtype)
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
