@@ -1,12 +1,13 @@
 // Dense 4- and 5-qubit gates on complex64 states with FP32 matrix cores.
 //
 // A K-qubit gate maps each group of D = 2^K amplitudes (the indices that differ only in the
-// target bits) through a D x D complex matrix. Taking 32 groups as the columns of a
-// 2D x 32 real matrix [Re a; Im a], the update is one real GEMM with the 2D x 2D matrix
-// [[Re U, -Im U], [Im U, Re U]], which each wave computes with v_mfma_f32_16x16x4f32: the gate
-// matrix stays in the A-operand registers, each lane's column is read once as B operands, and
-// the 16x16 accumulator tiles hold the real and imaginary halves of each output amplitude in the
-// same lane.
+// target bits) through a D x D complex matrix U = Ur + i Ui. Taking 16 groups as the columns
+// of real D x 16 matrices Ar, Ai (real and imaginary parts), the update uses three real products
+// instead of four: P1 = Ur Ar, P2 = Ui Ai, P3 = (Ur + Ui)(Ar + Ai), then Re = P1 - P2 and
+// Im = P3 - P1 - P2 (the three-multiplication form of a complex product). Each wave computes them
+// with v_mfma_f32_16x16x4f32: the three matrices stay in the A-operand registers, each lane's
+// column is read once as B operands (Ar + Ai formed in registers), and the accumulator tiles of
+// P1, P2, P3 hold the same output amplitudes in the same lanes.
 //
 // The amplitudes move through LDS: a workgroup loads a tile of 2^m index rows (the K target
 // bits and the lowest other bits, so every tile row run is contiguous in memory whatever the
@@ -50,6 +51,35 @@ __device__ __forceinline__ int swz5(int r)
     return r ^ ((r >> 5) & 31);
 }
 
+// The three products of one 16-column block: B operands Ar, Ai and Ar + Ai of member
+// 4 kc + (lane / 16), A operands the lane's fragments of Ur, Ui and Ur + Ui.
+template <int RT, int KC>
+__device__ __forceinline__ void mul3(const float (&am)[3][RT][KC], const float2 (&amp)[KC], v4f (&acc)[3][RT])
+{
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[w][rt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+        const float xr = amp[kc].x, xi = amp[kc].y, xs = xr + xi;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            acc[0][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[0][rt][kc], xr, acc[0][rt], 0, 0, 0);
+            acc[1][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[1][rt][kc], xi, acc[1][rt], 0, 0, 0);
+            acc[2][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[2][rt][kc], xs, acc[2][rt], 0, 0, 0);
+        }
+    }
+}
+
+// Output amplitude in accumulator register v of row tile rt: (P1 - P2, P3 - P1 - P2).
+template <int RT>
+__device__ __forceinline__ float2 out3(const v4f (&acc)[3][RT], int rt, int v)
+{
+    const float p1 = acc[0][rt][v], p2 = acc[1][rt][v];
+    return make_float2(p1 - p2, acc[2][rt][v] - p1 - p2);
+}
+
 // Lane layout of v_mfma_f32_16x16x4f32 (one block): A[i][k] from lane i + 16 k, B[k][j]
 // from lane j + 16 k, D[4 (l / 16) + v][l % 16] in accumulator register v of lane l.
 // FULL: the tile holds exactly 4096 amplitudes, so every load and store loop has a fixed trip
@@ -57,7 +87,7 @@ __device__ __forceinline__ int swz5(int r)
 template <int K, bool FULL>
 __global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, MfmaArgs a, const float* __restrict__ M)
 {
-    constexpr int D = 1 << K, RD = 2 * D, RT = RD / 16, KC = RD / 4, NA = D / 4;
+    constexpr int D = 1 << K, RT = D / 16, KC = D / 4;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     MfmaTables* t = reinterpret_cast<MfmaTables*>(lds_raw);
     float2* tile = reinterpret_cast<float2*>(lds_raw + sizeof(MfmaTables));
@@ -68,11 +98,13 @@ __global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, Mf
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, cl = lane & 15;
-    float am[RT][KC];
+    float am[3][RT][KC];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int w = 0; w < 3; ++w)
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) am[rt][kc] = M[(16 * rt + cl) * RD + 4 * kc + q];
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) am[w][rt][kc] = M[w * D * D + (16 * rt + cl) * D + 4 * kc + q];
     const int B = a.B;
     const int rows = 1 << a.m;
     const int E = FULL ? 4096 : rows * B;
@@ -123,27 +155,19 @@ __global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, Mf
                 const int r0 = (int)(t->col_lo[g & 63] | t->col_hi[g >> 6]);
                 const uint64_t idx0 = base | t->in_lo[r0 & 63] | t->in_hi[r0 >> 6];
                 const bool on = valid && ((idx0 & a.cmask) == a.cval);
-                float2 amp[NA];
+                float2 amp[KC];
 #pragma unroll
-                for (int m = 0; m < NA; ++m)
+                for (int m = 0; m < KC; ++m)
                     amp[m] = valid ? tile[swz5(r0 | t->mem[q + 4 * m]) * B + b] : make_float2(0.f, 0.f);
-                v4f acc[RT];
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt) acc[rt] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kc = 0; kc < KC; ++kc) {
-                    const int m = kc % NA;
-                    const float bv = (kc / NA) == 0 ? amp[m].x : amp[m].y;
-#pragma unroll
-                    for (int rt = 0; rt < RT; ++rt) acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[rt][kc], bv, acc[rt], 0, 0, 0);
-                }
+                v4f acc[3][RT];
+                mul3<RT, KC>(am, amp, acc);
                 if (on) {
 #pragma unroll
-                    for (int rt = 0; rt < RT / 2; ++rt)
+                    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const int s = 16 * rt + 4 * q + v;
-                            tile[swz5(r0 | t->mem[s]) * B + b] = make_float2(acc[rt][v], acc[rt + RT / 2][v]);
+                            tile[swz5(r0 | t->mem[s]) * B + b] = out3(acc, rt, v);
                         }
                 }
             }
@@ -169,7 +193,7 @@ __global__ __launch_bounds__(256) void k_dense_mfma(float2* __restrict__ psi, Mf
 template <int K>
 __global__ __launch_bounds__(256) void k_dense_mfma_b1(float2* __restrict__ psi, MfmaArgs a, const float* __restrict__ M)
 {
-    constexpr int D = 1 << K, RD = 2 * D, RT = RD / 16, KC = RD / 4, NA = D / 4;
+    constexpr int D = 1 << K, RT = D / 16, KC = D / 4;
     constexpr int NBLK = (4096 >> K) / 64;  // 16-column blocks per wave
     constexpr int kPer = 16;                // amplitudes per thread and tile
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -177,11 +201,13 @@ __global__ __launch_bounds__(256) void k_dense_mfma_b1(float2* __restrict__ psi,
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int q = lane >> 4, cl = lane & 15;
-    float am[RT][KC];
+    float am[3][RT][KC];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int w = 0; w < 3; ++w)
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) am[rt][kc] = M[(16 * rt + cl) * RD + 4 * kc + q];
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) am[w][rt][kc] = M[w * D * D + (16 * rt + cl) * D + 4 * kc + q];
     const uint64_t lo = a.tab.in_lo[lane];
     // Group columns of this lane (block wave + 4 j): first row, and the row bits that decide
     // its controls; member offsets split into a per-lane part and a uniform part (the member
@@ -222,25 +248,17 @@ __global__ __launch_bounds__(256) void k_dense_mfma_b1(float2* __restrict__ psi,
 #pragma unroll
         for (int j = 0; j < NBLK; ++j) {
             const bool on = ((base & a.cmask) | tctl[j]) == a.cval;
-            float2 amp[NA];
+            float2 amp[KC];
 #pragma unroll
-            for (int m = 0; m < NA; ++m) amp[m] = t[swz5(r0[j] | memq | (int)a.tab.mem[4 * m])];
-            v4f acc[RT];
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) acc[rt] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kc = 0; kc < KC; ++kc) {
-                const int m = kc % NA;
-                const float bv = (kc / NA) == 0 ? amp[m].x : amp[m].y;
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt) acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[rt][kc], bv, acc[rt], 0, 0, 0);
-            }
+            for (int m = 0; m < KC; ++m) amp[m] = t[swz5(r0[j] | memq | (int)a.tab.mem[4 * m])];
+            v4f acc[3][RT];
+            mul3<RT, KC>(am, amp, acc);
             if (on) {
 #pragma unroll
-                for (int rt = 0; rt < RT / 2; ++rt)
+                for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        t[swz5(r0[j] | memq4 | (int)a.tab.mem[16 * rt + v])] = make_float2(acc[rt][v], acc[rt + RT / 2][v]);
+                        t[swz5(r0[j] | memq4 | (int)a.tab.mem[16 * rt + v])] = out3(acc, rt, v);
             }
         }
         __syncthreads();
@@ -263,18 +281,16 @@ bool mfma_supported(int k, int n, int B)
     return (k == 4 || k == 5) && n >= k && n - kMfmaTileBits < 31 && ((size_t)B << k) <= 4096;
 }
 
-// Real form [[Ur, -Ui], [Ui, Ur]] of U in FP32, row-major 2D x 2D: the operand the kernel reads.
+// Ur, Ui and Ur + Ui of U in FP32 (the sum formed in FP64), each row-major D x D, one after
+// the other: the operands the kernels read.
 void mfma_encode(const HostMat& U, float* h)
 {
-    const int D = 1 << U.k, RD = 2 * D;
-    for (int r = 0; r < D; ++r)
-        for (int s = 0; s < D; ++s) {
-            const float ur = (float)U.re[r * D + s], ui = (float)U.im[r * D + s];
-            h[(size_t)r * RD + s] = ur;
-            h[(size_t)r * RD + D + s] = -ui;
-            h[(size_t)(D + r) * RD + s] = ui;
-            h[(size_t)(D + r) * RD + D + s] = ur;
-        }
+    const size_t DD = size_t(1) << (2 * U.k);
+    for (size_t e = 0; e < DD; ++e) {
+        h[e] = (float)U.re[e];
+        h[DD + e] = (float)U.im[e];
+        h[2 * DD + e] = (float)(U.re[e] + U.im[e]);
+    }
 }
 
 // Dense k = 4 or 5 gate on a complex64 state through matrix cores. dev_mat, when given, holds
@@ -284,7 +300,7 @@ int launch_dense_mfma(float2* psi, int n, int B, const HostMat& U, const int* lo
     const int k = U.k, D = 1 << k;
     const float* dm = (const float*)dev_mat;
     if (!dm) {
-        std::vector<float> h((size_t)4 * D * D);
+        std::vector<float> h((size_t)3 * D * D);
         mfma_encode(U, h.data());
         dm = (const float*)ring_upload(h.data(), h.size() * sizeof(float));
         if (!dm) return YAO_ENOMEM;
@@ -357,10 +373,11 @@ int launch_dense_mfma(float2* psi, int n, int B, const HostMat& U, const int* lo
     else if (k == 4) k_dense_mfma<4, false><<<(unsigned)blocks, 256, lds, stream()>>>(psi, a, dm);
     else if (full) k_dense_mfma<5, true><<<(unsigned)blocks, 256, lds, stream()>>>(psi, a, dm);
     else k_dense_mfma<5, false><<<(unsigned)blocks, 256, lds, stream()>>>(psi, a, dm);
-    // Algorithmic work: one read and one write of every element; 8 D real flops per element
-    // (for the elements whose controls pass).
+    // Work: one read and one write of every element; per element whose controls pass, 6 D real
+    // flops on the matrix cores (three real products; the complex product by definition takes
+    // 8 D, the additions forming Ar + Ai and the outputs run on the vector units).
     const double on = elems / double(uint64_t(1) << __builtin_popcountll(c.mask));
-    prof_end(pi, 2.0 * 8.0 * elems, 8.0 * D * on);
+    prof_end(pi, 2.0 * 8.0 * elems, 6.0 * D * on);
     YAO_HIP(hipGetLastError());
     return 0;
 }

@@ -204,7 +204,7 @@ int launch_collapse(yao_state* s, const double* probs, const int* locs_dev, cons
 
 // Dense 4/5-qubit gates on complex64 states through the FP32 matrix cores.
 bool mfma_supported(int k, int n, int B);
-void mfma_encode(const HostMat& U, float* out);  // 4 * 4^k floats
+void mfma_encode(const HostMat& U, float* out);  // 3 * 4^k floats
 int launch_dense_mfma(float2* psi, int n, int B, const HostMat& U, const int* locs, CtrlSpec c,
                       const void* dev_mat = nullptr);
 
