@@ -538,7 +538,7 @@ size_t encode_gate_matrix(int dtype, int n, int B, const HostMat& U, std::vector
     const size_t off = pool.size();
     const size_t dd = size_t(1) << (2 * U.k);
     if (dtype == YAO_C64 && options().mfma && mfma_supported(U.k, n, B)) {
-        pool.resize(off + (3 * dd + 1) / 2);  // 3 dd floats
+        pool.resize(off + 2 * dd);  // 4 dd floats
         mfma_encode(U, (float*)(pool.data() + off));
     } else if (dtype == YAO_C64) {
         pool.resize(off + dd);  // 2 dd floats
